@@ -1,0 +1,188 @@
+"""FP64 CPU oracle: Algorithm 2 (LADMM) of the paper, step by step.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring). Everything here is
+float64 NumPy; library primitives (SVD, matrix products, eigvalsh) serve as
+single steps, with no blocking, fusion or reordering beyond what the paper's
+definitions state.
+
+Array conventions: a spectroscopic image f (and z, d, g, c) is stored
+voxel-major as an (N, Q) array whose row n is f_n; data m is (N, P); the box
+grid is (nx, ny, nz) with voxel n = x + nx*(y + ny*z).
+
+Readings of points the paper leaves open (each is also listed in the design
+notes of the repository):
+  * Regulariser (Eq. l2, Sec. II-C): R(f) sums 1/2 ||f_n - f_m||^2 over every
+    voxel n and every face neighbour m of n, so each adjacent pair appears
+    twice and D has one row per ordered pair. Hence D^T D = 2 L with L the
+    graph Laplacian of the grid, and (D^T D z)_n = 2 sum_m (z_n - z_m).
+  * Neighbourhood: face neighbours (4 in 2-D, 6 in 3-D), unit weight per axis,
+    free (Neumann) boundary: edge voxels simply have fewer neighbours.
+  * The map returned after a fixed number of iterations is z^K (the feasible
+    iterate); f^K and d^K are returned too.
+  * g uses the rank-r factors as Algorithm 2 does, so the iteration minimises
+    the problem with K replaced by K_r; the objective here takes K_r likewise.
+  * Rank rule (Sec. III-F): smallest r whose relative Frobenius error
+    ||K - K_r||_F / ||K||_F is strictly below 0.005 % (5e-5).
+  * xi_p (Eq. sigma_cond): 0.75 * lambda * ||D^T D||_2 + 1e-10, spectral norm.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS_XI = 1e-10          # epsilon of Eq. (sigma_cond)
+XI_FACTOR = 0.75        # 0.75 factor of the convergence condition (Sec. III-F)
+RANK_TOL = 5e-5         # 0.005 % Frobenius approximation error (Sec. III-F)
+
+
+# --------------------------------------------------------------- dictionary
+def thin_svd(K: np.ndarray):
+    """Thin SVD K = U diag(s) V^T via LAPACK (Algorithm 2, SVD step).
+
+    Returns U (P, k), s (k,), V (Q, k) with k = min(P, Q), s descending."""
+    U, s, Vt = np.linalg.svd(np.asarray(K, dtype=np.float64), full_matrices=False)
+    return U, s, Vt.T
+
+
+def rank_rule(s: np.ndarray, rank: int = 0) -> int:
+    """Rank r (Sec. III-F, rank parameter).
+
+    rank > 0: that rank; rank == -1: min(P, Q) (the unapproximated K);
+    rank == 0: smallest r with ||K - K_r||_F < 5e-5 ||K||_F."""
+    k = len(s)
+    if rank == -1:
+        return k
+    if rank > 0:
+        if rank > k:
+            raise ValueError("rank exceeds min(P, Q)")
+        return rank
+    total = float(np.sum(s * s))
+    for r in range(1, k + 1):
+        tail = float(np.sum(s[r:] * s[r:]))
+        if np.sqrt(tail) < RANK_TOL * np.sqrt(total):
+            return r
+    return k
+
+
+# --------------------------------------------------------------- regulariser
+def dtd_apply(z: np.ndarray, grid) -> np.ndarray:
+    """D^T D z for the finite-difference operator of Eq. (l2).
+
+    Per axis, every adjacent pair (i, i+1) adds (z_i - z_{i+1}) to voxel i and
+    (z_{i+1} - z_i) to voxel i+1; the factor 2 comes from each pair being
+    counted from both of its voxels."""
+    nx, ny, nz = grid
+    N, Q = z.shape
+    Z = z.reshape(nz, ny, nx, Q)
+    out = np.zeros_like(Z)
+    for axis in range(3):
+        if Z.shape[axis] < 2:
+            continue
+        diff = np.diff(Z, axis=axis)                  # z_{i+1} - z_i
+        lo = [slice(None)] * 4
+        hi = [slice(None)] * 4
+        lo[axis] = slice(0, Z.shape[axis] - 1)
+        hi[axis] = slice(1, Z.shape[axis])
+        out[tuple(lo)] -= diff
+        out[tuple(hi)] += diff
+    return 2.0 * out.reshape(N, Q)
+
+
+def reg_value(z: np.ndarray, grid) -> float:
+    """R(z) = 1/2 ||D z||^2 = 1/2 <z, D^T D z> (Eq. l2)."""
+    return 0.5 * float(np.sum(z * dtd_apply(z, grid)))
+
+
+def dtd_norm(grid, dense_limit: int = 1024) -> float:
+    """Spectral norm ||D^T D||_2.
+
+    Small grids: largest eigenvalue of the dense D^T D (built by applying the
+    operator to the identity). Larger grids: D^T D = 2 (L_x (+) L_y (+) L_z),
+    a Kronecker sum of path-graph Laplacians whose largest eigenvalues are
+    2 + 2 cos(pi / n_a) (0 for a single-voxel axis)."""
+    nx, ny, nz = grid
+    N = nx * ny * nz
+    if N <= dense_limit:
+        A = dtd_apply(np.eye(N), grid)
+        return float(np.linalg.eigvalsh(0.5 * (A + A.T))[-1])
+    lam = 0.0
+    for n in (nx, ny, nz):
+        if n > 1:
+            lam += 2.0 + 2.0 * np.cos(np.pi / n)
+    return 2.0 * lam
+
+
+def xi_rule(lam: float, grid) -> float:
+    """xi_p = 0.75 lambda ||D^T D|| + epsilon (Eq. sigma_cond)."""
+    return XI_FACTOR * lam * dtd_norm(grid) + EPS_XI
+
+
+# --------------------------------------------------------------- objective
+def objective(K_r: np.ndarray, m: np.ndarray, z: np.ndarray, grid, lam: float) -> float:
+    """Cost of Eq. (spat) with R of Eq. (l2): 1/2 ||m - (I (x) K_r) z||^2 + lambda R(z)."""
+    res = m - z @ K_r.T
+    return 0.5 * float(np.sum(res * res)) + lam * reg_value(z, grid)
+
+
+# --------------------------------------------------------------- LADMM steps
+def f_step(c: np.ndarray, V_r: np.ndarray, s_w: np.ndarray, beta: float) -> np.ndarray:
+    """f_n = c_n / beta - sum_i s_i v_i (v_i^T c_n) for every voxel (Eq. DictVecSVD)."""
+    return c / beta - ((c @ V_r) * s_w) @ V_r.T
+
+
+def z_step(z, f, d, lam, xi, beta, grid):
+    """z^{k+1} = max(0, (xi z - lambda D^T D z + beta f + d) / (xi + beta)) (Eq. z2)."""
+    return np.maximum(0.0, (xi * z - lam * dtd_apply(z, grid) + beta * f + d) / (xi + beta))
+
+
+def d_step(d, z_new, f, beta):
+    """d^{k+1} = d^k - beta (z^{k+1} - f^{k+1}) (dual update)."""
+    return d - beta * (z_new - f)
+
+
+def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
+          track_every=0, f_star=None):
+    """Run Algorithm 2 for a fixed number of iterations.
+
+    Returns a dict with z, f, d (N, Q), the rank r, xi and, when
+    track_every > 0, a history of (k, objective(z^k), DFCS(z^k)) where DFCS
+    follows Eq. (DFCS) against f_star when one is given."""
+    K = np.asarray(K, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz = grid
+    N = nx * ny * nz
+    P, Q = K.shape
+    if m.shape != (N, P):
+        raise ValueError("m must be (N, P)")
+    U, s, V = thin_svd(K)
+    r = rank_rule(s, rank)
+    U_r, s_r, V_r = U[:, :r], s[:r], V[:, :r]
+    if xi is None:
+        xi = xi_rule(lam, grid)
+    # weights sigma_i^2 / (beta^2 + beta sigma_i^2) of Eq. (DictVecSVD)
+    s_w = s_r * s_r / (beta * beta + beta * s_r * s_r)
+    # g_n = sum_{i<=r} sigma_i v_i u_i^T m_n
+    g = ((m @ U_r) * s_r) @ V_r.T
+    z = np.zeros((N, Q)) if z0 is None else np.array(z0, dtype=np.float64)
+    d = np.zeros((N, Q)) if d0 is None else np.array(d0, dtype=np.float64)
+    f = np.zeros((N, Q))
+    K_r = (U_r * s_r) @ V_r.T
+    hist = []
+    for k in range(iters):
+        if track_every and k % track_every == 0:
+            hist.append(_track(k, K_r, m, z, grid, lam, f_star))
+        c = g + beta * z - d
+        f = f_step(c, V_r, s_w, beta)
+        z_new = z_step(z, f, d, lam, xi, beta, grid)
+        d = d_step(d, z_new, f, beta)
+        z = z_new
+    if track_every:
+        hist.append(_track(iters, K_r, m, z, grid, lam, f_star))
+    return dict(z=z, f=f, d=d, rank=r, xi=float(xi), sigma=s, hist=hist, K_r=K_r)
+
+
+def _track(k, K_r, m, z, grid, lam, f_star):
+    J = objective(K_r, m, z, grid, lam)
+    dfcs = None
+    if f_star is not None:
+        dfcs = float(np.linalg.norm(z - f_star) / np.linalg.norm(f_star))
+    return (k, J, dfcs)
