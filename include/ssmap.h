@@ -1,0 +1,173 @@
+/*
+ * ssmap.h -- C ABI of libssmap: spatially-regularised, nonnegative
+ * spatial-spectral partial-volume mapping with the LADMM iteration of
+ * Liu, Mandal, Liao, Setsompop, Haldar (arXiv 2401.12890), run on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Eq. spat with the regulariser of Eq. l2, Sec. II-C):
+ *     minimise_{f >= 0}  1/2 || m - (I_N (x) K) f ||^2 + lambda R(f),
+ *     R(f) = sum_n sum_{m in Delta(n)} 1/2 || f_n - f_m ||^2 = 1/2 || D f ||^2,
+ * with K the P x Q dictionary (linear mixture model, Sec. II-A), m_n the P
+ * measurements of voxel n and f_n its Q spectral values.
+ *
+ * Method: Algorithm 2 of the paper (Sec. III-E) -- the single splitting
+ * f = z of Eq. (Optprob_const), the low-rank f-step of Eq. (DictVecSVD)
+ * and the linearised z-step of Eq. (z2) -- for a fixed number of
+ * iterations from z = d = 0.
+ *
+ * Conventions used at this boundary:
+ *   - Box grid (nx, ny, nz), nz = 1 for 2-D; voxel n = x + nx*(y + ny*z).
+ *   - Delta(n): face neighbours (4 in 2-D, 6 in 3-D), free boundary (edge
+ *     voxels have fewer neighbours). Every adjacent pair appears twice in
+ *     the double sum of Eq. (l2), so D^T D = 2 L (L the grid Laplacian) and
+ *     ||D^T D|| = 2 * sum_axes (2 + 2 cos(pi / n_axis)).
+ *   - The returned map is z^K, the nonnegative iterate after K iterations.
+ *   - Dictionaries, data and maps are dense, row-major, float64 on the host.
+ *
+ * Ownership: the caller owns every buffer it passes; ssmap_create copies K
+ * and ssmap_solve copies M. A context owns all device memory it allocates
+ * and frees it in ssmap_destroy. A context is not thread-safe; distinct
+ * contexts may be used from distinct threads.
+ *
+ * Errors: functions return an ssmap_status (negative on failure) and never
+ * throw across the ABI. After SSMAP_EINVAL, SSMAP_ENOMEM or SSMAP_ENONFINITE
+ * the context stays usable. After SSMAP_EDEVICE it is poisoned: every later
+ * call on it returns SSMAP_EDEVICE until ssmap_destroy. ssmap_last_error
+ * gives a message for the last failure on a context.
+ */
+#ifndef SSMAP_H
+#define SSMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssmap_ctx ssmap_ctx;
+
+typedef enum {
+    SSMAP_OK = 0,
+    SSMAP_EINVAL = -1,      /* invalid argument (sizes, NULL, beta <= 0, ...) */
+    SSMAP_ENOMEM = -2,      /* device memory (or SSMAP_HBM_BUDGET) exceeded    */
+    SSMAP_EDEVICE = -3,     /* HIP runtime error; the context is poisoned       */
+    SSMAP_ENONFINITE = -4,  /* NaN/Inf in the input or in a monitored iterate    */
+    SSMAP_ENODEV = -5       /* no usable gfx950 device                           */
+} ssmap_status;
+
+/* Arithmetic of the iteration. The setup (SVD, rank, xi_p, coefficients)
+ * and the monitoring reductions are float64 in every case. */
+typedef enum {
+    SSMAP_FP64 = 0,         /* float64 state and contractions                    */
+    SSMAP_FP32 = 1,         /* float32 state and contractions                    */
+    SSMAP_BF16X3 = 2        /* float32 state; contractions as three bf16 products
+                               (hi*hi + hi*lo + lo*hi) with float32 accumulation */
+} ssmap_precision;
+
+/* Kernel family for the iteration (both compute the same iterates). */
+typedef enum {
+    SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows, else unfused */
+    SSMAP_KERNEL_UNFUSED = 1,
+    SSMAP_KERNEL_FUSED = 2
+} ssmap_kernel;
+
+enum {
+    SSMAP_KEEP_AUX = 1      /* keep f^K and d^K of the solve for ssmap_get_aux    */
+};
+
+/* LADMM parameters (Algorithm 2 inputs, Sec. III-E; selection rules, Sec. III-F). */
+typedef struct {
+    double beta;            /* penalty parameter, > 0                                    */
+    double xi_p;            /* <= 0: 0.75 * lambda * ||D^T D|| + 1e-10 (Eq. sigma_cond)   */
+    int rank;               /* 0: smallest r with ||K - K_r||_F < 5e-5 ||K||_F (Sec.
+                               III-F); -1: min(P, Q), the unapproximated K; > 0: that r */
+    int precision;          /* ssmap_precision                                           */
+    int check_every;        /* 0: no monitoring; k > 0: objective/residual reductions
+                               every k iterations and after the last one                 */
+    int flags;              /* SSMAP_KEEP_AUX                                            */
+    int kernel;             /* ssmap_kernel                                              */
+    int reserved;
+} ssmap_steps;
+
+#define SSMAP_MAX_HIST 512
+
+/* Observability of the last solve on a context. */
+typedef struct {
+    int rank;               /* r used                                             */
+    int rank_padded;        /* r rounded up for the contraction tiles              */
+    int precision;
+    int kernel;             /* ssmap_kernel actually used (1 or 2)                 */
+    int iters;              /* iterations run                                      */
+    int n_hist;             /* entries in the history arrays                       */
+    double xi_p;            /* xi_p used                                           */
+    double tau;             /* 1 / (xi_p + beta)                                   */
+    double dtd_norm;        /* ||D^T D||                                           */
+    double sigma_max;       /* largest singular value of K                         */
+    double setup_ms;        /* ssmap_create: SVD and uploads                        */
+    double project_ms;      /* data projection h = Sigma_r U_r^T m                  */
+    double iterate_ms;      /* the iteration loop, monitoring included             */
+    double output_ms;       /* z^K to the voxel-major output                        */
+    double device_bytes;    /* device memory held by the context                   */
+    int hist_iter[SSMAP_MAX_HIST];
+    double hist_objective[SSMAP_MAX_HIST];  /* 1/2||m - K_r z||^2 + lambda R(z)    */
+    double hist_dual[SSMAP_MAX_HIST];       /* beta ||z^k - z^{k-1}||               */
+    double hist_znorm[SSMAP_MAX_HIST];      /* ||z^k||                              */
+} ssmap_stats;
+
+/* Factor the dictionary and prepare a context for a fixed grid.
+ *   K     : P*Q float64, row-major (K[p*Q + q]); finite, not all zero.
+ *   P, Q  : >= 1.
+ *   grid  : {nx, ny, nz}, each >= 1 (nz = 1 for 2-D).
+ *   out   : receives the context (NULL on failure).
+ * Computes the thin SVD of K in float64 (Algorithm 2, SVD step) and
+ * uploads the factors to the current HIP device. */
+ssmap_status ssmap_create(const double *K, int P, int Q, const int64_t grid[3],
+                          ssmap_ctx **out);
+
+/* Run `iters` LADMM iterations (Algorithm 2) on host data.
+ *   M      : N*P float64, voxel-major (M[n*P + p]); N = nx*ny*nz.
+ *   lambda : regularisation weight, >= 0.
+ *   steps  : LADMM parameters (see ssmap_steps).
+ *   iters  : >= 0; 0 returns zeros (z^0 = 0).
+ *   F_out  : N*Q float64, voxel-major; receives z^iters.
+ * Blocks until the result is on the host. */
+ssmap_status ssmap_solve(ssmap_ctx *ctx, const double *M, double lambda,
+                         const ssmap_steps *steps, int iters, double *F_out);
+
+/* Same as ssmap_solve on device buffers, ordered on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).
+ *   dM : device, N*P voxel-major, float64 for SSMAP_FP64, else float32.
+ *   dF : device, N*Q voxel-major, same element type as dM; receives z^iters.
+ * The buffers are borrowed for the duration of the call, which returns
+ * after the work has completed on the stream. */
+ssmap_status ssmap_solve_device(ssmap_ctx *ctx, const void *dM, double lambda,
+                                const ssmap_steps *steps, int iters, void *dF,
+                                void *hip_stream);
+
+/* f^iters and d^iters of the last solve run with SSMAP_KEEP_AUX.
+ *   f_out, d_out : N*Q float64 voxel-major host buffers; either may be NULL. */
+ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out);
+
+/* Statistics of the last solve (see ssmap_stats). */
+ssmap_status ssmap_get_stats(const ssmap_ctx *ctx, ssmap_stats *out);
+
+/* Singular values of K (descending), min(P, Q) of them, into sigma_out
+ * (capacity `cap`); returns the count through *n_out. */
+ssmap_status ssmap_get_singular_values(const ssmap_ctx *ctx, double *sigma_out,
+                                       int cap, int *n_out);
+
+/* Message for the last failure on ctx (or of the last failed ssmap_create
+ * when ctx is NULL). Valid until the next call on the same context. */
+const char *ssmap_last_error(const ssmap_ctx *ctx);
+
+/* Release the context and its device memory. NULL is a no-op. */
+void ssmap_destroy(ssmap_ctx *ctx);
+
+/* Library version string. */
+const char *ssmap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSMAP_H */

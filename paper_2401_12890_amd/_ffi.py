@@ -1,0 +1,237 @@
+"""ctypes binding of libssmap (include/ssmap.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels. If the built
+library is missing this module raises at load time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SSMAP_LIB", os.path.join(HERE, "libssmap.so"))
+
+SSMAP_OK = 0
+SSMAP_EINVAL = -1
+SSMAP_ENOMEM = -2
+SSMAP_EDEVICE = -3
+SSMAP_ENONFINITE = -4
+SSMAP_ENODEV = -5
+STATUS_NAMES = {0: "SSMAP_OK", -1: "SSMAP_EINVAL", -2: "SSMAP_ENOMEM", -3: "SSMAP_EDEVICE",
+                -4: "SSMAP_ENONFINITE", -5: "SSMAP_ENODEV"}
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+KERNELS = {"auto": 0, "unfused": 1, "fused": 2}
+SSMAP_KEEP_AUX = 1
+MAX_HIST = 512
+
+EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_get_aux",
+           "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
+           "ssmap_destroy", "ssmap_version"]
+
+
+class Steps(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("xi_p", ctypes.c_double), ("rank", ctypes.c_int),
+                ("precision", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("flags", ctypes.c_int), ("kernel", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int), ("rank_padded", ctypes.c_int), ("precision", ctypes.c_int),
+                ("kernel", ctypes.c_int), ("iters", ctypes.c_int), ("n_hist", ctypes.c_int),
+                ("xi_p", ctypes.c_double), ("tau", ctypes.c_double), ("dtd_norm", ctypes.c_double),
+                ("sigma_max", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("project_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
+                ("output_ms", ctypes.c_double), ("device_bytes", ctypes.c_double),
+                ("hist_iter", ctypes.c_int * MAX_HIST),
+                ("hist_objective", ctypes.c_double * MAX_HIST),
+                ("hist_dual", ctypes.c_double * MAX_HIST),
+                ("hist_znorm", ctypes.c_double * MAX_HIST)]
+
+
+class SsmapError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libssmap.so (raises OSError when it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise OSError(f"libssmap.so not built at {p}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    lib.ssmap_create.argtypes = [dp, ip, ip, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)]
+    lib.ssmap_create.restype = ip
+    lib.ssmap_solve.argtypes = [vp, dp, ctypes.c_double, ctypes.POINTER(Steps), ip, dp]
+    lib.ssmap_solve.restype = ip
+    lib.ssmap_solve_device.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Steps), ip, vp, vp]
+    lib.ssmap_solve_device.restype = ip
+    lib.ssmap_get_aux.argtypes = [vp, dp, dp]
+    lib.ssmap_get_aux.restype = ip
+    lib.ssmap_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.ssmap_get_stats.restype = ip
+    lib.ssmap_get_singular_values.argtypes = [vp, dp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.ssmap_get_singular_values.restype = ip
+    lib.ssmap_last_error.argtypes = [vp]
+    lib.ssmap_last_error.restype = ctypes.c_char_p
+    lib.ssmap_destroy.argtypes = [vp]
+    lib.ssmap_destroy.restype = None
+    lib.ssmap_version.argtypes = []
+    lib.ssmap_version.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_steps(beta, xi_p=0.0, rank=0, precision="fp64", check_every=0, keep_aux=False,
+               kernel="auto") -> Steps:
+    return Steps(beta=float(beta), xi_p=float(xi_p), rank=int(rank),
+                 precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                 check_every=int(check_every), flags=SSMAP_KEEP_AUX if keep_aux else 0,
+                 kernel=KERNELS[kernel] if isinstance(kernel, str) else int(kernel), reserved=0)
+
+
+# ------------------------------------------------------------------ C names
+def ssmap_create(K: np.ndarray, grid) -> int:
+    """Returns the context handle (int); raises SsmapError on failure."""
+    lib = load()
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    P, Q = K.shape
+    g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    out = ctypes.c_void_p()
+    st = lib.ssmap_create(_dptr(K), P, Q, g, ctypes.byref(out))
+    if st != SSMAP_OK:
+        raise SsmapError(st, lib.ssmap_last_error(None).decode())
+    return out.value
+
+
+def _check(ctx, st):
+    if st != SSMAP_OK:
+        raise SsmapError(st, load().ssmap_last_error(ctx).decode())
+
+
+def ssmap_solve(ctx: int, M: np.ndarray, lam: float, steps: Steps, iters: int, N: int, Q: int):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    F = np.empty((N, Q), dtype=np.float64)
+    _check(ctx, load().ssmap_solve(ctx, _dptr(M), float(lam), ctypes.byref(steps), int(iters),
+                                   _dptr(F)))
+    return F
+
+
+def ssmap_solve_device(ctx: int, dM: int, lam: float, steps: Steps, iters: int, dF: int,
+                       stream: int = 0):
+    _check(ctx, load().ssmap_solve_device(ctx, ctypes.c_void_p(dM), float(lam),
+                                          ctypes.byref(steps), int(iters), ctypes.c_void_p(dF),
+                                          ctypes.c_void_p(stream)))
+
+
+def ssmap_get_aux(ctx: int, N: int, Q: int):
+    f = np.empty((N, Q), dtype=np.float64)
+    d = np.empty((N, Q), dtype=np.float64)
+    _check(ctx, load().ssmap_get_aux(ctx, _dptr(f), _dptr(d)))
+    return f, d
+
+
+def ssmap_get_stats(ctx: int) -> dict:
+    s = Stats()
+    _check(ctx, load().ssmap_get_stats(ctx, ctypes.byref(s)))
+    n = s.n_hist
+    return dict(rank=s.rank, rank_padded=s.rank_padded, precision=s.precision, kernel=s.kernel,
+                iters=s.iters, xi_p=s.xi_p, tau=s.tau, dtd_norm=s.dtd_norm,
+                sigma_max=s.sigma_max, setup_ms=s.setup_ms, project_ms=s.project_ms,
+                iterate_ms=s.iterate_ms, output_ms=s.output_ms, device_bytes=s.device_bytes,
+                hist_iter=list(s.hist_iter[:n]), hist_objective=list(s.hist_objective[:n]),
+                hist_dual=list(s.hist_dual[:n]), hist_znorm=list(s.hist_znorm[:n]))
+
+
+def ssmap_get_singular_values(ctx: int) -> np.ndarray:
+    lib = load()
+    n = ctypes.c_int()
+    _check(ctx, lib.ssmap_get_singular_values(ctx, None, 0, ctypes.byref(n)))
+    out = np.empty(n.value, dtype=np.float64)
+    _check(ctx, lib.ssmap_get_singular_values(ctx, _dptr(out), n.value, ctypes.byref(n)))
+    return out
+
+
+def ssmap_last_error(ctx: int | None) -> str:
+    return load().ssmap_last_error(ctx).decode()
+
+
+def ssmap_destroy(ctx: int | None) -> None:
+    load().ssmap_destroy(ctx)
+
+
+def ssmap_version() -> str:
+    return load().ssmap_version().decode()
+
+
+# ------------------------------------------------------------------ convenience
+class Mapper:
+    """One dictionary on one grid (owns an ssmap context)."""
+
+    def __init__(self, K: np.ndarray, grid):
+        self.K = np.ascontiguousarray(K, dtype=np.float64)
+        self.P, self.Q = self.K.shape
+        self.grid = tuple(int(v) for v in grid)
+        self.N = self.grid[0] * self.grid[1] * self.grid[2]
+        self.ctx = ssmap_create(self.K, self.grid)
+
+    def solve(self, M, lam, beta, iters, **kw) -> np.ndarray:
+        return ssmap_solve(self.ctx, M, lam, make_steps(beta, **kw), iters, self.N, self.Q)
+
+    def solve_torch(self, M, lam, beta, iters, F=None, stream=None, **kw):
+        """Device solve on torch tensors (float64 for fp64, float32 otherwise)."""
+        import torch
+        steps = make_steps(beta, **kw)
+        dt = torch.float64 if steps.precision == 0 else torch.float32
+        if M.dtype != dt or not M.is_cuda or not M.is_contiguous():
+            raise ValueError(f"M must be a contiguous device tensor of {dt}")
+        if M.shape != (self.N, self.P):
+            raise ValueError("M must be (N, P)")
+        if F is None:
+            F = torch.empty((self.N, self.Q), dtype=dt, device=M.device)
+        if F.dtype != dt or not F.is_contiguous() or F.shape != (self.N, self.Q):
+            raise ValueError("F must be a contiguous (N, Q) tensor of the I/O type")
+        s = stream if stream is not None else torch.cuda.current_stream(M.device)
+        ssmap_solve_device(self.ctx, M.data_ptr(), lam, steps, iters, F.data_ptr(), s.cuda_stream)
+        return F
+
+    def aux(self):
+        return ssmap_get_aux(self.ctx, self.N, self.Q)
+
+    def stats(self) -> dict:
+        return ssmap_get_stats(self.ctx)
+
+    def singular_values(self) -> np.ndarray:
+        return ssmap_get_singular_values(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            ssmap_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

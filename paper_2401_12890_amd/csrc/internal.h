@@ -1,0 +1,84 @@
+// Internal interfaces of libssmap (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace ssmap {
+
+// Iteration arithmetic (mirrors ssmap_precision).
+enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2 };
+
+// Spectral nodes are stored in chunks of QC consecutive q per voxel:
+// element (q, n) lives at ((q / QC) * N + n) * QC + q % QC. Q is padded to a
+// multiple of QC with rows of V equal to zero, which keeps padded z at 0.
+constexpr int QC = 16;
+
+// Monitoring reduction slots.
+enum { ST_DATA = 0, ST_REG, ST_ZNORM, ST_DZ, ST_NONFINITE, ST_COUNT = 8 };
+
+void thin_svd(const double *K, int P, int Q, std::vector<double> &U,
+              std::vector<double> &s, std::vector<double> &V);
+
+struct Grid {
+    int64_t nx, ny, nz, N;
+};
+
+// Device pointers and scalars of one LADMM iteration in the reduced form
+// (state z, plus per-voxel r-vectors w, y and the constant a*h).
+struct IterArgs {
+    const void *z;        // z^k      (chunked layout, Qp x N)
+    void *znew;           // z^{k+1}
+    void *w;              // w^k -> w^{k+1}   (RP x N, row i at i*N)
+    void *y;              // y^k -> y^{k+1}   (RP x N)
+    const void *ah;       // a .* h          (RP x N)
+    const void *V;        // V_r, Qp x RP row-major, zero padded (state type)
+    const void *Vhi;      // bf16 split of V (uint16, Qp x RP) for MODE_BF16X3
+    const void *Vlo;
+    const void *bcoef;    // b_i = sigma_i^2 / (beta + sigma_i^2), RP (state type)
+    int r, RP, nchunk;
+    Grid g;
+    double tau, lam2, beta;   // tau = 1/(xi+beta), lam2 = 2*lambda (D^T D = 2L)
+    const void *dprev;    // optional: d^k (for f^{k+1})
+    void *fout;           // optional: f^{k+1}
+    void *dout;           // optional: d^{k+1}
+};
+
+// Unfused reference kernels (any rank).
+void launch_update_unfused(int mode, const IterArgs &a, hipStream_t s);
+void launch_projw_unfused(int mode, const IterArgs &a, hipStream_t s);
+
+// Fused single-pass iteration (MFMA contractions); returns false if the
+// configuration (mode, RP) has no fused kernel.
+bool fused_supported(int mode, int RP);
+void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s);
+
+// Data projection t = U_r^T m, ah = a .* (sigma .* t), w = ah, y = 0,
+// mperp2 = ||m||^2 - ||t||^2; sets *bad != 0 if m holds a NaN/Inf.
+void launch_project(int mode, const void *M, int P, const double *Ur, const double *sig,
+                    const double *acoef, int r, int RP, int64_t N, double *t,
+                    double *mperp2, void *ah, void *w, void *y, int *bad, hipStream_t s);
+
+// Monitoring: per-block float64 partial sums of the objective terms, then a
+// fixed-order final reduction into out[ST_COUNT].
+void launch_monitor(int mode, const void *z, const void *zprev, const double *V64,
+                    const double *sig, const double *t, const double *mperp2, int r,
+                    int RP, int nchunk, Grid g, double *partial, int nblocks_cap,
+                    double *out, hipStream_t s);
+int monitor_blocks(int64_t N);
+
+// Chunked state -> voxel-major output (element type of the mode's I/O, or
+// float64 when to_double is set).
+void launch_output(int mode, const void *z, void *F, int Q, int64_t N, bool to_double,
+                   hipStream_t s);
+
+// Fill a device array of `count` elements of `elem_bytes` (4 or 8) with zero.
+void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s);
+
+// float -> bf16 (round to nearest even) hi/lo split of V on the device.
+void launch_split_bf16(const float *V, uint16_t *hi, uint16_t *lo, size_t count,
+                       hipStream_t s);
+
+}  // namespace ssmap

@@ -1,0 +1,399 @@
+// Setup, monitoring and output kernels shared by both iteration kernels,
+// and the unfused reference iteration (two passes per iteration, any rank).
+//
+// The iteration is Algorithm 2 (Sec. III-E) written in a reduced form that
+// gives the same iterates in exact arithmetic. With K_r = U_r S_r V_r^T,
+// h_n = S_r U_r^T m_n (so g_n = V_r h_n), a_i = 1/(beta + s_i^2) and
+// b_i = s_i^2/(beta + s_i^2) (the two parts of the weights of
+// Eq. DictVecSVD), the f-step becomes
+//     f^{k+1} = z^k - d^k/beta + V_r w^k,  w^k = a.h - b.(V_r^T z^k - V_r^T d^k/beta).
+// Substituting f into the z-step of Eq. (z2) cancels d exactly:
+//     z^{k+1} = max(0, z^k - tau (lambda D^T D z^k - beta V_r w^k)),  tau = 1/(xi_p + beta),
+//     d^{k+1} = beta (z^k - z^{k+1} + V_r w^k),
+// and, with y^k = V_r^T z^k, the r-vector recursion
+//     w^{k+1} = a.h - b.(2 y^{k+1} - y^k - w^k),  w^0 = a.h,  y^0 = 0.
+// Only z (Q per voxel) and three r-vectors per voxel are kept, and the form
+// has no c/beta - V(s.V^T c) cancellation, so it holds accuracy in float32.
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ssmap {
+
+namespace {
+
+template <int MODE> struct StateT { using T = float; };
+template <> struct StateT<MODE_FP64> { using T = double; };
+
+// bf16 round-to-nearest-even of a float, returned as a float (low 16 bits 0).
+__device__ __forceinline__ float bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+// Product used by the contractions. MODE_BF16X3 emulates the three-term
+// split product hi*hi + hi*lo + lo*hi that the MFMA path evaluates.
+template <int MODE, typename T>
+__device__ __forceinline__ T cprod(T v, T x) {
+    if constexpr (MODE == MODE_BF16X3) {
+        const float vh = bf16_rne(v), vl = bf16_rne(v - vh);
+        const float xh = bf16_rne(x), xl = bf16_rne(x - xh);
+        return vh * xh + (vh * xl + vl * xh);
+    } else {
+        return v * x;
+    }
+}
+
+__device__ __forceinline__ int64_t chunk_index(int q, int64_t n, int64_t N) {
+    return ((int64_t)(q / QC) * N + n) * QC + (q % QC);
+}
+
+// ------------------------------------------------------------- projection
+template <int MODE, int RB>
+__global__ void __launch_bounds__(256)
+k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
+          const double *__restrict__ Ur, const double *__restrict__ sig,
+          const double *__restrict__ acoef, int r, int RP, int64_t N,
+          double *__restrict__ t, double *__restrict__ mperp2,
+          typename StateT<MODE>::T *__restrict__ ah, typename StateT<MODE>::T *__restrict__ w,
+          typename StateT<MODE>::T *__restrict__ y, int *__restrict__ bad) {
+    using T = typename StateT<MODE>::T;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const T *mrow = M + n * P;
+    double msq = 0.0;
+    bool finite = true;
+    for (int p = 0; p < P; ++p) {
+        const double v = (double)mrow[p];
+        finite &= __builtin_isfinite(v);
+        msq += v * v;
+    }
+    if (!finite) atomicOr(bad, 1);
+    double tsq = 0.0;
+    for (int i0 = 0; i0 < r; i0 += RB) {
+        double acc[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[j] = 0.0;
+        for (int p = 0; p < P; ++p) {
+            const double v = (double)mrow[p];
+            const double *urow = Ur + (size_t)p * r + i0;
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if (i0 + j < r) acc[j] += urow[j] * v;
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int i = i0 + j;
+            if (i < r) {
+                tsq += acc[j] * acc[j];
+                if (t) t[(size_t)i * N + n] = acc[j];
+                const T v = (T)(acoef[i] * (sig[i] * acc[j]));
+                ah[(size_t)i * N + n] = v;
+                w[(size_t)i * N + n] = v;
+                y[(size_t)i * N + n] = (T)0;
+            }
+        }
+    }
+    for (int i = r; i < RP; ++i) {
+        ah[(size_t)i * N + n] = (T)0;
+        w[(size_t)i * N + n] = (T)0;
+        y[(size_t)i * N + n] = (T)0;
+    }
+    if (mperp2) mperp2[n] = msq - tsq;
+}
+
+// ------------------------------------------------------------- unfused iteration
+// Pass 1: for each (q, n): u = (V_r w)_q, the D^T D stencil on plane q,
+// the projected z-update, and optionally d^{k+1} and f^{k+1}.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_update(IterArgs a) {
+    using T = typename StateT<MODE>::T;
+    const int64_t N = a.g.N;
+    const int c = blockIdx.y;
+    const int64_t local = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (local >= N * QC) return;
+    const int64_t n = local / QC;
+    const int qq = (int)(local % QC);
+    const int q = c * QC + qq;
+    const int64_t e = ((int64_t)c * N + n) * QC + qq;
+    const T *z = (const T *)a.z;
+    const T *V = (const T *)a.V + (size_t)q * a.RP;
+    const T *w = (const T *)a.w;
+    T u = 0;
+    for (int i = 0; i < a.r; ++i) u += cprod<MODE>(V[i], w[(size_t)i * N + n]);
+    const T zc = z[e];
+    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int64_t x = n % nx, yy = (n / nx) % ny, zz = n / (nx * ny);
+    T lap = 0;
+    if (x > 0) lap += zc - z[e - QC];
+    if (x < nx - 1) lap += zc - z[e + QC];
+    if (yy > 0) lap += zc - z[e - nx * QC];
+    if (yy < ny - 1) lap += zc - z[e + nx * QC];
+    if (zz > 0) lap += zc - z[e - nx * ny * QC];
+    if (zz < nz - 1) lap += zc - z[e + nx * ny * QC];
+    const T tau = (T)a.tau, lam2 = (T)a.lam2, beta = (T)a.beta;
+    T zn = zc - tau * (lam2 * lap - beta * u);
+    zn = zn > (T)0 ? zn : (T)0;
+    ((T *)a.znew)[e] = zn;
+    if (a.fout) {
+        const T dp = a.dprev ? ((const T *)a.dprev)[e] : (T)0;
+        ((T *)a.fout)[e] = zc + u - dp / beta;
+    }
+    if (a.dout) ((T *)a.dout)[e] = beta * (zc - zn + u);
+}
+
+// Pass 2: y^{k+1} = V_r^T z^{k+1} per voxel and the w recursion.
+template <int MODE, int RB>
+__global__ void __launch_bounds__(256)
+k_projw(IterArgs a) {
+    using T = typename StateT<MODE>::T;
+    const int64_t N = a.g.N;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const T *zn = (const T *)a.znew;
+    const T *V = (const T *)a.V;
+    const T *b = (const T *)a.bcoef;
+    const T *ah = (const T *)a.ah;
+    T *w = (T *)a.w;
+    T *y = (T *)a.y;
+    for (int i0 = 0; i0 < a.r; i0 += RB) {
+        T acc[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[j] = 0;
+        for (int c = 0; c < a.nchunk; ++c) {
+            const T *zp = zn + ((int64_t)c * N + n) * QC;
+            for (int qq = 0; qq < QC; ++qq) {
+                const T zv = zp[qq];
+                const T *vrow = V + (size_t)(c * QC + qq) * a.RP + i0;
+#pragma unroll
+                for (int j = 0; j < RB; ++j)
+                    if (i0 + j < a.RP) acc[j] += cprod<MODE>(vrow[j], zv);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int i = i0 + j;
+            if (i < a.r) {
+                const size_t o = (size_t)i * N + n;
+                const T yn = acc[j];
+                w[o] = ah[o] - b[i] * ((T)2 * yn - y[o] - w[o]);
+                y[o] = yn;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- monitoring
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_monitor(const typename StateT<MODE>::T *__restrict__ z,
+          const typename StateT<MODE>::T *__restrict__ zprev, const double *__restrict__ V64,
+          const double *__restrict__ sig, const double *__restrict__ t,
+          const double *__restrict__ mperp2, int r, int RP, int nchunk, Grid g,
+          double *__restrict__ partial) {
+    using T = typename StateT<MODE>::T;
+    const int64_t N = g.N;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        // data term: ||m_perp||^2 + sum_i (t_i - sigma_i y_i)^2 with y = V_r^T z in float64
+        double data = mperp2[n];
+        for (int i0 = 0; i0 < r; i0 += 8) {
+            double yv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int c = 0; c < nchunk; ++c) {
+                const T *zp = z + ((int64_t)c * N + n) * QC;
+                for (int qq = 0; qq < QC; ++qq) {
+                    const double zv = (double)zp[qq];
+                    const double *vrow = V64 + (size_t)(c * QC + qq) * RP + i0;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (i0 + j < RP) yv[j] += vrow[j] * zv;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = i0 + j;
+                if (i < r) {
+                    const double e = t[(size_t)i * N + n] - sig[i] * yv[j];
+                    data += e * e;
+                }
+            }
+        }
+        // regulariser: each forward edge once; norms; non-finite count
+        const int64_t x = n % g.nx, yy = (n / g.nx) % g.ny, zz = n / (g.nx * g.ny);
+        double reg = 0.0, zsq = 0.0, dsq = 0.0, bad = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            const int64_t base = ((int64_t)c * N + n) * QC;
+            for (int qq = 0; qq < QC; ++qq) {
+                const double zc = (double)z[base + qq];
+                if (!__builtin_isfinite(zc)) bad += 1.0;
+                zsq += zc * zc;
+                if (zprev) {
+                    const double dz = zc - (double)zprev[base + qq];
+                    dsq += dz * dz;
+                }
+                if (x < g.nx - 1) {
+                    const double dd = zc - (double)z[base + qq + QC];
+                    reg += dd * dd;
+                }
+                if (yy < g.ny - 1) {
+                    const double dd = zc - (double)z[base + qq + g.nx * QC];
+                    reg += dd * dd;
+                }
+                if (zz < g.nz - 1) {
+                    const double dd = zc - (double)z[base + qq + g.nx * g.ny * QC];
+                    reg += dd * dd;
+                }
+            }
+        }
+        acc[0] += data;
+        acc[1] += reg;
+        acc[2] += zsq;
+        acc[3] += dsq;
+        acc[4] += bad;
+    }
+    __shared__ double red[5][256];
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < ST_COUNT; ++k)
+            partial[(size_t)blockIdx.x * ST_COUNT + k] = k < 5 ? red[k][0] : 0.0;
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_partials(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
+    __shared__ double red[ST_COUNT][256];
+    double acc[ST_COUNT];
+    for (int k = 0; k < ST_COUNT; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < ST_COUNT; ++k) acc[k] += partial[(size_t)b * ST_COUNT + k];
+    for (int k = 0; k < ST_COUNT; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < ST_COUNT; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < ST_COUNT) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------- output
+template <typename T, typename O>
+__global__ void __launch_bounds__(256)
+k_output(const T *__restrict__ z, O *__restrict__ F, int Q, int64_t N) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N * Q) return;
+    const int64_t n = idx / Q;
+    const int q = (int)(idx % Q);
+    F[idx] = (O)z[chunk_index(q, n, N)];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero(T *p, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = (T)0;
+}
+
+__global__ void __launch_bounds__(256)
+k_split_bf16(const float *__restrict__ V, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+             size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float v = V[i];
+    const float h = bf16_rne(v);
+    const float l = bf16_rne(v - h);
+    hi[i] = (uint16_t)(__float_as_uint(h) >> 16);
+    lo[i] = (uint16_t)(__float_as_uint(l) >> 16);
+}
+
+inline unsigned blocks_for(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+void launch_project(int mode, const void *M, int P, const double *Ur, const double *sig,
+                    const double *acoef, int r, int RP, int64_t N, double *t, double *mperp2,
+                    void *ah, void *w, void *y, int *bad, hipStream_t s) {
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    if (mode == MODE_FP64)
+        hipLaunchKernelGGL((k_project<MODE_FP64, 16>), grid, block, 0, s, (const double *)M, P,
+                           Ur, sig, acoef, r, RP, N, t, mperp2, (double *)ah, (double *)w,
+                           (double *)y, bad);
+    else
+        hipLaunchKernelGGL((k_project<MODE_FP32, 16>), grid, block, 0, s, (const float *)M, P,
+                           Ur, sig, acoef, r, RP, N, t, mperp2, (float *)ah, (float *)w,
+                           (float *)y, bad);
+}
+
+void launch_update_unfused(int mode, const IterArgs &a, hipStream_t s) {
+    const dim3 grid(blocks_for(a.g.N * QC, 256), a.nchunk), block(256);
+    if (mode == MODE_FP64) hipLaunchKernelGGL(k_update<MODE_FP64>, grid, block, 0, s, a);
+    else if (mode == MODE_FP32) hipLaunchKernelGGL(k_update<MODE_FP32>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_update<MODE_BF16X3>, grid, block, 0, s, a);
+}
+
+void launch_projw_unfused(int mode, const IterArgs &a, hipStream_t s) {
+    const dim3 grid(blocks_for(a.g.N, 256)), block(256);
+    if (mode == MODE_FP64) hipLaunchKernelGGL((k_projw<MODE_FP64, 16>), grid, block, 0, s, a);
+    else if (mode == MODE_FP32) hipLaunchKernelGGL((k_projw<MODE_FP32, 16>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_projw<MODE_BF16X3, 16>), grid, block, 0, s, a);
+}
+
+int monitor_blocks(int64_t N) {
+    const int64_t b = (N + 255) / 256;
+    return (int)(b < 2048 ? b : 2048);
+}
+
+void launch_monitor(int mode, const void *z, const void *zprev, const double *V64,
+                    const double *sig, const double *t, const double *mperp2, int r, int RP,
+                    int nchunk, Grid g, double *partial, int nblocks_cap, double *out,
+                    hipStream_t s) {
+    int nb = monitor_blocks(g.N);
+    if (nb > nblocks_cap) nb = nblocks_cap;
+    if (mode == MODE_FP64)
+        hipLaunchKernelGGL(k_monitor<MODE_FP64>, dim3(nb), dim3(256), 0, s, (const double *)z,
+                           (const double *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, partial);
+    else
+        hipLaunchKernelGGL(k_monitor<MODE_FP32>, dim3(nb), dim3(256), 0, s, (const float *)z,
+                           (const float *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+}
+
+void launch_output(int mode, const void *z, void *F, int Q, int64_t N, bool to_double,
+                   hipStream_t s) {
+    const dim3 grid(blocks_for(N * Q, 256)), block(256);
+    if (mode == MODE_FP64)
+        hipLaunchKernelGGL((k_output<double, double>), grid, block, 0, s, (const double *)z,
+                           (double *)F, Q, N);
+    else if (to_double)
+        hipLaunchKernelGGL((k_output<float, double>), grid, block, 0, s, (const float *)z,
+                           (double *)F, Q, N);
+    else
+        hipLaunchKernelGGL((k_output<float, float>), grid, block, 0, s, (const float *)z,
+                           (float *)F, Q, N);
+}
+
+void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s) {
+    if (count == 0) return;
+    const dim3 grid(blocks_for((int64_t)count, 256)), block(256);
+    if (elem_bytes == 8) hipLaunchKernelGGL(k_zero<double>, grid, block, 0, s, (double *)p, count);
+    else if (elem_bytes == 4) hipLaunchKernelGGL(k_zero<float>, grid, block, 0, s, (float *)p, count);
+    else hipLaunchKernelGGL(k_zero<uint16_t>, grid, block, 0, s, (uint16_t *)p, count);
+}
+
+void launch_split_bf16(const float *V, uint16_t *hi, uint16_t *lo, size_t count, hipStream_t s) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_split_bf16, dim3(blocks_for((int64_t)count, 256)), dim3(256), 0, s, V,
+                       hi, lo, count);
+}
+
+}  // namespace ssmap

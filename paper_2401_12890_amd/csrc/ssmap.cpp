@@ -1,0 +1,559 @@
+// libssmap host side: the C ABI, validation, parameter rules, device memory
+// plan and the launch sequence of the LADMM solve (Algorithm 2, Sec. III-E).
+#include "../../include/ssmap.h"
+#include "internal.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ssmap;
+
+namespace {
+
+constexpr double kEpsXi = 1e-10;      // epsilon of Eq. (sigma_cond)
+constexpr double kXiFactor = 0.75;    // xi_p > 0.75 lambda ||D^T D|| (Sec. III-F)
+constexpr double kRankTol = 5e-5;     // 0.005 % Frobenius error (Sec. III-F)
+
+struct Fail {
+    ssmap_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(ssmap_status st, const std::string &msg) { throw Fail{st, msg}; }
+
+std::string g_create_error;            // last ssmap_create failure (no context yet)
+
+}  // namespace
+
+struct ssmap_ctx {
+    int P = 0, Q = 0, kmin = 0, Qp = 0, nchunk = 0;
+    Grid g{};
+    int device = 0;
+    std::vector<double> U, s, V;          // thin SVD: U (P x k), s (k), V (Q x k)
+    double dtd_norm = 0.0;
+    bool poisoned = false;
+    std::string err;
+    ssmap_stats stats{};
+    // device buffers by name; kept until destroy and grown on demand
+    std::map<std::string, std::pair<void *, size_t>> bufs;
+    size_t held = 0;
+    // aux of the last solve
+    bool aux_valid = false;
+    int aux_mode = 0;
+    int aux_iters = 0;
+    void *aux_f = nullptr, *aux_d = nullptr;
+    hipEvent_t ev[6] = {};
+    double *host_stats = nullptr;         // pinned ST_COUNT doubles
+};
+
+namespace {
+
+void hip_check(ssmap_ctx *c, hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        if (c) c->poisoned = true;
+        fail(SSMAP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+#define HIPC(ctx, call) hip_check(ctx, (call), #call)
+
+size_t budget_bytes() {
+    const char *env = std::getenv("SSMAP_HBM_BUDGET");
+    if (!env || !*env) return (size_t)-1;
+    char *end = nullptr;
+    const double v = std::strtod(env, &end);
+    if (!(v >= 0)) return (size_t)-1;
+    return (size_t)v;
+}
+
+// Make sure the named buffer holds at least `bytes`; returns the pointer.
+void *ensure(ssmap_ctx *c, const std::string &name, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    auto it = c->bufs.find(name);
+    if (it != c->bufs.end() && it->second.second >= bytes) return it->second.first;
+    size_t extra = bytes - (it != c->bufs.end() ? it->second.second : 0);
+    if (c->held + extra > budget_bytes())
+        fail(SSMAP_ENOMEM, "device memory budget exceeded (SSMAP_HBM_BUDGET) for " + name);
+    if (it != c->bufs.end()) {
+        HIPC(c, hipFree(it->second.first));
+        c->held -= it->second.second;
+        c->bufs.erase(it);
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        fail(SSMAP_ENOMEM, "hipMalloc failed for " + name);
+    }
+    HIPC(c, e);
+    c->bufs[name] = {p, bytes};
+    c->held += bytes;
+    return p;
+}
+
+// Plan check before any allocation of a solve: fail early with ENOMEM.
+void plan_check(ssmap_ctx *c, const std::vector<std::pair<std::string, size_t>> &need) {
+    size_t extra = 0;
+    for (auto &kv : need) {
+        auto it = c->bufs.find(kv.first);
+        const size_t have = it == c->bufs.end() ? 0 : it->second.second;
+        if (kv.second > have) extra += kv.second - have;
+    }
+    if (c->held + extra > budget_bytes())
+        fail(SSMAP_ENOMEM, "solve needs " + std::to_string(c->held + extra) +
+                               " device bytes, above SSMAP_HBM_BUDGET");
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && extra > freeb)
+        fail(SSMAP_ENOMEM, "solve needs " + std::to_string(extra) + " more device bytes than free");
+}
+
+int rank_rule(const std::vector<double> &s, int rank) {
+    const int k = (int)s.size();
+    if (rank == -1) return k;
+    if (rank > 0) return rank;
+    // tails from the end: tail[r] = sum_{i >= r} s_i^2
+    std::vector<double> tail(k + 1, 0.0);
+    for (int i = k - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
+    const double total = tail[0];
+    for (int r = 1; r <= k; ++r)
+        if (std::sqrt(tail[r]) < kRankTol * std::sqrt(total)) return r;
+    return k;
+}
+
+double dtd_norm_closed(const Grid &g) {
+    // D^T D = 2 (L_x (+) L_y (+) L_z); a path of n voxels has largest
+    // Laplacian eigenvalue 2 + 2 cos(pi / n) (0 when n = 1).
+    double lam = 0.0;
+    for (int64_t n : {g.nx, g.ny, g.nz})
+        if (n > 1) lam += 2.0 + 2.0 * std::cos(M_PI / (double)n);
+    return 2.0 * lam;
+}
+
+struct Plan {
+    int mode, r, RP;
+    double xi, tau, beta, lam;
+    bool fused;
+};
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+void validate_steps(ssmap_ctx *c, double lambda, const ssmap_steps *st, int iters) {
+    if (!st) fail(SSMAP_EINVAL, "steps is NULL");
+    if (!(std::isfinite(lambda) && lambda >= 0)) fail(SSMAP_EINVAL, "lambda must be finite and >= 0");
+    if (!(std::isfinite(st->beta) && st->beta > 0)) fail(SSMAP_EINVAL, "beta must be finite and > 0");
+    if (!std::isfinite(st->xi_p)) fail(SSMAP_EINVAL, "xi_p must be finite");
+    if (iters < 0) fail(SSMAP_EINVAL, "iters must be >= 0");
+    if (st->rank < -1 || st->rank > c->kmin) fail(SSMAP_EINVAL, "rank must be in [-1, min(P,Q)]");
+    if (st->precision < SSMAP_FP64 || st->precision > SSMAP_BF16X3)
+        fail(SSMAP_EINVAL, "unknown precision");
+    if (st->check_every < 0) fail(SSMAP_EINVAL, "check_every must be >= 0");
+    if (st->kernel < SSMAP_KERNEL_AUTO || st->kernel > SSMAP_KERNEL_FUSED)
+        fail(SSMAP_EINVAL, "unknown kernel");
+}
+
+Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
+    Plan p{};
+    p.mode = st->precision;
+    p.r = rank_rule(c->s, st->rank);
+    p.beta = st->beta;
+    p.lam = lambda;
+    p.xi = st->xi_p > 0 ? st->xi_p : kXiFactor * lambda * c->dtd_norm + kEpsXi;
+    p.tau = 1.0 / (p.xi + p.beta);
+    p.RP = ((p.r + 15) / 16) * 16;
+    const bool can_fuse = fused_supported(p.mode, p.RP);
+    if (st->kernel == SSMAP_KERNEL_FUSED && !can_fuse)
+        fail(SSMAP_EINVAL, "no fused kernel for this precision and rank");
+    p.fused = st->kernel == SSMAP_KERNEL_FUSED || (st->kernel == SSMAP_KERNEL_AUTO && can_fuse);
+    return p;
+}
+
+// The solve on device buffers (dM, dF in the mode's I/O type).
+void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *st, int iters,
+                void *dF, hipStream_t s) {
+    const Plan pl = make_plan(c, lambda, st);
+    const int64_t N = c->g.N;
+    const int P = c->P, Q = c->Q, Qp = c->Qp, r = pl.r, RP = pl.RP;
+    const size_t esz = pl.mode == MODE_FP64 ? 8 : 4;
+    const bool monitor = st->check_every > 0;
+    const bool aux = (st->flags & SSMAP_KEEP_AUX) != 0;
+    const size_t zbytes = (size_t)Qp * N * esz;
+    const size_t rbytes = (size_t)RP * N * esz;
+
+    std::vector<std::pair<std::string, size_t>> need = {
+        {"z0", zbytes}, {"z1", zbytes}, {"w", rbytes}, {"y", rbytes}, {"ah", rbytes},
+        {"V", (size_t)Qp * RP * esz}, {"b", (size_t)RP * esz}, {"Ur", (size_t)P * r * 8},
+        {"sig", (size_t)RP * 8}, {"acoef", (size_t)RP * 8}, {"bad", 256}};
+    if (monitor) {
+        need.push_back({"t", (size_t)r * N * 8});
+        need.push_back({"mperp2", (size_t)N * 8});
+        need.push_back({"V64", (size_t)Qp * RP * 8});
+        need.push_back({"partial", (size_t)2048 * ST_COUNT * 8});
+        need.push_back({"stat", (size_t)ST_COUNT * 8});
+    }
+    if (aux) {
+        need.push_back({"auxA", zbytes});
+        need.push_back({"auxB", zbytes});
+    }
+    if (pl.mode == MODE_BF16X3) {
+        need.push_back({"Vhi", (size_t)Qp * RP * 2});
+        need.push_back({"Vlo", (size_t)Qp * RP * 2});
+    }
+    plan_check(c, need);
+    void *z[2] = {ensure(c, "z0", zbytes), ensure(c, "z1", zbytes)};
+    void *w = ensure(c, "w", rbytes), *y = ensure(c, "y", rbytes), *ah = ensure(c, "ah", rbytes);
+    void *Vd = ensure(c, "V", (size_t)Qp * RP * esz);
+    void *bd = ensure(c, "b", (size_t)RP * esz);
+    double *Ur = (double *)ensure(c, "Ur", (size_t)P * r * 8);
+    double *sig = (double *)ensure(c, "sig", (size_t)RP * 8);
+    double *acoef = (double *)ensure(c, "acoef", (size_t)RP * 8);
+    int *bad = (int *)ensure(c, "bad", 256);
+
+    // ---- per-solve coefficients (float64 on the host), Sec. III-F rules
+    std::vector<double> Vh((size_t)Qp * RP, 0.0), Urh((size_t)P * r), sh(RP, 0.0), ah_(RP, 0.0),
+        bh(RP, 0.0);
+    for (int q = 0; q < Q; ++q)
+        for (int i = 0; i < r; ++i) Vh[(size_t)q * RP + i] = c->V[(size_t)q * c->kmin + i];
+    for (int p = 0; p < P; ++p)
+        for (int i = 0; i < r; ++i) Urh[(size_t)p * r + i] = c->U[(size_t)p * c->kmin + i];
+    for (int i = 0; i < r; ++i) {
+        const double s2 = c->s[i] * c->s[i];
+        sh[i] = c->s[i];
+        ah_[i] = 1.0 / (pl.beta + s2);        // 1/beta - s_i of Eq. (DictVecSVD)
+        bh[i] = s2 / (pl.beta + s2);          // beta * s_i of Eq. (DictVecSVD)
+    }
+    if (pl.mode == MODE_FP64) {
+        HIPC(c, hipMemcpyAsync(Vd, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
+        HIPC(c, hipMemcpyAsync(bd, bh.data(), RP * 8, hipMemcpyHostToDevice, s));
+    } else {
+        std::vector<float> Vf(Vh.begin(), Vh.end()), bf(bh.begin(), bh.end());
+        HIPC(c, hipMemcpyAsync(Vd, Vf.data(), Vf.size() * 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipMemcpyAsync(bd, bf.data(), RP * 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipStreamSynchronize(s));       // host staging vectors go out of scope
+    }
+    HIPC(c, hipMemcpyAsync(Ur, Urh.data(), Urh.size() * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(sig, sh.data(), RP * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(acoef, ah_.data(), RP * 8, hipMemcpyHostToDevice, s));
+    void *Vhi = nullptr, *Vlo = nullptr;
+    if (pl.mode == MODE_BF16X3) {
+        Vhi = ensure(c, "Vhi", (size_t)Qp * RP * 2);
+        Vlo = ensure(c, "Vlo", (size_t)Qp * RP * 2);
+        launch_split_bf16((const float *)Vd, (uint16_t *)Vhi, (uint16_t *)Vlo, (size_t)Qp * RP, s);
+    }
+    double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr;
+    if (monitor) {
+        V64 = (double *)ensure(c, "V64", (size_t)Qp * RP * 8);
+        HIPC(c, hipMemcpyAsync(V64, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
+        t = (double *)ensure(c, "t", (size_t)r * N * 8);
+        mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
+        partial = (double *)ensure(c, "partial", (size_t)2048 * ST_COUNT * 8);
+        stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
+    }
+    HIPC(c, hipStreamSynchronize(s));         // Vh, Urh, ... are host locals
+
+    ssmap_stats &S = c->stats;
+    std::memset(&S, 0, sizeof(S));
+    S.rank = r;
+    S.rank_padded = RP;
+    S.precision = pl.mode;
+    S.kernel = pl.fused ? SSMAP_KERNEL_FUSED : SSMAP_KERNEL_UNFUSED;
+    S.xi_p = pl.xi;
+    S.tau = pl.tau;
+    S.dtd_norm = c->dtd_norm;
+    S.sigma_max = c->s.empty() ? 0.0 : c->s[0];
+    c->aux_valid = false;
+
+    // ---- a1: data projection, state initialisation (z^0 = 0, w^0 = a.h, y^0 = 0)
+    HIPC(c, hipEventRecord(c->ev[0], s));
+    launch_zero(bad, 1, 4, s);
+    launch_project(pl.mode, dM, P, Ur, sig, acoef, r, RP, N, t, mperp2, ah, w, y, bad, s);
+    launch_zero(z[0], (size_t)Qp * N, (int)esz, s);
+    if (iters >= 1) launch_zero(z[1], (size_t)Qp * N, (int)esz, s);
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipEventRecord(c->ev[1], s));
+    int badh = 0;
+    HIPC(c, hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (badh) fail(SSMAP_ENONFINITE, "M holds a NaN or Inf");
+
+    void *auxA = nullptr, *auxB = nullptr;
+    if (aux) {
+        auxA = ensure(c, "auxA", zbytes);
+        auxB = ensure(c, "auxB", zbytes);
+        launch_zero(auxA, (size_t)Qp * N, (int)esz, s);
+        launch_zero(auxB, (size_t)Qp * N, (int)esz, s);
+    }
+
+    // ---- the LADMM loop (a2 .. a7)
+    IterArgs a{};
+    a.w = w;
+    a.y = y;
+    a.ah = ah;
+    a.V = Vd;
+    a.Vhi = Vhi;
+    a.Vlo = Vlo;
+    a.bcoef = bd;
+    a.r = r;
+    a.RP = RP;
+    a.nchunk = c->nchunk;
+    a.g = c->g;
+    a.tau = pl.tau;
+    a.lam2 = 2.0 * pl.lam;
+    a.beta = pl.beta;
+    HIPC(c, hipEventRecord(c->ev[2], s));
+    int cur = 0;
+    for (int k = 0; k < iters; ++k) {
+        a.z = z[cur];
+        a.znew = z[cur ^ 1];
+        a.dprev = nullptr;
+        a.fout = nullptr;
+        a.dout = nullptr;
+        if (aux && k == iters - 2) a.dout = auxA;                 // d^{K-1}
+        if (aux && k == iters - 1) {
+            a.dprev = iters >= 2 ? auxA : nullptr;                 // d^{K-1} (0 when K = 1)
+            a.fout = auxA;                                        // f^K, in place
+            a.dout = auxB;                                        // d^K
+        }
+        if (pl.fused) {
+            launch_iter_fused(pl.mode, a, s);
+        } else {
+            launch_update_unfused(pl.mode, a, s);
+            launch_projw_unfused(pl.mode, a, s);
+        }
+        if (monitor && ((k + 1) % st->check_every == 0 || k + 1 == iters)) {
+            launch_monitor(pl.mode, z[cur ^ 1], z[cur], V64, sig, t, mperp2, r, RP, c->nchunk,
+                           c->g, partial, 2048, stat, s);
+            HIPC(c, hipGetLastError());
+            HIPC(c, hipMemcpyAsync(c->host_stats, stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
+            HIPC(c, hipStreamSynchronize(s));
+            const double *h = c->host_stats;
+            if (S.n_hist < SSMAP_MAX_HIST) {
+                S.hist_iter[S.n_hist] = k + 1;
+                S.hist_objective[S.n_hist] = 0.5 * h[ST_DATA] + pl.lam * h[ST_REG];
+                S.hist_dual[S.n_hist] = pl.beta * std::sqrt(h[ST_DZ]);
+                S.hist_znorm[S.n_hist] = std::sqrt(h[ST_ZNORM]);
+                S.n_hist++;
+            }
+            if (h[ST_NONFINITE] != 0.0 || !std::isfinite(h[ST_DATA]))
+                fail(SSMAP_ENONFINITE, "non-finite iterate at iteration " + std::to_string(k + 1));
+        }
+        cur ^= 1;
+    }
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipEventRecord(c->ev[3], s));
+    // ---- a8: z^K to the voxel-major output
+    launch_output(pl.mode, z[cur], dF, Q, N, false, s);
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipEventRecord(c->ev[4], s));
+    HIPC(c, hipStreamSynchronize(s));
+    S.iters = iters;
+    S.project_ms = elapsed_ms(c->ev[0], c->ev[1]);
+    S.iterate_ms = elapsed_ms(c->ev[2], c->ev[3]);
+    S.output_ms = elapsed_ms(c->ev[3], c->ev[4]);
+    S.device_bytes = (double)c->held;
+    if (aux) {
+        c->aux_valid = true;
+        c->aux_mode = pl.mode;
+        c->aux_iters = iters;
+        c->aux_f = auxA;
+        c->aux_d = auxB;
+    }
+}
+
+template <typename Fn>
+ssmap_status guarded(ssmap_ctx *c, Fn &&fn) {
+    try {
+        if (c && c->poisoned) fail(SSMAP_EDEVICE, "context poisoned by an earlier device error");
+        fn();
+        return SSMAP_OK;
+    } catch (const Fail &f) {
+        if (c) c->err = f.msg;
+        else g_create_error = f.msg;
+        return f.status;
+    } catch (const std::bad_alloc &) {
+        if (c) c->err = "host allocation failed";
+        else g_create_error = "host allocation failed";
+        return SSMAP_ENOMEM;
+    } catch (...) {
+        if (c) {
+            c->err = "unexpected internal error";
+            c->poisoned = true;
+        } else {
+            g_create_error = "unexpected internal error";
+        }
+        return SSMAP_EDEVICE;
+    }
+}
+
+void free_ctx(ssmap_ctx *c) {
+    if (!c) return;
+    for (auto &kv : c->bufs) (void)hipFree(kv.second.first);
+    c->bufs.clear();
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->host_stats) (void)hipHostFree(c->host_stats);
+    delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ssmap_version(void) { return "ssmap 0.1 (gfx950)"; }
+
+ssmap_status ssmap_create(const double *K, int P, int Q, const int64_t grid[3], ssmap_ctx **out) {
+    if (out) *out = nullptr;
+    ssmap_ctx *c = nullptr;
+    ssmap_status st = guarded(nullptr, [&] {
+        if (!K || !grid || !out) fail(SSMAP_EINVAL, "NULL argument");
+        if (P < 1 || Q < 1) fail(SSMAP_EINVAL, "P and Q must be >= 1");
+        for (int i = 0; i < 3; ++i)
+            if (grid[i] < 1) fail(SSMAP_EINVAL, "grid dimensions must be >= 1");
+        const double Nd = (double)grid[0] * (double)grid[1] * (double)grid[2];
+        if (Nd * (double)((Q + QC - 1) / QC * QC) > 9.0e18)
+            fail(SSMAP_EINVAL, "grid too large");
+        double fro = 0.0;
+        for (size_t i = 0; i < (size_t)P * Q; ++i) {
+            if (!std::isfinite(K[i])) fail(SSMAP_ENONFINITE, "K holds a NaN or Inf");
+            fro += K[i] * K[i];
+        }
+        if (!(fro > 0)) fail(SSMAP_EINVAL, "K is zero");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+            (void)hipGetLastError();
+            fail(SSMAP_ENODEV, "no HIP device");
+        }
+        auto t0 = std::chrono::steady_clock::now();
+        c = new ssmap_ctx();
+        c->P = P;
+        c->Q = Q;
+        c->kmin = std::min(P, Q);
+        c->Qp = (Q + QC - 1) / QC * QC;
+        c->nchunk = c->Qp / QC;
+        c->g = Grid{grid[0], grid[1], grid[2], grid[0] * grid[1] * grid[2]};
+        if (hipGetDevice(&c->device) != hipSuccess) fail(SSMAP_ENODEV, "hipGetDevice failed");
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c->device) != hipSuccess)
+            fail(SSMAP_ENODEV, "hipGetDeviceProperties failed");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            fail(SSMAP_ENODEV, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+        thin_svd(K, P, Q, c->U, c->s, c->V);
+        c->dtd_norm = dtd_norm_closed(c->g);
+        for (auto &e : c->ev) HIPC(c, hipEventCreate(&e));
+        HIPC(c, hipHostMalloc((void **)&c->host_stats, ST_COUNT * sizeof(double)));
+        auto t1 = std::chrono::steady_clock::now();
+        c->stats.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        *out = c;
+    });
+    if (st != SSMAP_OK) {
+        free_ctx(c);
+        if (out) *out = nullptr;
+    }
+    return st;
+}
+
+ssmap_status ssmap_solve_device(ssmap_ctx *ctx, const void *dM, double lambda,
+                                const ssmap_steps *steps, int iters, void *dF, void *hip_stream) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!dM || !dF) fail(SSMAP_EINVAL, "NULL buffer");
+        validate_steps(ctx, lambda, steps, iters);
+        HIPC(ctx, hipSetDevice(ctx->device));
+        const double setup = ctx->stats.setup_ms;
+        solve_impl(ctx, dM, lambda, steps, iters, dF, (hipStream_t)hip_stream);
+        ctx->stats.setup_ms = setup;
+    });
+}
+
+ssmap_status ssmap_solve(ssmap_ctx *ctx, const double *M, double lambda, const ssmap_steps *steps,
+                         int iters, double *F_out) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!M || !F_out) fail(SSMAP_EINVAL, "NULL buffer");
+        validate_steps(ctx, lambda, steps, iters);
+        HIPC(ctx, hipSetDevice(ctx->device));
+        const int64_t N = ctx->g.N;
+        const size_t nm = (size_t)N * ctx->P, nf = (size_t)N * ctx->Q;
+        for (size_t i = 0; i < nm; ++i)
+            if (!std::isfinite(M[i])) fail(SSMAP_ENONFINITE, "M holds a NaN or Inf");
+        const bool f64 = steps->precision == SSMAP_FP64;
+        const size_t esz = f64 ? 8 : 4;
+        plan_check(ctx, {{"io_M", nm * esz}, {"io_F", nf * esz}});
+        void *dM = ensure(ctx, "io_M", nm * esz);
+        void *dF = ensure(ctx, "io_F", nf * esz);
+        hipStream_t s = nullptr;
+        if (f64) {
+            HIPC(ctx, hipMemcpy(dM, M, nm * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> tmp(M, M + nm);
+            HIPC(ctx, hipMemcpy(dM, tmp.data(), nm * 4, hipMemcpyHostToDevice));
+        }
+        const double setup = ctx->stats.setup_ms;
+        solve_impl(ctx, dM, lambda, steps, iters, dF, s);
+        ctx->stats.setup_ms = setup;
+        if (f64) {
+            HIPC(ctx, hipMemcpy(F_out, dF, nf * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(nf);
+            HIPC(ctx, hipMemcpy(tmp.data(), dF, nf * 4, hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < nf; ++i) F_out[i] = tmp[i];
+        }
+    });
+}
+
+ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!ctx->aux_valid) fail(SSMAP_EINVAL, "no solve with SSMAP_KEEP_AUX has run");
+        const int64_t N = ctx->g.N;
+        const size_t nf = (size_t)N * ctx->Q;
+        double *tmp = (double *)ensure(ctx, "io_aux", nf * 8);
+        void *src[2] = {ctx->aux_f, ctx->aux_d};
+        double *dst[2] = {f_out, d_out};
+        for (int k = 0; k < 2; ++k) {
+            if (!dst[k]) continue;
+            if (ctx->aux_iters == 0) {
+                std::memset(dst[k], 0, nf * 8);
+                continue;
+            }
+            launch_output(ctx->aux_mode, src[k], tmp, ctx->Q, N, true, nullptr);
+            HIPC(ctx, hipGetLastError());
+            HIPC(ctx, hipMemcpy(dst[k], tmp, nf * 8, hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+ssmap_status ssmap_get_stats(const ssmap_ctx *ctx, ssmap_stats *out) {
+    if (!ctx || !out) return SSMAP_EINVAL;
+    *out = ctx->stats;
+    return SSMAP_OK;
+}
+
+ssmap_status ssmap_get_singular_values(const ssmap_ctx *ctx, double *sigma_out, int cap,
+                                       int *n_out) {
+    if (!ctx || !n_out) return SSMAP_EINVAL;
+    *n_out = ctx->kmin;
+    if (sigma_out)
+        for (int i = 0; i < std::min(cap, ctx->kmin); ++i) sigma_out[i] = ctx->s[i];
+    return SSMAP_OK;
+}
+
+const char *ssmap_last_error(const ssmap_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+void ssmap_destroy(ssmap_ctx *ctx) { free_ctx(ctx); }
+
+}  // extern "C"
