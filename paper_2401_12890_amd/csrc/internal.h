@@ -38,6 +38,8 @@ struct IterArgs {
     const void *Vhi;      // bf16 split of V (uint16, Qp x RP) for MODE_BF16X3
     const void *Vlo;
     const void *bcoef;    // b_i = sigma_i^2 / (beta + sigma_i^2), RP (state type)
+    const void *Vu;       // fused-kernel operand images of V (state type)
+    const void *Vy;
     int r, RP, nchunk;
     Grid g;
     double tau, lam2, beta;   // tau = 1/(xi+beta), lam2 = 2*lambda (D^T D = 2L)
@@ -54,6 +56,10 @@ void launch_projw_unfused(int mode, const IterArgs &a, hipStream_t s);
 // configuration (mode, RP) has no fused kernel.
 bool fused_supported(int mode, int RP);
 void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s);
+void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
+                    std::vector<double> &Vu, std::vector<double> &Vy);
+void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vu,
+                         std::vector<uint16_t> &Vy);
 
 // Data projection t = U_r^T m, ah = a .* (sigma .* t), w = ah, y = 0,
 // mperp2 = ||m||^2 - ||t||^2; sets *bad != 0 if m holds a NaN/Inf.

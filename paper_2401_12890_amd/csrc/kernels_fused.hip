@@ -1,12 +1,472 @@
-// Fused single-pass LADMM iteration (placeholder until the MFMA kernel lands).
+// Fused single-pass LADMM iteration with MFMA contractions (gfx950).
+//
+// One workgroup owns a brick of TX x TY x TZ voxels (TX = 16) and streams
+// all Q spectral nodes of it in chunks of 16. Per chunk it
+//   1. stages z^k of the brick and its one-voxel face halo into LDS,
+//   2. forms u = V_r w^k on the matrix cores (the f-step contraction of
+//      Eq. DictVecSVD, M = 16 nodes, N = 16 voxels, K = r),
+//   3. applies the D^T D stencil of Eq. (l2) on every plane of the chunk
+//      from LDS, the linearised z-update of Eq. (z2) and the projection onto
+//      z >= 0, and writes z^{k+1},
+//   4. accumulates y^{k+1} = V_r^T z^{k+1} on the matrix cores
+//      (M = 16 ranks, N = 16 voxels, K = 16 nodes), straight from the
+//      registers that hold z^{k+1}.
+// After the last chunk each voxel's r-vectors are updated
+// (w^{k+1} = a.h - b.(2 y^{k+1} - y^k - w^k)). z is read once from HBM
+// and written once per iteration; f and d never touch HBM.
+//
+// Lane mapping (64-lane wave, 16x16 MFMA output): lane l holds voxel
+// j = l % 16 of a 16-voxel row and the four consecutive nodes
+// 4*(l/16) .. 4*(l/16)+3 of the chunk. That is exactly the MFMA D layout,
+// so u arrives where the stencil needs it, and z^{k+1} is fed back as the
+// B operand of the second contraction by permuting the contraction index
+// (step i uses node 4*(l/16)+i in K-row l/16), with V's A operand
+// permuted the same way when it is prepared on the host.
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <cstring>
+
 namespace ssmap {
 
-bool fused_supported(int, int) { return false; }
+namespace {
 
-void launch_iter_fused(int, const IterArgs &, hipStream_t) {}
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// bf16 bits of a float, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_val(unsigned bits) { return __uint_as_float(bits << 16); }
+
+// hi/lo bf16 split of 4 floats into two short4 operands
+__device__ __forceinline__ void split4(const v4f &x, v4s &hi, v4s &lo) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const unsigned h = bf16_bits(x[i]);
+        hi[i] = (short)h;
+        lo[i] = (short)bf16_bits(x[i] - bf16_val(h));
+    }
+}
+
+template <int MODE> struct FT;
+template <> struct FT<MODE_BF16X3> {
+    using T = float;
+    using V4 = v4f;
+};
+template <> struct FT<MODE_FP32> {
+    using T = float;
+    using V4 = v4f;
+    static __device__ __forceinline__ V4 mfma(T a, T b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct FT<MODE_FP64> {
+    using T = double;
+    using V4 = v4d;
+    static __device__ __forceinline__ V4 mfma(T a, T b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int TX = 16;
+
+// Slots of the staged brick: the centre box plus the six one-voxel face
+// layers (edges and corners of the halo box are never read).
+template <int TY, int TZ> struct Brick {
+    static constexpr int SX = TX + 2, SY = TY + 2, SZ = TZ + 2;
+    static constexpr int NS = SX * SY * SZ;
+    // pad the per-quad plane so the four quads of one slot fall on different banks
+    static constexpr int NSP = ((NS + 11) / 16) * 16 + 4;
+    static constexpr int C = TX * TY * TZ;
+    static constexpr int XF = 2 * TY * TZ;
+    static constexpr int YF = 2 * TX * TZ;
+    static constexpr int ZF = 2 * TX * TY;
+    static constexpr int NSLOT = C + XF + YF + ZF;
+
+    // staged slot id -> halo-box coordinates (0..SX-1, ...)
+    static __device__ __forceinline__ void decode(int id, int &sx, int &sy, int &sz) {
+        if (id < C) {
+            sx = id % TX + 1;
+            sy = (id / TX) % TY + 1;
+            sz = id / (TX * TY) + 1;
+            return;
+        }
+        id -= C;
+        if (id < XF) {
+            sx = (id & 1) ? TX + 1 : 0;
+            sy = (id >> 1) % TY + 1;
+            sz = (id >> 1) / TY + 1;
+            return;
+        }
+        id -= XF;
+        if (id < YF) {
+            sx = id % TX + 1;
+            sy = ((id / TX) & 1) ? TY + 1 : 0;
+            sz = id / (2 * TX) + 1;
+            return;
+        }
+        id -= YF;
+        sx = id % TX + 1;
+        sy = (id / TX) % TY + 1;
+        sz = (id / (TX * TY)) ? TZ + 1 : 0;
+    }
+};
+
+template <int MODE, int RB, int TY, int TZ, int MINB>
+__global__ void __launch_bounds__(256, MINB)
+k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
+    using F = FT<MODE>;
+    using T = typename F::T;
+    using V4 = typename F::V4;
+    using B = Brick<TY, TZ>;
+    constexpr int NB = TY * TZ;          // 16-voxel rows in the brick
+    constexpr int BPW = NB / 4;          // rows per wave
+    constexpr int KS = 4 * RB;           // K-steps of the u contraction (r padded to 16*RB)
+    static_assert(NB % 4 == 0, "brick rows must split over 4 waves");
+
+    __shared__ V4 lds[4 * B::NSP];       // [quad][slot]
+
+    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
+    const int ntiles = tiles_x * tiles_y * tiles_z;
+    int tile = blockIdx.x;
+    if ((ntiles & 7) == 0) {             // keep neighbouring bricks on one XCD (shared L2)
+        const int per = ntiles >> 3;
+        tile = (tile & 7) * per + (tile >> 3);
+    }
+    const int tx = tile % tiles_x;
+    const int ty = (tile / tiles_x) % tiles_y;
+    const int tz = tile / (tiles_x * tiles_y);
+    const int64_t x0 = (int64_t)tx * TX, y0 = (int64_t)ty * TY, z0 = (int64_t)tz * TZ;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int j = lane & 15;
+    const int i4 = lane >> 4;
+
+    const T tau = (T)a.tau, lam2 = (T)a.lam2, beta = (T)a.beta;
+    const T *zin = (const T *)a.z;
+    T *zout = (T *)a.znew;
+    const T *Vu = (const T *)a.Vu;
+    const T *Vy = (const T *)a.Vy;
+
+    // per-row voxel coordinates
+    int64_t nvox[BPW];
+    bool valid[BPW];
+    int slot0[BPW];
+    bool hxm[BPW], hxp[BPW], hym[BPW], hyp[BPW], hzm[BPW], hzp[BPW];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int row = wave + 4 * b;
+        const int by = row % TY, bz = row / TY;
+        const int64_t gx = x0 + j, gy = y0 + by, gz = z0 + bz;
+        valid[b] = gx < nx && gy < ny && gz < nz;
+        nvox[b] = gx + nx * (gy + ny * gz);
+        slot0[b] = (j + 1) + B::SX * ((by + 1) + B::SY * (bz + 1));
+        hxm[b] = gx > 0;
+        hxp[b] = gx + 1 < nx;
+        hym[b] = gy > 0;
+        hyp[b] = gy + 1 < ny;
+        hzm[b] = gz > 0;
+        hzp[b] = gz + 1 < nz;
+    }
+
+    // B operand of u = V_r w. fp32/fp64: lane holds w[r = 4 s + l/16][voxel j];
+    // bf16x3: lane holds w[r = 8 (l/16) + jj][voxel j], jj < 8, split hi/lo.
+    constexpr bool BF = MODE == MODE_BF16X3;
+    constexpr int KSW = BF ? 1 : KS;
+    T wop[BPW][KSW];
+    v8bf whi[BF ? BPW : 1], wlo[BF ? BPW : 1];
+    V4 yacc[BPW][RB];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        if constexpr (BF) {
+            v4u h = v4u{0, 0, 0, 0}, l = v4u{0, 0, 0, 0};
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const int r = 8 * i4 + jj;
+                const float v = (valid[b] && r < a.RP) ? ((const T *)a.w)[(size_t)r * N + nvox[b]] : 0.0f;
+                const unsigned hb = bf16_bits(v);
+                const unsigned lb = bf16_bits(v - bf16_val(hb));
+                h[jj >> 1] |= hb << (16 * (jj & 1));
+                l[jj >> 1] |= lb << (16 * (jj & 1));
+            }
+            whi[b] = __builtin_bit_cast(v8bf, h);
+            wlo[b] = __builtin_bit_cast(v8bf, l);
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                wop[b][s] = valid[b] ? ((const T *)a.w)[(size_t)(4 * s + i4) * N + nvox[b]] : (T)0;
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) yacc[b][rb] = V4{0, 0, 0, 0};
+    }
+
+    const size_t chunk_stride = (size_t)N * QC;
+    for (int c = 0; c < a.nchunk; ++c) {
+        // ---- stage z^k (chunk c) of the brick and its face halo into LDS
+        const T *zc_base = zin + (size_t)c * chunk_stride;
+        for (int f = threadIdx.x; f < 4 * B::NSLOT; f += 256) {
+            const int quad = f & 3;
+            int sx, sy, sz;
+            B::decode(f >> 2, sx, sy, sz);
+            const int64_t gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+                const int64_t n = gx + nx * (gy + ny * gz);
+                lds[quad * B::NSP + sx + B::SX * (sy + B::SY * sz)] =
+                    *(const V4 *)(zc_base + n * QC + 4 * quad);
+            }
+        }
+        __syncthreads();
+
+        // V operands of this chunk (pre-permuted on the host, one value per lane)
+        T vu[KSW];
+        T vy[BF ? 1 : RB][4];
+        v8bf vuh, vul;
+        v4s vyh[RB], vyl[RB];
+        if constexpr (BF) {
+            const v4u *U8 = (const v4u *)a.Vu;   // [c][hi/lo][lane] x 8 bf16
+            vuh = __builtin_bit_cast(v8bf, U8[((size_t)c * 2 + 0) * 64 + lane]);
+            vul = __builtin_bit_cast(v8bf, U8[((size_t)c * 2 + 1) * 64 + lane]);
+            const v2u *Y4 = (const v2u *)a.Vy;   // [c][rb][hi/lo][lane] x 4 bf16
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                vyh[rb] = __builtin_bit_cast(v4s, Y4[(((size_t)c * RB + rb) * 2 + 0) * 64 + lane]);
+                vyl[rb] = __builtin_bit_cast(v4s, Y4[(((size_t)c * RB + rb) * 2 + 1) * 64 + lane]);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) vu[s] = Vu[((size_t)c * KS + s) * 64 + lane];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    vy[rb][i] = Vy[(((size_t)c * RB + rb) * 4 + i) * 64 + lane];
+        }
+
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            // u = V_r w^k for 16 nodes x 16 voxels
+            V4 u = V4{0, 0, 0, 0};
+            if constexpr (BF) {
+                // three split products, small terms first: lo*hi + hi*lo + hi*hi
+                u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vul, whi[b], u, 0, 0, 0);
+                u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vuh, wlo[b], u, 0, 0, 0);
+                u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vuh, whi[b], u, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    if (s < ks_eff) u = F::mfma(vu[s], wop[b][s], u);
+            }
+            // D^T D z^k on the four planes of this lane, from LDS
+            const V4 *L = lds + i4 * B::NSP;
+            const int sl = slot0[b];
+            const V4 zc = L[sl];
+            V4 lap = V4{0, 0, 0, 0};
+            if (hxm[b]) lap += zc - L[sl - 1];
+            if (hxp[b]) lap += zc - L[sl + 1];
+            if (hym[b]) lap += zc - L[sl - B::SX];
+            if (hyp[b]) lap += zc - L[sl + B::SX];
+            if (hzm[b]) lap += zc - L[sl - B::SX * B::SY];
+            if (hzp[b]) lap += zc - L[sl + B::SX * B::SY];
+            // projected z-update (Eq. z2 with f substituted)
+            V4 zn = zc - tau * (lam2 * lap - beta * u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zn[i] = zn[i] > (T)0 ? zn[i] : (T)0;
+            if (valid[b]) {
+                const size_t e = (size_t)c * chunk_stride + (size_t)nvox[b] * QC + 4 * i4;
+                *(V4 *)(zout + e) = zn;
+                if (a.fout) {
+                    V4 dp = V4{0, 0, 0, 0};
+                    if (a.dprev) dp = *(const V4 *)((const T *)a.dprev + e);
+                    *(V4 *)((T *)a.fout + e) = zc + u - dp / beta;
+                }
+                if (a.dout) *(V4 *)((T *)a.dout + e) = beta * (zc - zn + u);
+            }
+            // y^{k+1} += V_r^T z^{k+1}: K-row l/16 of step i is node 4*(l/16)+i
+            if constexpr (BF) {
+                // K = the 16 nodes of the chunk in their natural lane order
+                v4s zh, zl;
+                split4(zn, zh, zl);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyl[rb], zh, yacc[b][rb], 0, 0, 0);
+                    yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyh[rb], zl, yacc[b][rb], 0, 0, 0);
+                    yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyh[rb], zh, yacc[b][rb], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        yacc[b][rb] = F::mfma(vy[rb][i], zn[i], yacc[b][rb]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- r-vector recursion; lane holds y^{k+1}[r][voxel j] for the four
+    //      ranks r of its accumulator rows
+    const T *ah = (const T *)a.ah;
+    const T *bc = (const T *)a.bcoef;
+    T *w = (T *)a.w;
+    T *y = (T *)a.y;
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        if (!valid[b]) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // f64 16x16x4 returns rows l/16 + 4 i; the others rows 4 (l/16) + i
+                const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
+                const size_t o = (size_t)r * N + nvox[b];
+                const T yn = yacc[b][rb][i];
+                w[o] = ah[o] - bc[r] * ((T)2 * yn - y[o] - w[o]);
+                y[o] = yn;
+            }
+    }
+}
+
+struct Shape {
+    int ty, tz;
+};
+
+// Brick shape per grid: 2-D grids use one plane.
+Shape pick_shape(int mode, const Grid &g) {
+    if (mode == MODE_FP64) return g.nz == 1 ? Shape{16, 1} : Shape{4, 4};
+    return g.nz == 1 ? Shape{16, 1} : Shape{8, 4};
+}
+
+template <int MODE, int RB, int TY, int TZ, int MINB>
+void launch_t(const IterArgs &a, hipStream_t s) {
+    const int tiles_x = (int)((a.g.nx + TX - 1) / TX);
+    const int tiles_y = (int)((a.g.ny + TY - 1) / TY);
+    const int tiles_z = (int)((a.g.nz + TZ - 1) / TZ);
+    const int ks_eff = (a.r + 3) / 4;
+    hipLaunchKernelGGL((k_fused<MODE, RB, TY, TZ, MINB>), dim3(tiles_x * tiles_y * tiles_z),
+                       dim3(256), 0, s, a, tiles_x, tiles_y, tiles_z, ks_eff);
+}
+
+template <int MODE, int RB>
+void launch_rb(const IterArgs &a, hipStream_t s) {
+    const Shape sh = pick_shape(MODE, a.g);
+    if constexpr (MODE == MODE_FP64) {
+        if (sh.tz == 1) launch_t<MODE, RB, 16, 1, 1>(a, s);
+        else launch_t<MODE, RB, 4, 4, 1>(a, s);
+    } else {
+        if (sh.tz == 1) launch_t<MODE, RB, 16, 1, 2>(a, s);
+        else launch_t<MODE, RB, 8, 4, 2>(a, s);
+    }
+}
+
+}  // namespace
+
+bool fused_supported(int mode, int RP) {
+    return (mode == MODE_FP32 || mode == MODE_FP64 || mode == MODE_BF16X3) &&
+           (RP == 16 || RP == 32);
+}
+
+void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s) {
+    const int RB = a.RP / 16;
+    if (mode == MODE_FP64) {
+        if (RB == 1) launch_rb<MODE_FP64, 1>(a, s);
+        else launch_rb<MODE_FP64, 2>(a, s);
+    } else if (mode == MODE_FP32) {
+        if (RB == 1) launch_rb<MODE_FP32, 1>(a, s);
+        else launch_rb<MODE_FP32, 2>(a, s);
+    } else {
+        if (RB == 1) launch_rb<MODE_BF16X3, 1>(a, s);
+        else launch_rb<MODE_BF16X3, 2>(a, s);
+    }
+}
+
+namespace {
+uint16_t host_bf16_bits(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float host_bf16_val(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+}  // namespace
+
+// bf16 hi/lo operand images of the float32-rounded V for the split-precision
+// fused kernel:
+//   Vu[c][h][l][jj]     = V[16 c + l % 16][8 (l / 16) + jj]   (A of u, K = rank, 32 wide)
+//   Vy[c][rb][h][l][jj] = V[16 c + 4 (l / 16) + jj][16 rb + l % 16]  (A of y, K = 16 nodes)
+// h = 0 holds the rounded value, h = 1 the rounded remainder.
+void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vu,
+                         std::vector<uint16_t> &Vy) {
+    const int nchunk = Qp / QC, RB = RP / 16;
+    Vu.assign((size_t)nchunk * 2 * 64 * 8, 0);
+    Vy.assign((size_t)nchunk * RB * 2 * 64 * 4, 0);
+    auto split = [](double v, uint16_t &h, uint16_t &l) {
+        const float f = (float)v;
+        h = host_bf16_bits(f);
+        l = host_bf16_bits(f - host_bf16_val(h));
+    };
+    for (int c = 0; c < nchunk; ++c)
+        for (int l = 0; l < 64; ++l) {
+            for (int jj = 0; jj < 8; ++jj) {
+                const int r = 8 * (l / 16) + jj;
+                const double v = r < RP ? Vh[(size_t)(16 * c + l % 16) * RP + r] : 0.0;
+                uint16_t h, lo;
+                split(v, h, lo);
+                Vu[(((size_t)c * 2 + 0) * 64 + l) * 8 + jj] = h;
+                Vu[(((size_t)c * 2 + 1) * 64 + l) * 8 + jj] = lo;
+            }
+            for (int rb = 0; rb < RB; ++rb)
+                for (int jj = 0; jj < 4; ++jj) {
+                    const double v = Vh[(size_t)(16 * c + 4 * (l / 16) + jj) * RP + 16 * rb + l % 16];
+                    uint16_t h, lo;
+                    split(v, h, lo);
+                    Vy[((((size_t)c * RB + rb) * 2 + 0) * 64 + l) * 4 + jj] = h;
+                    Vy[((((size_t)c * RB + rb) * 2 + 1) * 64 + l) * 4 + jj] = lo;
+                }
+        }
+}
+
+// Operand images of V for the fused kernel (see the lane mapping above).
+//   Vu[c][s][l]     = V[16 c + row(l % 16)][4 s + l / 16]       (A of u = V w)
+//   Vy[c][rb][i][l] = V[16 c + 4 (l / 16) + i][16 rb + l % 16]  (A of y = V^T z)
+// The f32 16x16x4 MFMA returns output rows 4 (l/16) + i in lane l, the f64
+// one rows l/16 + 4 i; row() maps an MFMA output row of u to the chunk node
+// that lane must hold (node 4 (l/16) + i): identity for f32, m -> 4 (m % 4)
+// + m / 4 for f64.
+void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
+                    std::vector<double> &Vu, std::vector<double> &Vy) {
+    const int nchunk = Qp / QC, RB = RP / 16, KS = 4 * RB;
+    Vu.assign((size_t)nchunk * KS * 64, 0.0);
+    Vy.assign((size_t)nchunk * RB * 4 * 64, 0.0);
+    for (int c = 0; c < nchunk; ++c)
+        for (int l = 0; l < 64; ++l) {
+            for (int s = 0; s < KS; ++s)
+            {
+                const int m = l % 16;
+                const int row = f64_rows ? 4 * (m % 4) + m / 4 : m;
+                Vu[((size_t)c * KS + s) * 64 + l] = Vh[(size_t)(16 * c + row) * RP + 4 * s + l / 16];
+            }
+            for (int rb = 0; rb < RB; ++rb)
+                for (int i = 0; i < 4; ++i)
+                    Vy[(((size_t)c * RB + rb) * 4 + i) * 64 + l] =
+                        Vh[(size_t)(16 * c + 4 * (l / 16) + i) * RP + 16 * rb + l % 16];
+        }
+}
 
 }  // namespace ssmap

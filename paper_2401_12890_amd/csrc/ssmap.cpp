@@ -207,6 +207,10 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
         need.push_back({"auxA", zbytes});
         need.push_back({"auxB", zbytes});
     }
+    if (pl.fused) {
+        need.push_back({"Vu", (size_t)c->nchunk * 4 * (RP / 16) * 64 * esz});
+        need.push_back({"Vy", (size_t)c->nchunk * 4 * (RP / 16) * 64 * esz});
+    }
     if (pl.mode == MODE_BF16X3) {
         need.push_back({"Vhi", (size_t)Qp * RP * 2});
         need.push_back({"Vlo", (size_t)Qp * RP * 2});
@@ -251,6 +255,28 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
         Vhi = ensure(c, "Vhi", (size_t)Qp * RP * 2);
         Vlo = ensure(c, "Vlo", (size_t)Qp * RP * 2);
         launch_split_bf16((const float *)Vd, (uint16_t *)Vhi, (uint16_t *)Vlo, (size_t)Qp * RP, s);
+    }
+    void *Vu = nullptr, *Vy = nullptr;
+    if (pl.fused && pl.mode == MODE_BF16X3) {
+        std::vector<uint16_t> Vu_h, Vy_h;
+        fused_operands_bf16(Vh, Qp, RP, Vu_h, Vy_h);
+        Vu = ensure(c, "Vu", Vu_h.size() * 2);
+        Vy = ensure(c, "Vy", Vy_h.size() * 2);
+        HIPC(c, hipMemcpy(Vu, Vu_h.data(), Vu_h.size() * 2, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(Vy, Vy_h.data(), Vy_h.size() * 2, hipMemcpyHostToDevice));
+    } else if (pl.fused) {
+        std::vector<double> Vu_h, Vy_h;
+        fused_operands(Vh, Qp, RP, pl.mode == MODE_FP64, Vu_h, Vy_h);
+        Vu = ensure(c, "Vu", Vu_h.size() * esz);
+        Vy = ensure(c, "Vy", Vy_h.size() * esz);
+        if (pl.mode == MODE_FP64) {
+            HIPC(c, hipMemcpy(Vu, Vu_h.data(), Vu_h.size() * 8, hipMemcpyHostToDevice));
+            HIPC(c, hipMemcpy(Vy, Vy_h.data(), Vy_h.size() * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> a(Vu_h.begin(), Vu_h.end()), b(Vy_h.begin(), Vy_h.end());
+            HIPC(c, hipMemcpy(Vu, a.data(), a.size() * 4, hipMemcpyHostToDevice));
+            HIPC(c, hipMemcpy(Vy, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+        }
     }
     double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr;
     if (monitor) {
@@ -305,6 +331,8 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
     a.Vhi = Vhi;
     a.Vlo = Vlo;
     a.bcoef = bd;
+    a.Vu = Vu;
+    a.Vy = Vy;
     a.r = r;
     a.RP = RP;
     a.nchunk = c->nchunk;

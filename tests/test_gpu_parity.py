@@ -18,8 +18,11 @@ TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}
 DT = {"fp64": np.float64, "fp32": np.float32, "bf16x3": np.float32}
 
 
-def relerr(a, b):
-    nb = np.linalg.norm(b)
+def relerr(a, b, floor=0.0):
+    """||a - b|| / ||b|| (the DFCS form), with the denominator floored at
+    `floor` for quantities that converge to zero (the dual d and the
+    residual-like parts of f at an interior solution)."""
+    nb = max(np.linalg.norm(b), floor)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
@@ -158,9 +161,10 @@ def test_edge_cases(torch_cuda, kernel, prec, label, case):
     if case["iters"] == 0:
         assert not z.any() and not f.any() and not d.any()
         return
+    scale = prob.beta * np.linalg.norm(ref["z"])     # d is measured against beta * ||z||
     assert relerr(z, ref["z"]) <= tol
     assert relerr(f, ref["f"]) <= 10 * tol
-    assert relerr(d, ref["d"]) <= 10 * tol
+    assert relerr(d, ref["d"], floor=scale) <= 10 * tol
 
 
 # ------------------------------------------------------------ device entry point
