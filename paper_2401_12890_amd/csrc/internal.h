@@ -38,8 +38,8 @@ struct IterArgs {
     const void *Vhi;      // bf16 split of V (uint16, Qp x RP) for MODE_BF16X3
     const void *Vlo;
     const void *bcoef;    // b_i = sigma_i^2 / (beta + sigma_i^2), RP (state type)
-    const void *Vu;       // fused-kernel operand images of V (state type)
-    const void *Vy;
+    const void *Vu;       // fused kernel: per-chunk V operand blocks
+    const void *Vy;       // (unused)
     int r, RP, nchunk;
     Grid g;
     double tau, lam2, beta;   // tau = 1/(xi+beta), lam2 = 2*lambda (D^T D = 2L)
@@ -52,14 +52,22 @@ struct IterArgs {
 void launch_update_unfused(int mode, const IterArgs &a, hipStream_t s);
 void launch_projw_unfused(int mode, const IterArgs &a, hipStream_t s);
 
-// Fused single-pass iteration (MFMA contractions); returns false if the
-// configuration (mode, RP) has no fused kernel.
-bool fused_supported(int mode, int RP);
+// Fused single-pass iteration (MFMA contractions); fused_supported() tells
+// whether (mode, padded rank, voxel count) has a fused kernel.
+bool fused_supported(int mode, int RP, int64_t N);
 void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s);
+// Per-chunk V operand blocks of the fused kernel (IterArgs::Vu points to them).
 void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
-                    std::vector<double> &Vu, std::vector<double> &Vy);
-void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vu,
-                         std::vector<uint16_t> &Vy);
+                    std::vector<double> &Vop);
+void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vop);
+
+// f and d around a fused iteration (see kernels_common.hip):
+// pre: t = z^k + V_r w^k and, if f != NULL, f = t - dprev / beta (dprev NULL: d^k = 0;
+// f may alias dprev); post: t <- beta (t - z^{k+1}) = d^{k+1}.
+void launch_aux_pre(int mode, const IterArgs &a, void *t, void *f, const void *dprev,
+                    hipStream_t s);
+void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t count,
+                     hipStream_t s);
 
 // Data projection t = U_r^T m, ah = a .* (sigma .* t), w = ah, y = 0,
 // mperp2 = ||m||^2 - ||t||^2; sets *bad != 0 if m holds a NaN/Inf.

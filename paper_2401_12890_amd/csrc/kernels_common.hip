@@ -187,6 +187,42 @@ k_projw(IterArgs a) {
     }
 }
 
+// ------------------------------------------------------------- aux (f, d) around a fused pass
+// The fused iteration never materialises f or d. When f^K and d^K are asked
+// for, the last two iterations are bracketed by these passes:
+//   before iteration k:  t = z^k + V_r w^k            (and f^{k+1} = t - d^k / beta)
+//   after  iteration k:  d^{k+1} = beta (t - z^{k+1})
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_aux_pre(IterArgs a, typename StateT<MODE>::T *__restrict__ t, typename StateT<MODE>::T *f,
+          const typename StateT<MODE>::T *dprev) {
+    using T = typename StateT<MODE>::T;
+    const int64_t N = a.g.N;
+    const int c = blockIdx.y;
+    const int64_t local = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (local >= N * QC) return;
+    const int64_t n = local / QC;
+    const int q = c * QC + (int)(local % QC);
+    const int64_t e = ((int64_t)c * N + n) * QC + (local % QC);
+    const T *V = (const T *)a.V + (size_t)q * a.RP;
+    const T *w = (const T *)a.w;
+    T u = 0;
+    for (int i = 0; i < a.r; ++i) u += cprod<MODE>(V[i], w[(size_t)i * N + n]);
+    const T tv = ((const T *)a.z)[e] + u;
+    t[e] = tv;
+    if (f) {
+        const T dp = dprev ? dprev[e] : (T)0;
+        f[e] = tv - dp / (T)a.beta;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_aux_post(T *__restrict__ t, const T *__restrict__ znew, T beta, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) t[i] = beta * (t[i] - znew[i]);
+}
+
 // ------------------------------------------------------------- monitoring
 template <int MODE>
 __global__ void __launch_bounds__(256)
@@ -346,6 +382,31 @@ void launch_projw_unfused(int mode, const IterArgs &a, hipStream_t s) {
     if (mode == MODE_FP64) hipLaunchKernelGGL((k_projw<MODE_FP64, 16>), grid, block, 0, s, a);
     else if (mode == MODE_FP32) hipLaunchKernelGGL((k_projw<MODE_FP32, 16>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_projw<MODE_BF16X3, 16>), grid, block, 0, s, a);
+}
+
+void launch_aux_pre(int mode, const IterArgs &a, void *t, void *f, const void *dprev,
+                    hipStream_t s) {
+    const dim3 grid(blocks_for(a.g.N * QC, 256), a.nchunk), block(256);
+    if (mode == MODE_FP64)
+        hipLaunchKernelGGL(k_aux_pre<MODE_FP64>, grid, block, 0, s, a, (double *)t, (double *)f,
+                           (const double *)dprev);
+    else if (mode == MODE_FP32)
+        hipLaunchKernelGGL(k_aux_pre<MODE_FP32>, grid, block, 0, s, a, (float *)t, (float *)f,
+                           (const float *)dprev);
+    else
+        hipLaunchKernelGGL(k_aux_pre<MODE_BF16X3>, grid, block, 0, s, a, (float *)t, (float *)f,
+                           (const float *)dprev);
+}
+
+void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t count,
+                     hipStream_t s) {
+    const dim3 grid(blocks_for((int64_t)count, 256)), block(256);
+    if (mode == MODE_FP64)
+        hipLaunchKernelGGL(k_aux_post<double>, grid, block, 0, s, (double *)t, (const double *)znew,
+                           beta, count);
+    else
+        hipLaunchKernelGGL(k_aux_post<float>, grid, block, 0, s, (float *)t, (const float *)znew,
+                           (float)beta, count);
 }
 
 int monitor_blocks(int64_t N) {

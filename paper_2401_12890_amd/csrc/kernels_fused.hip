@@ -123,19 +123,69 @@ template <int TY, int TZ> struct Brick {
     }
 };
 
-template <int MODE, int RB, int TY, int TZ, int MINB>
-__global__ void __launch_bounds__(256, MINB)
-k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
+// Bytes of the per-chunk V operand block (u operand image, then y operand image).
+template <int MODE, int RB> struct VopSize {
+    static constexpr int bytes = MODE == MODE_BF16X3 ? 2048 + 1024 * RB
+                               : (MODE == MODE_FP64 ? 4096 * RB : 2048 * RB);
+};
+
+constexpr int NT = 512;                 // threads per workgroup (8 waves)
+constexpr unsigned OOB = 0x80000000u;   // buffer offset beyond every range: loads 0, stores dropped
+constexpr int RSRC_W3 = 0x00020000;     // buffer descriptor word 3 (raw buffer, gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, RSRC_W3);
+}
+
+// Four state values (16 B for float, 32 B for double) through a buffer resource.
+template <typename T, typename V4> struct Buf;
+template <> struct Buf<float, v4f> {
+    static __device__ __forceinline__ v4f load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    }
+    static __device__ __forceinline__ void store(v4f v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, off, 0, 0);
+    }
+};
+template <> struct Buf<double, v4d> {
+    typedef unsigned v8u __attribute__((ext_vector_type(8)));
+    static __device__ __forceinline__ v4d load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(r, off == OOB ? OOB : off + 16, 0, 0);
+        const v8u w = v8u{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        return __builtin_bit_cast(v4d, w);
+    }
+    static __device__ __forceinline__ void store(v4d v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+        const v8u w = __builtin_bit_cast(v8u, v);
+        __builtin_amdgcn_raw_buffer_store_b128(v4u{w[0], w[1], w[2], w[3]}, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v4u{w[4], w[5], w[6], w[7]}, r,
+                                               off == OOB ? OOB : off + 16, 0, 0);
+    }
+};
+
+// KSU: K-steps of the u contraction actually needed (ceil(r / 4)); RB: 16-row
+// blocks of r in the y contraction. bf16x3 uses one 32-wide K-step (KSU unused).
+template <int MODE, int RB, int KSU, int TY, int TZ>
+__global__ void __launch_bounds__(NT, 1)
+k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
     using F = FT<MODE>;
     using T = typename F::T;
     using V4 = typename F::V4;
     using B = Brick<TY, TZ>;
+    using IO = Buf<T, V4>;
+    constexpr bool BF = MODE == MODE_BF16X3;
+    constexpr int NW = NT / 64;
     constexpr int NB = TY * TZ;          // 16-voxel rows in the brick
-    constexpr int BPW = NB / 4;          // rows per wave
-    constexpr int KS = 4 * RB;           // K-steps of the u contraction (r padded to 16*RB)
-    static_assert(NB % 4 == 0, "brick rows must split over 4 waves");
+    constexpr int BPW = NB / NW;         // rows per wave
+    constexpr int NL = (4 * B::NSLOT + NT - 1) / NT;   // staged quads per thread
+    constexpr int VB = VopSize<MODE, RB>::bytes;
+    constexpr int KS = 4 * RB;           // stride of the u part of the V block
+    static_assert(NB % NW == 0, "brick rows must split over the waves");
+    static_assert(VB % 16 == 0 && VB / 16 <= NT, "V operand block must stage in one pass");
+    static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
 
-    __shared__ V4 lds[4 * B::NSP];       // [quad][slot]
+    __shared__ V4 lds[4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
+    __shared__ uint4 ldsv[NT];           // V operands of the chunk (entries >= VB/16 unused)
 
     const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
     const int ntiles = tiles_x * tiles_y * tiles_z;
@@ -149,43 +199,58 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
     const int tz = tile / (tiles_x * tiles_y);
     const int64_t x0 = (int64_t)tx * TX, y0 = (int64_t)ty * TY, z0 = (int64_t)tz * TZ;
 
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int j = lane & 15;
     const int i4 = lane >> 4;
 
     const T tau = (T)a.tau, lam2 = (T)a.lam2, beta = (T)a.beta;
-    const T *zin = (const T *)a.z;
-    T *zout = (T *)a.znew;
-    const T *Vu = (const T *)a.Vu;
-    const T *Vy = (const T *)a.Vy;
+    const size_t chunk_elems = (size_t)N * QC;
+    const unsigned chunk_bytes = (unsigned)(chunk_elems * sizeof(T));
 
-    // per-row voxel coordinates
+    // ---- staging descriptors (fixed for the brick): byte offset of the quad
+    //      inside a chunk (OOB outside the grid, which stages zeros) and its LDS entry
+    unsigned voff[NL];
+    int loff[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const int f = tid + NT * l;
+        voff[l] = OOB;
+        loff[l] = 4 * B::NSP;            // sink
+        if (f < 4 * B::NSLOT) {
+            const int quad = f & 3;
+            int sx, sy, sz;
+            B::decode(f >> 2, sx, sy, sz);
+            loff[l] = quad * B::NSP + sx + B::SX * (sy + B::SY * sz);
+            const int64_t gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                voff[l] = (unsigned)(((gx + nx * (gy + ny * gz)) * QC + 4 * quad) * sizeof(T));
+        }
+    }
+
+    // ---- per-row voxel coordinates, neighbour count and store offsets
     int64_t nvox[BPW];
     bool valid[BPW];
     int slot0[BPW];
-    bool hxm[BPW], hxp[BPW], hym[BPW], hyp[BPW], hzm[BPW], hzp[BPW];
+    T deg[BPW];
+    unsigned soff[BPW];                  // byte offset of this lane's quad in a chunk
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
-        const int row = wave + 4 * b;
+        const int row = wave + NW * b;
         const int by = row % TY, bz = row / TY;
         const int64_t gx = x0 + j, gy = y0 + by, gz = z0 + bz;
         valid[b] = gx < nx && gy < ny && gz < nz;
-        nvox[b] = gx + nx * (gy + ny * gz);
+        nvox[b] = valid[b] ? gx + nx * (gy + ny * gz) : 0;
         slot0[b] = (j + 1) + B::SX * ((by + 1) + B::SY * (bz + 1));
-        hxm[b] = gx > 0;
-        hxp[b] = gx + 1 < nx;
-        hym[b] = gy > 0;
-        hyp[b] = gy + 1 < ny;
-        hzm[b] = gz > 0;
-        hzp[b] = gz + 1 < nz;
+        deg[b] = (T)((gx > 0) + (gx + 1 < nx) + (gy > 0) + (gy + 1 < ny) + (gz > 0) + (gz + 1 < nz));
+        soff[b] = valid[b] ? (unsigned)((nvox[b] * QC + 4 * i4) * sizeof(T)) : OOB;
     }
 
-    // B operand of u = V_r w. fp32/fp64: lane holds w[r = 4 s + l/16][voxel j];
-    // bf16x3: lane holds w[r = 8 (l/16) + jj][voxel j], jj < 8, split hi/lo.
-    constexpr bool BF = MODE == MODE_BF16X3;
-    constexpr int KSW = BF ? 1 : KS;
-    T wop[BPW][KSW];
+    // ---- B operand of u = V_r w. fp32/fp64: lane holds w[r = 4 s + l/16][voxel j];
+    //      bf16x3: lane holds w[r = 8 (l/16) + jj][voxel j], jj < 8, split hi/lo.
+    const T *wsrc = (const T *)a.w;
+    T wop[BPW][BF ? 1 : KSU];
     v8bf whi[BF ? BPW : 1], wlo[BF ? BPW : 1];
     V4 yacc[BPW][RB];
 #pragma unroll
@@ -195,7 +260,7 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
                 const int r = 8 * i4 + jj;
-                const float v = (valid[b] && r < a.RP) ? ((const T *)a.w)[(size_t)r * N + nvox[b]] : 0.0f;
+                const float v = r < a.RP ? wsrc[(size_t)r * N + nvox[b]] : 0.0f;
                 const unsigned hb = bf16_bits(v);
                 const unsigned lb = bf16_bits(v - bf16_val(hb));
                 h[jj >> 1] |= hb << (16 * (jj & 1));
@@ -205,53 +270,63 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
             wlo[b] = __builtin_bit_cast(v8bf, l);
         } else {
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
-                wop[b][s] = valid[b] ? ((const T *)a.w)[(size_t)(4 * s + i4) * N + nvox[b]] : (T)0;
+            for (int s = 0; s < KSU; ++s) wop[b][s] = wsrc[(size_t)(4 * s + i4) * N + nvox[b]];
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) yacc[b][rb] = V4{0, 0, 0, 0};
     }
 
-    const size_t chunk_stride = (size_t)N * QC;
-    for (int c = 0; c < a.nchunk; ++c) {
-        // ---- stage z^k (chunk c) of the brick and its face halo into LDS
-        const T *zc_base = zin + (size_t)c * chunk_stride;
-        for (int f = threadIdx.x; f < 4 * B::NSLOT; f += 256) {
-            const int quad = f & 3;
-            int sx, sy, sz;
-            B::decode(f >> 2, sx, sy, sz);
-            const int64_t gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
-                const int64_t n = gx + nx * (gy + ny * gz);
-                lds[quad * B::NSP + sx + B::SX * (sy + B::SY * sz)] =
-                    *(const V4 *)(zc_base + n * QC + 4 * quad);
-            }
-        }
-        __syncthreads();
+    // ---- prefetch registers: z quads of the next chunk and its V operand block
+    V4 R[NL];
+    uint4 Rv;
+    const __amdgpu_buffer_rsrc_t vrs = rsrc(a.Vu, (unsigned)(a.nchunk * VB));
+    const unsigned vlane = tid < VB / 16 ? (unsigned)tid * 16 : OOB;
+    auto fetch = [&](int c) {
+        const __amdgpu_buffer_rsrc_t zr = rsrc((const T *)a.z + (size_t)c * chunk_elems, chunk_bytes);
+        Rv = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                           vrs, vlane == OOB ? OOB : vlane + (unsigned)(c * VB), 0, 0));
+#pragma unroll
+        for (int l = 0; l < NL; ++l) R[l] = IO::load(zr, voff[l]);
+    };
+    fetch(0);
 
-        // V operands of this chunk (pre-permuted on the host, one value per lane)
-        T vu[KSW];
+    for (int c = 0; c < a.nchunk; ++c) {
+        // ---- chunk c: registers -> LDS (out-of-grid slots hold zeros)
+#pragma unroll
+        for (int l = 0; l < NL; ++l) lds[loff[l]] = R[l];
+        ldsv[tid] = Rv;
+        __syncthreads();
+        // ---- loads of chunk c+1 stay in flight during the arithmetic of chunk c
+        //      (the last pass re-reads its own chunk: one loop path, exact wait counts)
+        fetch(c + 1 < a.nchunk ? c + 1 : c);
+        // keep the loads ahead of the arithmetic (float64 has no registers to spare)
+        if constexpr (MODE != MODE_FP64) __builtin_amdgcn_sched_barrier(0);
+
+        const __amdgpu_buffer_rsrc_t zo = rsrc((T *)a.znew + (size_t)c * chunk_elems, chunk_bytes);
+
+        // V operands of this chunk (one value per lane, see the host layout)
+        T vu[BF ? 1 : KSU];
         T vy[BF ? 1 : RB][4];
         v8bf vuh, vul;
         v4s vyh[RB], vyl[RB];
         if constexpr (BF) {
-            const v4u *U8 = (const v4u *)a.Vu;   // [c][hi/lo][lane] x 8 bf16
-            vuh = __builtin_bit_cast(v8bf, U8[((size_t)c * 2 + 0) * 64 + lane]);
-            vul = __builtin_bit_cast(v8bf, U8[((size_t)c * 2 + 1) * 64 + lane]);
-            const v2u *Y4 = (const v2u *)a.Vy;   // [c][rb][hi/lo][lane] x 4 bf16
+            const v4u *U8 = (const v4u *)ldsv;                      // [hi/lo][lane] x 8 bf16
+            vuh = __builtin_bit_cast(v8bf, U8[lane]);
+            vul = __builtin_bit_cast(v8bf, U8[64 + lane]);
+            const v2u *Y4 = (const v2u *)((const char *)ldsv + 2048); // [rb][hi/lo][lane] x 4 bf16
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                vyh[rb] = __builtin_bit_cast(v4s, Y4[(((size_t)c * RB + rb) * 2 + 0) * 64 + lane]);
-                vyl[rb] = __builtin_bit_cast(v4s, Y4[(((size_t)c * RB + rb) * 2 + 1) * 64 + lane]);
+                vyh[rb] = __builtin_bit_cast(v4s, Y4[(rb * 2 + 0) * 64 + lane]);
+                vyl[rb] = __builtin_bit_cast(v4s, Y4[(rb * 2 + 1) * 64 + lane]);
             }
         } else {
+            const T *VT = (const T *)ldsv;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) vu[s] = Vu[((size_t)c * KS + s) * 64 + lane];
+            for (int s = 0; s < KSU; ++s) vu[s] = VT[s * 64 + lane];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    vy[rb][i] = Vy[(((size_t)c * RB + rb) * 4 + i) * 64 + lane];
+                for (int i = 0; i < 4; ++i) vy[rb][i] = VT[(KS + rb * 4 + i) * 64 + lane];
         }
 
 #pragma unroll
@@ -265,35 +340,21 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
                 u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vuh, whi[b], u, 0, 0, 0);
             } else {
 #pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    if (s < ks_eff) u = F::mfma(vu[s], wop[b][s], u);
+                for (int s = 0; s < KSU; ++s) u = F::mfma(vu[s], wop[b][s], u);
             }
-            // D^T D z^k on the four planes of this lane, from LDS
+            // D^T D z^k on the four planes of this lane, from LDS: neighbours outside
+            // the grid were staged as zeros, so deg * z - sum(neighbours) is exact
             const V4 *L = lds + i4 * B::NSP;
             const int sl = slot0[b];
             const V4 zc = L[sl];
-            V4 lap = V4{0, 0, 0, 0};
-            if (hxm[b]) lap += zc - L[sl - 1];
-            if (hxp[b]) lap += zc - L[sl + 1];
-            if (hym[b]) lap += zc - L[sl - B::SX];
-            if (hyp[b]) lap += zc - L[sl + B::SX];
-            if (hzm[b]) lap += zc - L[sl - B::SX * B::SY];
-            if (hzp[b]) lap += zc - L[sl + B::SX * B::SY];
+            const V4 nsum = (L[sl - 1] + L[sl + 1]) + (L[sl - B::SX] + L[sl + B::SX]) +
+                            (L[sl - B::SX * B::SY] + L[sl + B::SX * B::SY]);
+            const V4 lap = deg[b] * zc - nsum;
             // projected z-update (Eq. z2 with f substituted)
             V4 zn = zc - tau * (lam2 * lap - beta * u);
 #pragma unroll
             for (int i = 0; i < 4; ++i) zn[i] = zn[i] > (T)0 ? zn[i] : (T)0;
-            if (valid[b]) {
-                const size_t e = (size_t)c * chunk_stride + (size_t)nvox[b] * QC + 4 * i4;
-                *(V4 *)(zout + e) = zn;
-                if (a.fout) {
-                    V4 dp = V4{0, 0, 0, 0};
-                    if (a.dprev) dp = *(const V4 *)((const T *)a.dprev + e);
-                    *(V4 *)((T *)a.fout + e) = zc + u - dp / beta;
-                }
-                if (a.dout) *(V4 *)((T *)a.dout + e) = beta * (zc - zn + u);
-            }
-            // y^{k+1} += V_r^T z^{k+1}: K-row l/16 of step i is node 4*(l/16)+i
+            IO::store(zn, zo, soff[b]);
             if constexpr (BF) {
                 // K = the 16 nodes of the chunk in their natural lane order
                 v4s zh, zl;
@@ -305,6 +366,7 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
                     yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyh[rb], zh, yacc[b][rb], 0, 0, 0);
                 }
             } else {
+                // y^{k+1} += V_r^T z^{k+1}: K-row l/16 of step i is node 4*(l/16)+i
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -319,11 +381,11 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
     //      ranks r of its accumulator rows
     const T *ah = (const T *)a.ah;
     const T *bc = (const T *)a.bcoef;
-    T *w = (T *)a.w;
-    T *y = (T *)a.y;
+    const unsigned rbytes = (unsigned)((size_t)a.RP * N * sizeof(T));
+    const __amdgpu_buffer_rsrc_t wr = rsrc(a.w, rbytes), yr = rsrc(a.y, rbytes);
+    const T *yold = (const T *)a.y;
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
-        if (!valid[b]) continue;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -332,8 +394,15 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z, int ks_eff) {
                 const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
                 const size_t o = (size_t)r * N + nvox[b];
                 const T yn = yacc[b][rb][i];
-                w[o] = ah[o] - bc[r] * ((T)2 * yn - y[o] - w[o]);
-                y[o] = yn;
+                const T wn = ah[o] - bc[r] * ((T)2 * yn - yold[o] - wsrc[o]);
+                const unsigned ob = valid[b] ? (unsigned)(o * sizeof(T)) : OOB;
+                if constexpr (sizeof(T) == 8) {
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, wn), wr, ob, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, yn), yr, ob, 0, 0);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, wn), wr, ob, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, yn), yr, ob, 0, 0);
+                }
             }
     }
 }
@@ -348,46 +417,54 @@ Shape pick_shape(int mode, const Grid &g) {
     return g.nz == 1 ? Shape{16, 1} : Shape{8, 4};
 }
 
-template <int MODE, int RB, int TY, int TZ, int MINB>
+template <int MODE, int RB, int KSU, int TY, int TZ>
 void launch_t(const IterArgs &a, hipStream_t s) {
     const int tiles_x = (int)((a.g.nx + TX - 1) / TX);
     const int tiles_y = (int)((a.g.ny + TY - 1) / TY);
     const int tiles_z = (int)((a.g.nz + TZ - 1) / TZ);
-    const int ks_eff = (a.r + 3) / 4;
-    hipLaunchKernelGGL((k_fused<MODE, RB, TY, TZ, MINB>), dim3(tiles_x * tiles_y * tiles_z),
-                       dim3(256), 0, s, a, tiles_x, tiles_y, tiles_z, ks_eff);
+    hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(tiles_x * tiles_y * tiles_z), dim3(NT),
+                       0, s, a, tiles_x, tiles_y, tiles_z);
 }
 
-template <int MODE, int RB>
-void launch_rb(const IterArgs &a, hipStream_t s) {
+template <int MODE, int RB, int KSU>
+void launch_shape(const IterArgs &a, hipStream_t s) {
     const Shape sh = pick_shape(MODE, a.g);
     if constexpr (MODE == MODE_FP64) {
-        if (sh.tz == 1) launch_t<MODE, RB, 16, 1, 1>(a, s);
-        else launch_t<MODE, RB, 4, 4, 1>(a, s);
+        if (sh.tz == 1) launch_t<MODE, RB, KSU, 16, 1>(a, s);
+        else launch_t<MODE, RB, KSU, 4, 4>(a, s);
     } else {
-        if (sh.tz == 1) launch_t<MODE, RB, 16, 1, 2>(a, s);
-        else launch_t<MODE, RB, 8, 4, 2>(a, s);
+        if (sh.tz == 1) launch_t<MODE, RB, KSU, 16, 1>(a, s);
+        else launch_t<MODE, RB, KSU, 8, 4>(a, s);
     }
+}
+
+// u K-steps: r <= 16 -> 4, 17..20 -> 5, 21..24 -> 6, 25..32 -> 8 (zero-padded ranks)
+template <int MODE>
+void launch_mode(const IterArgs &a, hipStream_t s) {
+    if (a.r <= 16) launch_shape<MODE, 1, 4>(a, s);
+    else if (a.r <= 20) launch_shape<MODE, 2, 5>(a, s);
+    else if (a.r <= 24) launch_shape<MODE, 2, 6>(a, s);
+    else launch_shape<MODE, 2, 8>(a, s);
 }
 
 }  // namespace
 
-bool fused_supported(int mode, int RP) {
+bool fused_supported(int mode, int RP, int64_t N) {
+    // buffer offsets are 32-bit and must stay below the out-of-range marker
+    const int64_t esz = mode == MODE_FP64 ? 8 : 4;
     return (mode == MODE_FP32 || mode == MODE_FP64 || mode == MODE_BF16X3) &&
-           (RP == 16 || RP == 32);
+           (RP == 16 || RP == 32) && N * QC * esz < ((int64_t)1 << 31) &&
+           (int64_t)RP * N * esz < ((int64_t)1 << 31);
 }
 
 void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s) {
-    const int RB = a.RP / 16;
     if (mode == MODE_FP64) {
-        if (RB == 1) launch_rb<MODE_FP64, 1>(a, s);
-        else launch_rb<MODE_FP64, 2>(a, s);
+        launch_mode<MODE_FP64>(a, s);
     } else if (mode == MODE_FP32) {
-        if (RB == 1) launch_rb<MODE_FP32, 1>(a, s);
-        else launch_rb<MODE_FP32, 2>(a, s);
+        launch_mode<MODE_FP32>(a, s);
     } else {
-        if (RB == 1) launch_rb<MODE_BF16X3, 1>(a, s);
-        else launch_rb<MODE_BF16X3, 2>(a, s);
+        if (a.RP == 16) launch_shape<MODE_BF16X3, 1, 1>(a, s);
+        else launch_shape<MODE_BF16X3, 2, 1>(a, s);
     }
 }
 
@@ -407,66 +484,70 @@ float host_bf16_val(uint16_t b) {
 }  // namespace
 
 // bf16 hi/lo operand images of the float32-rounded V for the split-precision
-// fused kernel:
-//   Vu[c][h][l][jj]     = V[16 c + l % 16][8 (l / 16) + jj]   (A of u, K = rank, 32 wide)
-//   Vy[c][rb][h][l][jj] = V[16 c + 4 (l / 16) + jj][16 rb + l % 16]  (A of y, K = 16 nodes)
+// fused kernel, one contiguous block per chunk c:
+//   u part: [h][l][jj] = V[16 c + l % 16][8 (l / 16) + jj]        (A of u, K = rank, 32 wide)
+//   y part: [rb][h][l][jj] = V[16 c + 4 (l / 16) + jj][16 rb + l % 16]  (A of y, K = 16 nodes)
 // h = 0 holds the rounded value, h = 1 the rounded remainder.
-void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vu,
-                         std::vector<uint16_t> &Vy) {
+void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vop) {
     const int nchunk = Qp / QC, RB = RP / 16;
-    Vu.assign((size_t)nchunk * 2 * 64 * 8, 0);
-    Vy.assign((size_t)nchunk * RB * 2 * 64 * 4, 0);
+    const size_t per = 2 * 64 * 8 + (size_t)RB * 2 * 64 * 4;   // uint16 per chunk
+    Vop.assign((size_t)nchunk * per, 0);
     auto split = [](double v, uint16_t &h, uint16_t &l) {
         const float f = (float)v;
         h = host_bf16_bits(f);
         l = host_bf16_bits(f - host_bf16_val(h));
     };
-    for (int c = 0; c < nchunk; ++c)
+    for (int c = 0; c < nchunk; ++c) {
+        uint16_t *U = &Vop[(size_t)c * per];
+        uint16_t *Y = U + 2 * 64 * 8;
         for (int l = 0; l < 64; ++l) {
             for (int jj = 0; jj < 8; ++jj) {
                 const int r = 8 * (l / 16) + jj;
                 const double v = r < RP ? Vh[(size_t)(16 * c + l % 16) * RP + r] : 0.0;
                 uint16_t h, lo;
                 split(v, h, lo);
-                Vu[(((size_t)c * 2 + 0) * 64 + l) * 8 + jj] = h;
-                Vu[(((size_t)c * 2 + 1) * 64 + l) * 8 + jj] = lo;
+                U[(0 * 64 + l) * 8 + jj] = h;
+                U[(1 * 64 + l) * 8 + jj] = lo;
             }
             for (int rb = 0; rb < RB; ++rb)
                 for (int jj = 0; jj < 4; ++jj) {
                     const double v = Vh[(size_t)(16 * c + 4 * (l / 16) + jj) * RP + 16 * rb + l % 16];
                     uint16_t h, lo;
                     split(v, h, lo);
-                    Vy[((((size_t)c * RB + rb) * 2 + 0) * 64 + l) * 4 + jj] = h;
-                    Vy[((((size_t)c * RB + rb) * 2 + 1) * 64 + l) * 4 + jj] = lo;
+                    Y[((rb * 2 + 0) * 64 + l) * 4 + jj] = h;
+                    Y[((rb * 2 + 1) * 64 + l) * 4 + jj] = lo;
                 }
         }
+    }
 }
 
-// Operand images of V for the fused kernel (see the lane mapping above).
-//   Vu[c][s][l]     = V[16 c + row(l % 16)][4 s + l / 16]       (A of u = V w)
-//   Vy[c][rb][i][l] = V[16 c + 4 (l / 16) + i][16 rb + l % 16]  (A of y = V^T z)
+// Operand images of V for the fused kernel (see the lane mapping above), one
+// contiguous block of (KS + 4 RB) * 64 values per chunk c:
+//   u part: [s][l]    = V[16 c + row(l % 16)][4 s + l / 16]       (A of u = V w)
+//   y part: [rb][i][l] = V[16 c + 4 (l / 16) + i][16 rb + l % 16]  (A of y = V^T z)
 // The f32 16x16x4 MFMA returns output rows 4 (l/16) + i in lane l, the f64
 // one rows l/16 + 4 i; row() maps an MFMA output row of u to the chunk node
 // that lane must hold (node 4 (l/16) + i): identity for f32, m -> 4 (m % 4)
 // + m / 4 for f64.
 void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
-                    std::vector<double> &Vu, std::vector<double> &Vy) {
+                    std::vector<double> &Vop) {
     const int nchunk = Qp / QC, RB = RP / 16, KS = 4 * RB;
-    Vu.assign((size_t)nchunk * KS * 64, 0.0);
-    Vy.assign((size_t)nchunk * RB * 4 * 64, 0.0);
-    for (int c = 0; c < nchunk; ++c)
+    const size_t per = (size_t)(KS + 4 * RB) * 64;
+    Vop.assign((size_t)nchunk * per, 0.0);
+    for (int c = 0; c < nchunk; ++c) {
+        double *U = &Vop[(size_t)c * per];
+        double *Y = U + (size_t)KS * 64;
         for (int l = 0; l < 64; ++l) {
+            const int m = l % 16;
+            const int row = f64_rows ? 4 * (m % 4) + m / 4 : m;
             for (int s = 0; s < KS; ++s)
-            {
-                const int m = l % 16;
-                const int row = f64_rows ? 4 * (m % 4) + m / 4 : m;
-                Vu[((size_t)c * KS + s) * 64 + l] = Vh[(size_t)(16 * c + row) * RP + 4 * s + l / 16];
-            }
+                U[s * 64 + l] = Vh[(size_t)(16 * c + row) * RP + 4 * s + l / 16];
             for (int rb = 0; rb < RB; ++rb)
                 for (int i = 0; i < 4; ++i)
-                    Vy[(((size_t)c * RB + rb) * 4 + i) * 64 + l] =
+                    Y[(rb * 4 + i) * 64 + l] =
                         Vh[(size_t)(16 * c + 4 * (l / 16) + i) * RP + 16 * rb + l % 16];
         }
+    }
 }
 
 }  // namespace ssmap

@@ -173,7 +173,7 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
     p.xi = st->xi_p > 0 ? st->xi_p : kXiFactor * lambda * c->dtd_norm + kEpsXi;
     p.tau = 1.0 / (p.xi + p.beta);
     p.RP = ((p.r + 15) / 16) * 16;
-    const bool can_fuse = fused_supported(p.mode, p.RP);
+    const bool can_fuse = fused_supported(p.mode, p.RP, c->g.N);
     if (st->kernel == SSMAP_KERNEL_FUSED && !can_fuse)
         fail(SSMAP_EINVAL, "no fused kernel for this precision and rank");
     p.fused = st->kernel == SSMAP_KERNEL_FUSED || (st->kernel == SSMAP_KERNEL_AUTO && can_fuse);
@@ -207,10 +207,7 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
         need.push_back({"auxA", zbytes});
         need.push_back({"auxB", zbytes});
     }
-    if (pl.fused) {
-        need.push_back({"Vu", (size_t)c->nchunk * 4 * (RP / 16) * 64 * esz});
-        need.push_back({"Vy", (size_t)c->nchunk * 4 * (RP / 16) * 64 * esz});
-    }
+    if (pl.fused) need.push_back({"Vop", (size_t)c->nchunk * 8 * RP * 64 * 2});
     if (pl.mode == MODE_BF16X3) {
         need.push_back({"Vhi", (size_t)Qp * RP * 2});
         need.push_back({"Vlo", (size_t)Qp * RP * 2});
@@ -258,24 +255,19 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
     }
     void *Vu = nullptr, *Vy = nullptr;
     if (pl.fused && pl.mode == MODE_BF16X3) {
-        std::vector<uint16_t> Vu_h, Vy_h;
-        fused_operands_bf16(Vh, Qp, RP, Vu_h, Vy_h);
-        Vu = ensure(c, "Vu", Vu_h.size() * 2);
-        Vy = ensure(c, "Vy", Vy_h.size() * 2);
-        HIPC(c, hipMemcpy(Vu, Vu_h.data(), Vu_h.size() * 2, hipMemcpyHostToDevice));
-        HIPC(c, hipMemcpy(Vy, Vy_h.data(), Vy_h.size() * 2, hipMemcpyHostToDevice));
+        std::vector<uint16_t> Vop;
+        fused_operands_bf16(Vh, Qp, RP, Vop);
+        Vu = ensure(c, "Vop", Vop.size() * 2);
+        HIPC(c, hipMemcpy(Vu, Vop.data(), Vop.size() * 2, hipMemcpyHostToDevice));
     } else if (pl.fused) {
-        std::vector<double> Vu_h, Vy_h;
-        fused_operands(Vh, Qp, RP, pl.mode == MODE_FP64, Vu_h, Vy_h);
-        Vu = ensure(c, "Vu", Vu_h.size() * esz);
-        Vy = ensure(c, "Vy", Vy_h.size() * esz);
+        std::vector<double> Vop;
+        fused_operands(Vh, Qp, RP, pl.mode == MODE_FP64, Vop);
+        Vu = ensure(c, "Vop", Vop.size() * esz);
         if (pl.mode == MODE_FP64) {
-            HIPC(c, hipMemcpy(Vu, Vu_h.data(), Vu_h.size() * 8, hipMemcpyHostToDevice));
-            HIPC(c, hipMemcpy(Vy, Vy_h.data(), Vy_h.size() * 8, hipMemcpyHostToDevice));
+            HIPC(c, hipMemcpy(Vu, Vop.data(), Vop.size() * 8, hipMemcpyHostToDevice));
         } else {
-            std::vector<float> a(Vu_h.begin(), Vu_h.end()), b(Vy_h.begin(), Vy_h.end());
-            HIPC(c, hipMemcpy(Vu, a.data(), a.size() * 4, hipMemcpyHostToDevice));
-            HIPC(c, hipMemcpy(Vy, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+            std::vector<float> f(Vop.begin(), Vop.end());
+            HIPC(c, hipMemcpy(Vu, f.data(), f.size() * 4, hipMemcpyHostToDevice));
         }
     }
     double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr;
@@ -355,7 +347,14 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
             a.dout = auxB;                                        // d^K
         }
         if (pl.fused) {
+            // f and d are not part of the fused pass; bracket the last two iterations
+            const size_t cnt = (size_t)Qp * N;
+            if (aux && k == iters - 2) launch_aux_pre(pl.mode, a, auxA, nullptr, nullptr, s);
+            if (aux && k == iters - 1)   // auxB = z + u, auxA: d^{K-1} -> f^K (d^0 = 0 if K = 1)
+                launch_aux_pre(pl.mode, a, auxB, auxA, iters >= 2 ? auxA : nullptr, s);
             launch_iter_fused(pl.mode, a, s);
+            if (aux && k == iters - 2) launch_aux_post(pl.mode, auxA, a.znew, pl.beta, cnt, s);
+            if (aux && k == iters - 1) launch_aux_post(pl.mode, auxB, a.znew, pl.beta, cnt, s);
         } else {
             launch_update_unfused(pl.mode, a, s);
             launch_projw_unfused(pl.mode, a, s);

@@ -21,14 +21,22 @@ namespace ssmap {
 
 namespace {
 
-// A holds n vectors of length L (row-major n x L). G (n x n, row-major)
-// accumulates the rotations: on exit A = G^T A0 with mutually orthogonal rows.
+// A holds n vectors of length L (row-major n x L). Gt (n x n, row-major)
+// accumulates the rotations transposed: on exit A = Gt A0 with mutually
+// orthogonal rows, i.e. A0 = Gt^T A.
 void jacobi_rows(std::vector<double> &A, int n, int L, std::vector<double> &G) {
     G.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) G[(size_t)i * n + i] = 1.0;
     if (n < 2) return;
     const int m = (n % 2) ? n + 1 : n;          // players, one bye if n is odd
-    const double tol = 1e-15;
+    // pairs count as orthogonal once |a_i . a_j| <= sqrt(L) eps ||a_i|| ||a_j||;
+    // rows whose norm is at the rounding level of ||A||_F (below 4 eps ||A||_F)
+    // are numerically zero and are left alone
+    const double eps = 2.220446049250313e-16;
+    const double tol = std::sqrt((double)L) * eps;
+    double fro2 = 0.0;
+    for (double v : A) fro2 += v * v;
+    const double negligible2 = fro2 * (4 * eps) * (4 * eps);
     unsigned hw = std::thread::hardware_concurrency();
     int nthreads = (int)std::min<unsigned>(hw ? hw : 1, 16);
     const double work = (double)n * n * L;
@@ -51,6 +59,7 @@ void jacobi_rows(std::vector<double> &A, int n, int L, std::vector<double> &G) {
             beta += aj[k] * aj[k];
             gamma += ai[k] * aj[k];
         }
+        if (alpha <= negligible2 || beta <= negligible2) return false;
         if (gamma == 0.0 || !(std::fabs(gamma) > tol * std::sqrt(alpha * beta))) return false;
         const double zeta = (beta - alpha) / (2.0 * gamma);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
@@ -61,11 +70,11 @@ void jacobi_rows(std::vector<double> &A, int n, int L, std::vector<double> &G) {
             ai[k] = c * x - s * y;
             aj[k] = s * x + c * y;
         }
-        for (int k = 0; k < n; ++k) {          // columns i, j of G
-            double *gr = &G[(size_t)k * n];
-            const double x = gr[i], y = gr[j];
-            gr[i] = c * x - s * y;
-            gr[j] = s * x + c * y;
+        double *gi = &G[(size_t)i * n], *gj = &G[(size_t)j * n];   // rows i, j of Gt
+        for (int k = 0; k < n; ++k) {
+            const double x = gi[k], y = gj[k];
+            gi[k] = c * x - s * y;
+            gj[k] = s * x + c * y;
         }
         return true;
     };
@@ -162,10 +171,10 @@ void thin_svd(const double *K, int P, int Q, std::vector<double> &U,
         // normalised orthogonal vector (length L) and the rotation column (length n)
         if (rows) {
             for (int q = 0; q < Q; ++q) V[(size_t)q * n + c] = A[(size_t)i * L + q] * inv;
-            for (int p = 0; p < P; ++p) U[(size_t)p * n + c] = G[(size_t)p * n + i];
+            for (int p = 0; p < P; ++p) U[(size_t)p * n + c] = G[(size_t)i * n + p];
         } else {
             for (int p = 0; p < P; ++p) U[(size_t)p * n + c] = A[(size_t)i * L + p] * inv;
-            for (int q = 0; q < Q; ++q) V[(size_t)q * n + c] = G[(size_t)q * n + i];
+            for (int q = 0; q < Q; ++q) V[(size_t)q * n + c] = G[(size_t)i * n + q];
         }
     }
 }
