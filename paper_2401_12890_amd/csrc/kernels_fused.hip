@@ -407,6 +407,282 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variant with the chunk staged by direct buffer->LDS loads (used for bf16x3;
+// it also compiles for float32).
+//
+// The brick's halo box (SX x SY x SZ voxel slots, 64 B each) is copied into
+// LDS by buffer_load ... lds, which writes lane k's 16 bytes to entry k of a
+// 1 KB run; no registers hold the data in flight. Two LDS buffers alternate:
+// chunk c+1 lands in one while chunk c is read from the other, so a single
+// barrier per chunk suffices. Inside a slot the four 16-byte quads are
+// XOR-swizzled by bits 2..3 of the slot index, so the sixteen lanes of a row
+// (sixteen consecutive slots, one quad) hit sixteen distinct bank groups.
+// z^{k+1} of chunk c is written at the start of chunk c+1 (deferred), so the
+// wait for chunk c+1's loads never stalls on stores just issued.
+template <int TY, int TZ> struct Box {
+    static constexpr int SX = TX + 2, SY = TY + 2, SZ = TZ + 2;
+    static constexpr int NS = SX * SY * SZ;       // slots
+    static constexpr int NE = NS * 4;             // 16-byte entries
+    static constexpr int NG = (NE + 63) / 64;     // 64-entry load groups
+};
+
+__device__ __forceinline__ int swz(int slot) { return (slot >> 2) & 3; }
+
+// 16 bytes per lane from a buffer straight into LDS: lane k fills the k-th
+// 16-byte entry after `lds` (wave-uniform base).
+__device__ __forceinline__ void lds_dma16(__amdgpu_buffer_rsrc_t r, void *lds, unsigned voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds, 16,
+                                             voff, 0, 0, 0);
+}
+
+template <int MODE, int RB, int KSU, int TY, int TZ>
+__global__ void __launch_bounds__(NT, 1)
+k_fused_dma(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
+    static_assert(MODE != MODE_FP64, "float64 uses the register-staged kernel");
+    using F = FT<MODE>;
+    using V4 = v4f;
+    using BX = Box<TY, TZ>;
+    constexpr bool BF = MODE == MODE_BF16X3;
+    constexpr int NW = NT / 64;
+    constexpr int NB = TY * TZ;
+    constexpr int BPW = NB / NW;
+    constexpr int GPW = (BX::NG + NW - 1) / NW;   // load groups per wave
+    constexpr int VB = VopSize<MODE, RB>::bytes;
+    constexpr int VG = VB / 1024;                 // V load groups (waves 0 .. VG-1)
+    constexpr int KS = 4 * RB;
+    static_assert(NB % NW == 0, "brick rows must split over the waves");
+    static_assert(VB % 1024 == 0 && VG <= NW, "V block must be whole load groups");
+    static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
+
+    __shared__ uint4 zbuf[2][BX::NG * 64];
+    __shared__ uint4 vbuf[2][VB / 16];
+
+    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
+    const int ntiles = tiles_x * tiles_y * tiles_z;
+    int tile = blockIdx.x;
+    if ((ntiles & 7) == 0) {             // keep neighbouring bricks on one XCD (shared L2)
+        const int per = ntiles >> 3;
+        tile = (tile & 7) * per + (tile >> 3);
+    }
+    const int tx = tile % tiles_x;
+    const int ty = (tile / tiles_x) % tiles_y;
+    const int tz = tile / (tiles_x * tiles_y);
+    const int64_t x0 = (int64_t)tx * TX, y0 = (int64_t)ty * TY, z0 = (int64_t)tz * TZ;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int j = lane & 15;
+    const int i4 = lane >> 4;
+
+    const float tau = (float)a.tau, lam2 = (float)a.lam2, beta = (float)a.beta;
+    const size_t chunk_elems = (size_t)N * QC;
+    const unsigned chunk_bytes = (unsigned)(chunk_elems * sizeof(float));
+
+    // ---- load descriptors: entry e = 64 g + lane of the box -> slot e/4, stored
+    //      position e%4 holds quad (e%4) ^ swz(slot) of that voxel's chunk
+    unsigned voff[GPW];
+#pragma unroll
+    for (int i = 0; i < GPW; ++i) {
+        const int e = 64 * (wave + NW * i) + lane;
+        const int sl = e >> 2;
+        voff[i] = OOB;
+        if (sl < BX::NS) {
+            const int q = (e & 3) ^ swz(sl);
+            const int sx = sl % BX::SX, sy = (sl / BX::SX) % BX::SY, sz = sl / (BX::SX * BX::SY);
+            const int64_t gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
+            // edge and corner slots of the halo box are never read: leave them unloaded
+            const int rim = (sx == 0 || sx == BX::SX - 1) + (sy == 0 || sy == BX::SY - 1) +
+                            (sz == 0 || sz == BX::SZ - 1);
+            if (rim < 2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                voff[i] = (unsigned)(((gx + nx * (gy + ny * gz)) * QC + 4 * q) * sizeof(float));
+        }
+    }
+    const __amdgpu_buffer_rsrc_t vrs = rsrc(a.Vu, (unsigned)(a.nchunk * VB));
+    auto issue = [&](int c) {
+        const int b = c & 1;
+        const __amdgpu_buffer_rsrc_t zr = rsrc((const float *)a.z + (size_t)c * chunk_elems, chunk_bytes);
+#pragma unroll
+        for (int i = 0; i < GPW; ++i) {
+            const int g = wave + NW * i;
+            if (g < BX::NG) lds_dma16(zr, &zbuf[b][64 * g], voff[i]);
+        }
+        if (wave < VG)
+            lds_dma16(vrs, &vbuf[b][64 * wave], (unsigned)(c * VB + 1024 * wave + 16 * lane));
+    };
+
+    // ---- per-row voxel coordinates and LDS byte addresses of the 7-point stencil
+    int64_t nvox[BPW];
+    bool valid[BPW];
+    float deg[BPW];
+    unsigned soff[BPW];
+    int sa[BPW][7];                      // byte offsets inside a z buffer
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int row = wave + NW * b;
+        const int by = row % TY, bz = row / TY;
+        const int64_t gx = x0 + j, gy = y0 + by, gz = z0 + bz;
+        valid[b] = gx < nx && gy < ny && gz < nz;
+        nvox[b] = valid[b] ? gx + nx * (gy + ny * gz) : 0;
+        deg[b] = (float)((gx > 0) + (gx + 1 < nx) + (gy > 0) + (gy + 1 < ny) + (gz > 0) + (gz + 1 < nz));
+        soff[b] = valid[b] ? (unsigned)((nvox[b] * QC + 4 * i4) * sizeof(float)) : OOB;
+        const int s0 = (j + 1) + BX::SX * ((by + 1) + BX::SY * (bz + 1));
+        const int nb[7] = {s0, s0 - 1, s0 + 1, s0 - BX::SX, s0 + BX::SX, s0 - BX::SX * BX::SY,
+                           s0 + BX::SX * BX::SY};
+#pragma unroll
+        for (int k = 0; k < 7; ++k) sa[b][k] = 64 * nb[k] + 16 * (i4 ^ swz(nb[k]));
+    }
+
+    // ---- u operand (see k_fused)
+    const float *wsrc = (const float *)a.w;
+    float wop[BPW][BF ? 1 : KSU];
+    v8bf whi[BF ? BPW : 1], wlo[BF ? BPW : 1];
+    V4 yacc[BPW][RB];
+    V4 zkeep[BPW];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        if constexpr (BF) {
+            v4u h = v4u{0, 0, 0, 0}, l = v4u{0, 0, 0, 0};
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const int r = 8 * i4 + jj;
+                const float v = r < a.RP ? wsrc[(size_t)r * N + nvox[b]] : 0.0f;
+                const unsigned hb = bf16_bits(v);
+                const unsigned lb = bf16_bits(v - bf16_val(hb));
+                h[jj >> 1] |= hb << (16 * (jj & 1));
+                l[jj >> 1] |= lb << (16 * (jj & 1));
+            }
+            whi[b] = __builtin_bit_cast(v8bf, h);
+            wlo[b] = __builtin_bit_cast(v8bf, l);
+        } else {
+#pragma unroll
+            for (int s = 0; s < KSU; ++s) wop[b][s] = wsrc[(size_t)(4 * s + i4) * N + nvox[b]];
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) yacc[b][rb] = V4{0, 0, 0, 0};
+        zkeep[b] = V4{0, 0, 0, 0};
+    }
+
+    issue(0);
+    for (int c = 0; c < a.nchunk; ++c) {
+        // this wave's loads of chunk c (and its stores of chunk c-1) are done;
+        // the barrier makes every wave's part visible and frees the other buffer
+        __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0)
+        __syncthreads();
+        if (c > 0) {                                  // deferred z^{k+1} of chunk c-1
+            const __amdgpu_buffer_rsrc_t zo =
+                rsrc((float *)a.znew + (size_t)(c - 1) * chunk_elems, chunk_bytes);
+#pragma unroll
+            for (int b = 0; b < BPW; ++b) Buf<float, v4f>::store(zkeep[b], zo, soff[b]);
+        }
+        if (c + 1 < a.nchunk) issue(c + 1);
+        const int bsel = c & 1;
+        const char *Z = (const char *)&zbuf[bsel][0];
+
+        float vu[BF ? 1 : KSU];
+        float vy[BF ? 1 : RB][4];
+        v8bf vuh, vul;
+        v4s vyh[RB], vyl[RB];
+        if constexpr (BF) {
+            const v4u *U8 = (const v4u *)&vbuf[bsel][0];
+            vuh = __builtin_bit_cast(v8bf, U8[lane]);
+            vul = __builtin_bit_cast(v8bf, U8[64 + lane]);
+            const v2u *Y4 = (const v2u *)((const char *)&vbuf[bsel][0] + 2048);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                vyh[rb] = __builtin_bit_cast(v4s, Y4[(rb * 2 + 0) * 64 + lane]);
+                vyl[rb] = __builtin_bit_cast(v4s, Y4[(rb * 2 + 1) * 64 + lane]);
+            }
+        } else {
+            const float *VT = (const float *)&vbuf[bsel][0];
+#pragma unroll
+            for (int s = 0; s < KSU; ++s) vu[s] = VT[s * 64 + lane];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) vy[rb][i] = VT[(KS + rb * 4 + i) * 64 + lane];
+        }
+
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            V4 u = V4{0, 0, 0, 0};
+            if constexpr (BF) {
+                u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vul, whi[b], u, 0, 0, 0);
+                u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vuh, wlo[b], u, 0, 0, 0);
+                u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vuh, whi[b], u, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int s = 0; s < KSU; ++s) u = F::mfma(vu[s], wop[b][s], u);
+            }
+            const V4 zc = *(const V4 *)(Z + sa[b][0]);
+            const V4 nsum = (*(const V4 *)(Z + sa[b][1]) + *(const V4 *)(Z + sa[b][2])) +
+                            (*(const V4 *)(Z + sa[b][3]) + *(const V4 *)(Z + sa[b][4])) +
+                            (*(const V4 *)(Z + sa[b][5]) + *(const V4 *)(Z + sa[b][6]));
+            const V4 lap = deg[b] * zc - nsum;
+            V4 zn = zc - tau * (lam2 * lap - beta * u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zn[i] = zn[i] > 0.0f ? zn[i] : 0.0f;
+            zkeep[b] = zn;
+            if constexpr (BF) {
+                v4s zh, zl;
+                split4(zn, zh, zl);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyl[rb], zh, yacc[b][rb], 0, 0, 0);
+                    yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyh[rb], zl, yacc[b][rb], 0, 0, 0);
+                    yacc[b][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vyh[rb], zh, yacc[b][rb], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        yacc[b][rb] = F::mfma(vy[rb][i], zn[i], yacc[b][rb]);
+            }
+        }
+    }
+    {
+        const __amdgpu_buffer_rsrc_t zo =
+            rsrc((float *)a.znew + (size_t)(a.nchunk - 1) * chunk_elems, chunk_bytes);
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) Buf<float, v4f>::store(zkeep[b], zo, soff[b]);
+    }
+
+    // ---- r-vector recursion: gather, then update, then store
+    const float *ah = (const float *)a.ah;
+    const float *bc = (const float *)a.bcoef;
+    const unsigned rbytes = (unsigned)((size_t)a.RP * N * sizeof(float));
+    const __amdgpu_buffer_rsrc_t wr = rsrc(a.w, rbytes), yr = rsrc(a.y, rbytes);
+    const float *yold = (const float *)a.y;
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        float ahv[RB][4], yov[RB][4], wov[RB][4], bcv[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rb + 4 * i4 + i;
+                const size_t o = (size_t)r * N + nvox[b];
+                ahv[rb][i] = ah[o];
+                yov[rb][i] = yold[o];
+                wov[rb][i] = wsrc[o];
+                bcv[rb][i] = bc[r];
+            }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rb + 4 * i4 + i;
+                const unsigned ob = valid[b] ? (unsigned)(((size_t)r * N + nvox[b]) * sizeof(float)) : OOB;
+                const float yn = yacc[b][rb][i];
+                const float wn = ahv[rb][i] - bcv[rb][i] * (2.0f * yn - yov[rb][i] - wov[rb][i]);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, wn), wr, ob, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, yn), yr, ob, 0, 0);
+            }
+    }
+}
+
 struct Shape {
     int ty, tz;
 };
@@ -422,8 +698,14 @@ void launch_t(const IterArgs &a, hipStream_t s) {
     const int tiles_x = (int)((a.g.nx + TX - 1) / TX);
     const int tiles_y = (int)((a.g.ny + TY - 1) / TY);
     const int tiles_z = (int)((a.g.nz + TZ - 1) / TZ);
-    hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(tiles_x * tiles_y * tiles_z), dim3(NT),
-                       0, s, a, tiles_x, tiles_y, tiles_z);
+    // float64 and float32 stage through registers (measured faster for float32),
+    // bf16x3 through direct LDS loads
+    if constexpr (MODE == MODE_BF16X3)
+        hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(tiles_x * tiles_y * tiles_z),
+                           dim3(NT), 0, s, a, tiles_x, tiles_y, tiles_z);
+    else
+        hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(tiles_x * tiles_y * tiles_z),
+                           dim3(NT), 0, s, a, tiles_x, tiles_y, tiles_z);
 }
 
 template <int MODE, int RB, int KSU>
