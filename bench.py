@@ -92,6 +92,31 @@ def sampled_parity(mp, prob, prec, kernel, rank, xi, k=4, nsamp=12, seed=0):
     return worst, len(pts)
 
 
+def kernel_source_digest():
+    """sha256 of the fused-kernel source: counter-derived traffic is only
+    reported while it matches the source the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2401_12890_amd", "csrc", "kernels_fused.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, KiB per dispatch, scaled by the
+    calibration factor measured on a copy kernel of known size), or None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + \
+        rec["write_kib_per_dispatch"] * rec["write_scale"]
+    return kib * 1024.0
+
+
 def cpu_baseline(name, seconds_hint=20.0):
     """The FP64 oracle, untuned, on a bounded sample of the same workload."""
     import numpy as np
@@ -188,8 +213,9 @@ def main():
     alg = alg_bytes_per_voxel_iter(prob.Q, r, wbytes) * prob.N
     achieved = alg / (per_launch_ms / 1e3) / 1e9
     kern_name = "ssmap_iter_fused" if st["kernel"] == 2 else "k_update+k_projw (unfused)"
+    traffic = measured_traffic(args.workload) if args.kernel in ("auto", "fused") else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kern_name, "avg_launch_ms": round(per_launch_ms, 5),
                 "alg_bytes_per_launch": alg}
 

@@ -43,6 +43,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # stand-alone read+write streaming reference used by the roofline notes
+    exe = os.path.join(HERE, "copy_ceiling")
+    cmd = [HIPCC] + DEVICE_FLAGS + ["-O3", "-std=c++20", os.path.join(CSRC, "copy_ceiling.hip"),
+                                    "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
     return LIB
 
 
