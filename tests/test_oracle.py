@@ -325,3 +325,46 @@ def test_dfcs_history_monotone_objective():
     J = [h[1] for h in out["hist"]]
     assert J[-1] < J[0]
     assert len(out["hist"]) == 7
+
+
+def test_fullsize_golden_values_come_from_the_oracle():
+    """The stored full-size sample values (used by the benchmark) are what the
+    oracle gives on crops: recompute two of them."""
+    import importlib.util
+    path = os.path.join(GOLDEN, "make_fullsize_golden.py")
+    spec = importlib.util.spec_from_file_location("make_fullsize_golden", path)
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    with open(os.path.join(GOLDEN, "fullsize_c2.json")) as fh:
+        gold = json.load(fh)
+    prob = synth.generate("c2")
+    g = np.random.Generator(np.random.PCG64(gold["projection_seed"])).standard_normal(prob.Q)
+    nx, ny, nz = prob.grid
+    h = gold["iters"] + 1
+    for smp in gold["samples"][:2]:
+        x, y, z = smp["voxel"]
+        x0, x1 = max(0, x - h), min(nx, x + h + 1)
+        y0, y1 = max(0, y - h), min(ny, y + h + 1)
+        z0, z1 = max(0, z - h), min(nz, z + h + 1)
+        idx = [xx + nx * (yy + ny * zz) for zz in range(z0, z1) for yy in range(y0, y1)
+               for xx in range(x0, x1)]
+        sub = oracle.ladmm(prob.K, prob.m[idx], (x1 - x0, y1 - y0, z1 - z0), prob.lam, prob.beta,
+                           gold["iters"], rank=gold["rank"], xi=gold["xi_p"])
+        zr = sub["z"][(x - x0) + (x1 - x0) * ((y - y0) + (y1 - y0) * (z - z0))]
+        assert np.linalg.norm(zr) == pytest.approx(smp["norm"], rel=1e-12)
+        assert zr @ g == pytest.approx(smp["proj"], rel=1e-10, abs=1e-14)
+    assert [s["voxel"] for s in gold["samples"]] == [list(p) for p in mk.points(prob.grid)]
+
+
+def test_bench_uses_the_oracle_only_in_its_cpu_baseline():
+    import ast
+    src = open(os.path.join(os.path.dirname(GOLDEN), "..", "bench.py")).read()
+    tree = ast.parse(src)
+    users = set()
+    for fn in [n for n in ast.walk(tree) if isinstance(n, ast.FunctionDef)]:
+        for node in ast.walk(fn):
+            if isinstance(node, (ast.Import, ast.ImportFrom)):
+                names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
+                if any(nm.split(".")[0] == "oracle" for nm in names):
+                    users.add(fn.name)
+    assert users == {"cpu_baseline"}
