@@ -31,6 +31,8 @@ WORKLOADS = {
     "c2": "3-D diffusion-relaxation 128x128x64, P=60, Q=1600 (40x40), fp32, 300 iters",
     "c3": "3-D T1-T2 fingerprinting-like 96x96x32, P=1000, Q=1024 (32x32), bf16x3, 300 iters",
     "c1": "2-D diffusion-relaxation 32x32, P=30, Q=100 (10x10), fp64, 500 iters",
+    "c4": "64 uneven 2-D slices (sides 48..256), P in {30,60}, Q in {100,400,1600}, one batch, "
+          "200 iters",
 }
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 state)"}
 
@@ -142,6 +144,100 @@ def cpu_baseline(name, seconds_hint=20.0):
                       f"{np.__version__}, {platform.processor() or platform.machine()}"}
 
 
+def cpu_baseline_batch(sub):
+    """The FP64 oracle, untuned, on a few slices of the batched workload."""
+    import oracle
+    t0 = time.perf_counter()
+    for p in sub:
+        oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, 1)
+    one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for p in sub:
+        oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, 4)
+    four = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": sum(p.N for p in sub) * 3 / max(four - one, 1e-9),
+            "unit": "voxel-iterations/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"the first {len(sub)} slices ({sum(p.N for p in sub)} voxels), 3 float64 "
+                      f"iterations after one"}
+
+
+def bench_batch(args):
+    """Batched uneven slices: one batch solve (all slices, shared launches,
+    autotuned bricks) per step, in bf16x3 and in float32, against the same
+    slices solved one after another in float32."""
+    import numpy as np
+    import torch
+
+    from paper_2401_12890_amd import _ffi, synth
+    log("generating 64 slices")
+    probs = synth.generate_batch(iters=args.iters)
+    iters = probs[0].iters
+    Ntot = sum(p.N for p in probs)
+    Ms = [torch.tensor(p.m, dtype=torch.float32, device="cuda") for p in probs]
+    Fs = [torch.empty((p.N, p.Q), dtype=torch.float32, device="cuda") for p in probs]
+    bm = _ffi.BatchMapper([p.K for p in probs], [p.grid for p in probs])
+    lams, betas = [p.lam for p in probs], [p.beta for p in probs]
+    torch.cuda.synchronize()
+    out = {}
+    for prec in ("bf16x3", "fp32"):
+        bm.solve_torch(Ms, lams, betas, iters, Fs=Fs, precision=prec, autotune=True)  # tune + warm
+        torch.cuda.synchronize()
+        tuned = bm.stats()["classes"]
+        lat, loop = [], []
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            bm.solve_torch(Ms, lams, betas, iters, Fs=Fs, precision=prec)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            loop.append(bm.stats()["iterate_ms"])
+            log(f"{prec} batch step {k}: {lat[-1]:.1f} ms (loop {loop[-1]:.1f} ms)")
+        out[prec] = dict(ms=sum(lat) / len(lat), loop_ms=sum(loop) / len(loop), lat=lat,
+                         classes=tuned, ranks=None)
+    # the same slices one after another (float32, default bricks)
+    seq_ms = 0.0
+    ranks = []
+    mps = [_ffi.Mapper(p.K, p.grid) for p in probs]
+    for mp, p, M, F in zip(mps, probs, Ms, Fs):               # warm
+        mp.solve_torch(M, p.lam, p.beta, iters, F=F, precision="fp32")
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for mp, p, M, F in zip(mps, probs, Ms, Fs):
+        mp.solve_torch(M, p.lam, p.beta, iters, F=F, precision="fp32")
+        ranks.append(mp.stats()["rank"])
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - ts) * 1e3
+    for mp in mps:
+        mp.close()
+    bm.close()
+    alg = sum((2 * p.Q + 5 * r) * 4 * p.N for p, r in zip(probs, ranks))
+    per_launch_ms = out["bf16x3"]["loop_ms"] / iters
+    achieved = alg / (per_launch_ms / 1e3) / 1e9
+    value = Ntot * iters / (out["bf16x3"]["ms"] / 1e3)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batch(probs[:2])
+    line = {
+        "metric": METRIC, "value": value, "unit": "voxel-iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": out["bf16x3"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3 (f32 state)", "data": "synthetic (seeded generator, no dataset)",
+        "config": {"workload": WORKLOADS["c4"], "slices": len(probs), "voxels": Ntot,
+                   "iters": iters, "classes_bf16x3": out["bf16x3"]["classes"],
+                   "classes_fp32": out["fp32"]["classes"]},
+        "p50_ms": percentile(out["bf16x3"]["lat"], 50), "p99_ms": percentile(out["bf16x3"]["lat"], 99),
+        "batched_fp32_voxel_iter_per_s": Ntot * iters / (out["fp32"]["ms"] / 1e3),
+        "sequential_fp32_voxel_iter_per_s": Ntot * iters / (seq_ms / 1e3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "shared fused launches (bf16x3)", "avg_launch_ms": per_launch_ms,
+                     "alg_bytes_per_launch": alg},
+        "cpu_baseline": cpu, "parity": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +262,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return bench_batch(args)
     log("generating workload", args.workload)
     prob = synth.generate(args.workload, iters=args.iters)
     prec = args.precision or prob.precision

@@ -166,6 +166,68 @@ void ssmap_destroy(ssmap_ctx *ctx);
 /* Library version string. */
 const char *ssmap_version(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent problems (each with its own dictionary, grid and
+ * data, e.g. the slices of a study or the B1-binned dictionaries of the
+ * paper's MRF experiment, Sec. IV-D) solved together. Problems of one class
+ * (precision, padded rank, planar or volumetric grid) share each fused
+ * launch: one launch walks the bricks of all of them, so many small problems
+ * fill the GPU. Each problem's iterates are exactly those of ssmap_solve on
+ * it alone (same kernels, same arithmetic order).
+ * ---------------------------------------------------------------------- */
+typedef struct ssmap_batch ssmap_batch;
+
+enum {
+    SSMAP_AUTOTUNE = 2      /* steps.flags: choose each class's brick shape by timing */
+};
+
+#define SSMAP_MAX_CLASSES 16
+
+typedef struct {
+    int njobs;
+    int nclasses;           /* shared-launch classes of the last solve               */
+    int solo_jobs;          /* jobs without a fused kernel (run one launch each)      */
+    int iters;
+    double voxels;          /* sum of N over the jobs                                */
+    double project_ms;      /* projections of all jobs                               */
+    double iterate_ms;      /* the iteration loop                                    */
+    double output_ms;
+    double autotune_ms;     /* shape search (0 when not requested)                   */
+    int class_precision[SSMAP_MAX_CLASSES];
+    int class_rank_padded[SSMAP_MAX_CLASSES];
+    int class_jobs[SSMAP_MAX_CLASSES];
+    int class_bricks[SSMAP_MAX_CLASSES];
+    int class_brick_y[SSMAP_MAX_CLASSES];    /* chosen brick: 16 x brick_y x brick_z  */
+    int class_brick_z[SSMAP_MAX_CLASSES];
+} ssmap_batch_stats;
+
+/* Factor `njobs` dictionaries (as ssmap_create, one context per job).
+ *   K[j] : P[j]*Q[j] float64 row-major;  grids : njobs*3 int64 {nx, ny, nz}.
+ * All arrays are caller-owned and copied. */
+ssmap_status ssmap_batch_create(int njobs, const double *const *K, const int *P, const int *Q,
+                                const int64_t *grids, ssmap_batch **out);
+
+/* Solve every job for `iters` iterations on device buffers, ordered on
+ * `hip_stream`. dM[j] / dF[j] as in ssmap_solve_device for job j; lambda and
+ * steps are per job (njobs entries). steps[j].check_every must be 0 and
+ * SSMAP_KEEP_AUX unset (use the single-problem entry points for those).
+ * SSMAP_AUTOTUNE in any job's flags turns the shape search on. */
+ssmap_status ssmap_batch_solve_device(ssmap_batch *b, const void *const *dM, const double *lambda,
+                                      const ssmap_steps *steps, int iters, void *const *dF,
+                                      void *hip_stream);
+
+/* Host-buffer variant (float64 M[j], F_out[j]); blocks until done. */
+ssmap_status ssmap_batch_solve(ssmap_batch *b, const double *const *M, const double *lambda,
+                               const ssmap_steps *steps, int iters, double *const *F_out);
+
+ssmap_status ssmap_batch_get_stats(const ssmap_batch *b, ssmap_batch_stats *out);
+
+/* Message for the last failure on b (or of the last failed ssmap_batch_create when b is NULL). */
+const char *ssmap_batch_last_error(const ssmap_batch *b);
+
+/* Release the batch, its contexts and device memory. NULL is a no-op. */
+void ssmap_batch_destroy(ssmap_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,11 @@ MAX_HIST = 512
 
 EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_get_aux",
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
-           "ssmap_destroy", "ssmap_version"]
+           "ssmap_destroy", "ssmap_version",
+           "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
+           "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy"]
+SSMAP_AUTOTUNE = 2
+MAX_CLASSES = 16
 
 
 class Steps(ctypes.Structure):
@@ -49,6 +53,19 @@ class Stats(ctypes.Structure):
                 ("hist_objective", ctypes.c_double * MAX_HIST),
                 ("hist_dual", ctypes.c_double * MAX_HIST),
                 ("hist_znorm", ctypes.c_double * MAX_HIST)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("njobs", ctypes.c_int), ("nclasses", ctypes.c_int), ("solo_jobs", ctypes.c_int),
+                ("iters", ctypes.c_int), ("voxels", ctypes.c_double),
+                ("project_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
+                ("output_ms", ctypes.c_double), ("autotune_ms", ctypes.c_double),
+                ("class_precision", ctypes.c_int * MAX_CLASSES),
+                ("class_rank_padded", ctypes.c_int * MAX_CLASSES),
+                ("class_jobs", ctypes.c_int * MAX_CLASSES),
+                ("class_bricks", ctypes.c_int * MAX_CLASSES),
+                ("class_brick_y", ctypes.c_int * MAX_CLASSES),
+                ("class_brick_z", ctypes.c_int * MAX_CLASSES)]
 
 
 class SsmapError(RuntimeError):
@@ -88,6 +105,21 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_destroy.restype = None
     lib.ssmap_version.argtypes = []
     lib.ssmap_version.restype = ctypes.c_char_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.ssmap_batch_create.argtypes = [ip, pp, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(vp)]
+    lib.ssmap_batch_create.restype = ip
+    lib.ssmap_batch_solve.argtypes = [vp, pp, dp, ctypes.POINTER(Steps), ip, pp]
+    lib.ssmap_batch_solve.restype = ip
+    lib.ssmap_batch_solve_device.argtypes = [vp, pp, dp, ctypes.POINTER(Steps), ip, pp, vp]
+    lib.ssmap_batch_solve_device.restype = ip
+    lib.ssmap_batch_get_stats.argtypes = [vp, ctypes.POINTER(BatchStats)]
+    lib.ssmap_batch_get_stats.restype = ip
+    lib.ssmap_batch_last_error.argtypes = [vp]
+    lib.ssmap_batch_last_error.restype = ctypes.c_char_p
+    lib.ssmap_batch_destroy.argtypes = [vp]
+    lib.ssmap_batch_destroy.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -98,10 +130,11 @@ def _dptr(a: np.ndarray):
 
 
 def make_steps(beta, xi_p=0.0, rank=0, precision="fp64", check_every=0, keep_aux=False,
-               kernel="auto") -> Steps:
+               kernel="auto", autotune=False) -> Steps:
+    flags = (SSMAP_KEEP_AUX if keep_aux else 0) | (SSMAP_AUTOTUNE if autotune else 0)
     return Steps(beta=float(beta), xi_p=float(xi_p), rank=int(rank),
                  precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
-                 check_every=int(check_every), flags=SSMAP_KEEP_AUX if keep_aux else 0,
+                 check_every=int(check_every), flags=flags,
                  kernel=KERNELS[kernel] if isinstance(kernel, str) else int(kernel), reserved=0)
 
 
@@ -223,6 +256,123 @@ class Mapper:
         if self.ctx:
             ssmap_destroy(self.ctx)
             self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ batches
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*ptrs)
+
+
+def ssmap_batch_create(Ks, grids) -> int:
+    lib = load()
+    Ks = [np.ascontiguousarray(K, dtype=np.float64) for K in Ks]
+    n = len(Ks)
+    P = (ctypes.c_int * n)(*[K.shape[0] for K in Ks])
+    Q = (ctypes.c_int * n)(*[K.shape[1] for K in Ks])
+    g = (ctypes.c_int64 * (3 * n))(*[int(v) for gr in grids for v in gr])
+    out = ctypes.c_void_p()
+    st = lib.ssmap_batch_create(n, _ptr_array([K.ctypes.data for K in Ks]), P, Q, g,
+                                ctypes.byref(out))
+    if st != SSMAP_OK:
+        raise SsmapError(st, lib.ssmap_batch_last_error(None).decode())
+    return out.value
+
+
+def _bcheck(b, st):
+    if st != SSMAP_OK:
+        raise SsmapError(st, load().ssmap_batch_last_error(b).decode())
+
+
+def ssmap_batch_solve(b, Ms, lams, steps_list, iters, shapes):
+    """Host solve; shapes[j] = (N_j, Q_j). Returns a list of (N_j, Q_j) maps."""
+    Ms = [np.ascontiguousarray(M, dtype=np.float64) for M in Ms]
+    Fs = [np.empty(sh, dtype=np.float64) for sh in shapes]
+    n = len(Ms)
+    steps = (Steps * n)(*steps_list)
+    lam = (ctypes.c_double * n)(*[float(x) for x in lams])
+    _bcheck(b, load().ssmap_batch_solve(b, _ptr_array([M.ctypes.data for M in Ms]), lam, steps,
+                                        int(iters), _ptr_array([F.ctypes.data for F in Fs])))
+    return Fs
+
+
+def ssmap_batch_solve_device(b, dMs, lams, steps_list, iters, dFs, stream=0):
+    n = len(dMs)
+    steps = (Steps * n)(*steps_list)
+    lam = (ctypes.c_double * n)(*[float(x) for x in lams])
+    _bcheck(b, load().ssmap_batch_solve_device(b, _ptr_array(dMs), lam, steps, int(iters),
+                                               _ptr_array(dFs), ctypes.c_void_p(stream)))
+
+
+def ssmap_batch_get_stats(b) -> dict:
+    s = BatchStats()
+    _bcheck(b, load().ssmap_batch_get_stats(b, ctypes.byref(s)))
+    c = s.nclasses
+    return dict(njobs=s.njobs, nclasses=c, solo_jobs=s.solo_jobs, iters=s.iters, voxels=s.voxels,
+                project_ms=s.project_ms, iterate_ms=s.iterate_ms, output_ms=s.output_ms,
+                autotune_ms=s.autotune_ms,
+                classes=[dict(precision=s.class_precision[i], rank_padded=s.class_rank_padded[i],
+                              jobs=s.class_jobs[i], bricks=s.class_bricks[i],
+                              brick=(16, s.class_brick_y[i], s.class_brick_z[i]))
+                         for i in range(c)])
+
+
+def ssmap_batch_last_error(b) -> str:
+    return load().ssmap_batch_last_error(b).decode()
+
+
+def ssmap_batch_destroy(b) -> None:
+    load().ssmap_batch_destroy(b)
+
+
+class BatchMapper:
+    """Many problems solved together (owns an ssmap batch)."""
+
+    def __init__(self, Ks, grids):
+        self.Ks = [np.ascontiguousarray(K, dtype=np.float64) for K in Ks]
+        self.grids = [tuple(int(v) for v in g) for g in grids]
+        self.N = [g[0] * g[1] * g[2] for g in self.grids]
+        self.b = ssmap_batch_create(self.Ks, self.grids)
+
+    def solve(self, Ms, lams, betas, iters, **kw):
+        steps = [make_steps(bt, **kw) for bt in betas]
+        return ssmap_batch_solve(self.b, Ms, lams, steps, iters,
+                                 [(n, K.shape[1]) for n, K in zip(self.N, self.Ks)])
+
+    def solve_torch(self, Ms, lams, betas, iters, Fs=None, stream=None, **kw):
+        import torch
+        steps = [make_steps(bt, **kw) for bt in betas]
+        if Fs is None:
+            Fs = [torch.empty((n, K.shape[1]), dtype=M.dtype, device=M.device)
+                  for n, K, M in zip(self.N, self.Ks, Ms)]
+        for M, F, n, K in zip(Ms, Fs, self.N, self.Ks):
+            if not (M.is_cuda and M.is_contiguous() and M.shape == (n, K.shape[0])):
+                raise ValueError("each M must be a contiguous (N, P) device tensor")
+            if not (F.is_contiguous() and F.shape == (n, K.shape[1]) and F.dtype == M.dtype):
+                raise ValueError("each F must be a contiguous (N, Q) tensor of M's type")
+        s = stream if stream is not None else torch.cuda.current_stream(Ms[0].device)
+        ssmap_batch_solve_device(self.b, [M.data_ptr() for M in Ms], lams, steps, iters,
+                                 [F.data_ptr() for F in Fs], s.cuda_stream)
+        return Fs
+
+    def stats(self) -> dict:
+        return ssmap_batch_get_stats(self.b)
+
+    def close(self):
+        if self.b:
+            ssmap_batch_destroy(self.b)
+            self.b = None
 
     def __enter__(self):
         return self

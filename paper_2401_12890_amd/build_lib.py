@@ -29,10 +29,7 @@ def build(verbose: bool = False) -> str:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = DEVICE_FLAGS
-        else:
-            cmd += ["-D__HIP_PLATFORM_AMD__"]
+        cmd[1:1] = DEVICE_FLAGS   # host-only sources too: no device pass for other targets
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

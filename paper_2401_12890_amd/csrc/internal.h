@@ -52,10 +52,28 @@ struct IterArgs {
 void launch_update_unfused(int mode, const IterArgs &a, hipStream_t s);
 void launch_projw_unfused(int mode, const IterArgs &a, hipStream_t s);
 
-// Fused single-pass iteration (MFMA contractions); fused_supported() tells
-// whether (mode, padded rank, voxel count) has a fused kernel.
+// Fused single-pass iteration (MFMA contractions). One launch walks a table
+// of bricks, each naming its job (an IterArgs entry), so one launch can cover
+// many problems of one class (precision, padded rank, brick shape).
+struct TileRef {
+    int job, tx, ty, tz;   // brick (tx, ty, tz) of job `job`; bricks are 16 x ty x tz voxels
+};
+struct FusedShape {
+    int ty, tz;
+};
+struct FusedLaunch {
+    int mode, r, RP;
+    FusedShape shape;
+    const IterArgs *jobs;  // device array
+    const TileRef *tiles;  // device array
+    int ntiles;
+};
+// fused_supported(): whether (mode, padded rank, voxel count) has a fused kernel.
 bool fused_supported(int mode, int RP, int64_t N);
-void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s);
+bool launch_fused(const FusedLaunch &L, hipStream_t s);   // false: no such shape
+FusedShape default_shape(int mode, const Grid &g);
+std::vector<FusedShape> candidate_shapes(int mode, bool planar);
+void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out);
 // Per-chunk V operand blocks of the fused kernel (IterArgs::Vu points to them).
 void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
                     std::vector<double> &Vop);

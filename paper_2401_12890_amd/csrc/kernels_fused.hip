@@ -167,7 +167,7 @@ template <> struct Buf<double, v4d> {
 // blocks of r in the y contraction. bf16x3 uses one 32-wide K-step (KSU unused).
 template <int MODE, int RB, int KSU, int TY, int TZ>
 __global__ void __launch_bounds__(NT, 1)
-k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
+k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles) {
     using F = FT<MODE>;
     using T = typename F::T;
     using V4 = typename F::V4;
@@ -187,17 +187,15 @@ k_fused(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
     __shared__ V4 lds[4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
     __shared__ uint4 ldsv[NT];           // V operands of the chunk (entries >= VB/16 unused)
 
-    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
-    const int ntiles = tiles_x * tiles_y * tiles_z;
     int tile = blockIdx.x;
     if ((ntiles & 7) == 0) {             // keep neighbouring bricks on one XCD (shared L2)
         const int per = ntiles >> 3;
         tile = (tile & 7) * per + (tile >> 3);
     }
-    const int tx = tile % tiles_x;
-    const int ty = (tile / tiles_x) % tiles_y;
-    const int tz = tile / (tiles_x * tiles_y);
-    const int64_t x0 = (int64_t)tx * TX, y0 = (int64_t)ty * TY, z0 = (int64_t)tz * TZ;
+    const TileRef tr = tiles[tile];
+    const IterArgs &a = jobs[tr.job];
+    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
+    const int64_t x0 = (int64_t)tr.tx * TX, y0 = (int64_t)tr.ty * TY, z0 = (int64_t)tr.tz * TZ;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -438,7 +436,7 @@ __device__ __forceinline__ void lds_dma16(__amdgpu_buffer_rsrc_t r, void *lds, u
 
 template <int MODE, int RB, int KSU, int TY, int TZ>
 __global__ void __launch_bounds__(NT, 1)
-k_fused_dma(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
+k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles) {
     static_assert(MODE != MODE_FP64, "float64 uses the register-staged kernel");
     using F = FT<MODE>;
     using V4 = v4f;
@@ -458,17 +456,15 @@ k_fused_dma(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
     __shared__ uint4 zbuf[2][BX::NG * 64];
     __shared__ uint4 vbuf[2][VB / 16];
 
-    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
-    const int ntiles = tiles_x * tiles_y * tiles_z;
     int tile = blockIdx.x;
     if ((ntiles & 7) == 0) {             // keep neighbouring bricks on one XCD (shared L2)
         const int per = ntiles >> 3;
         tile = (tile & 7) * per + (tile >> 3);
     }
-    const int tx = tile % tiles_x;
-    const int ty = (tile / tiles_x) % tiles_y;
-    const int tz = tile / (tiles_x * tiles_y);
-    const int64_t x0 = (int64_t)tx * TX, y0 = (int64_t)ty * TY, z0 = (int64_t)tz * TZ;
+    const TileRef tr = tiles[tile];
+    const IterArgs &a = jobs[tr.job];
+    const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
+    const int64_t x0 = (int64_t)tr.tx * TX, y0 = (int64_t)tr.ty * TY, z0 = (int64_t)tr.tz * TZ;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -683,50 +679,42 @@ k_fused_dma(IterArgs a, int tiles_x, int tiles_y, int tiles_z) {
     }
 }
 
-struct Shape {
-    int ty, tz;
-};
-
-// Brick shape per grid: 2-D grids use one plane.
-Shape pick_shape(int mode, const Grid &g) {
-    if (mode == MODE_FP64) return g.nz == 1 ? Shape{16, 1} : Shape{4, 4};
-    return g.nz == 1 ? Shape{16, 1} : Shape{8, 4};
-}
-
 template <int MODE, int RB, int KSU, int TY, int TZ>
-void launch_t(const IterArgs &a, hipStream_t s) {
-    const int tiles_x = (int)((a.g.nx + TX - 1) / TX);
-    const int tiles_y = (int)((a.g.ny + TY - 1) / TY);
-    const int tiles_z = (int)((a.g.nz + TZ - 1) / TZ);
+void launch_t(const FusedLaunch &L, hipStream_t s) {
     // float64 and float32 stage through registers (measured faster for float32),
     // bf16x3 through direct LDS loads
     if constexpr (MODE == MODE_BF16X3)
-        hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(tiles_x * tiles_y * tiles_z),
-                           dim3(NT), 0, s, a, tiles_x, tiles_y, tiles_z);
+        hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s,
+                           L.jobs, L.tiles, L.ntiles);
     else
-        hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(tiles_x * tiles_y * tiles_z),
-                           dim3(NT), 0, s, a, tiles_x, tiles_y, tiles_z);
+        hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s, L.jobs,
+                           L.tiles, L.ntiles);
 }
 
 template <int MODE, int RB, int KSU>
-void launch_shape(const IterArgs &a, hipStream_t s) {
-    const Shape sh = pick_shape(MODE, a.g);
+bool launch_shape(const FusedLaunch &L, hipStream_t s) {
+    const int ty = L.shape.ty, tz = L.shape.tz;
     if constexpr (MODE == MODE_FP64) {
-        if (sh.tz == 1) launch_t<MODE, RB, KSU, 16, 1>(a, s);
-        else launch_t<MODE, RB, KSU, 4, 4>(a, s);
+        if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
+        if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
     } else {
-        if (sh.tz == 1) launch_t<MODE, RB, KSU, 16, 1>(a, s);
-        else launch_t<MODE, RB, KSU, 8, 4>(a, s);
+        if (ty == 8 && tz == 1) return launch_t<MODE, RB, KSU, 8, 1>(L, s), true;
+        if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
+        if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
+        if (ty == 8 && tz == 4) return launch_t<MODE, RB, KSU, 8, 4>(L, s), true;
+        if constexpr (MODE == MODE_FP32)
+            if (ty == 32 && tz == 1) return launch_t<MODE, RB, KSU, 32, 1>(L, s), true;
     }
+    return false;
 }
 
 // u K-steps: r <= 16 -> 4, 17..20 -> 5, 21..24 -> 6, 25..32 -> 8 (zero-padded ranks)
 template <int MODE>
-void launch_mode(const IterArgs &a, hipStream_t s) {
-    if (a.r <= 16) launch_shape<MODE, 1, 4>(a, s);
-    else if (a.r <= 20) launch_shape<MODE, 2, 5>(a, s);
-    else if (a.r <= 24) launch_shape<MODE, 2, 6>(a, s);
-    else launch_shape<MODE, 2, 8>(a, s);
+bool launch_mode(const FusedLaunch &L, hipStream_t s) {
+    if (L.r <= 16) return launch_shape<MODE, 1, 4>(L, s);
+    if (L.r <= 20) return launch_shape<MODE, 2, 5>(L, s);
+    if (L.r <= 24) return launch_shape<MODE, 2, 6>(L, s);
+    return launch_shape<MODE, 2, 8>(L, s);
 }
 
 }  // namespace
@@ -739,15 +727,34 @@ bool fused_supported(int mode, int RP, int64_t N) {
            (int64_t)RP * N * esz < ((int64_t)1 << 31);
 }
 
-void launch_iter_fused(int mode, const IterArgs &a, hipStream_t s) {
-    if (mode == MODE_FP64) {
-        launch_mode<MODE_FP64>(a, s);
-    } else if (mode == MODE_FP32) {
-        launch_mode<MODE_FP32>(a, s);
-    } else {
-        if (a.RP == 16) launch_shape<MODE_BF16X3, 1, 1>(a, s);
-        else launch_shape<MODE_BF16X3, 2, 1>(a, s);
+FusedShape default_shape(int mode, const Grid &g) {
+    if (mode == MODE_FP64) return g.nz == 1 ? FusedShape{16, 1} : FusedShape{4, 4};
+    return g.nz == 1 ? FusedShape{16, 1} : FusedShape{8, 4};
+}
+
+std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
+    if (mode == MODE_FP64) return planar ? std::vector<FusedShape>{{16, 1}} : std::vector<FusedShape>{{4, 4}};
+    if (planar) {
+        if (mode == MODE_FP32) return {{8, 1}, {16, 1}, {32, 1}};
+        return {{8, 1}, {16, 1}};
     }
+    return {{4, 4}, {8, 4}};
+}
+
+void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out) {
+    const int tx = (int)((g.nx + 15) / 16), ty = (int)((g.ny + sh.ty - 1) / sh.ty),
+              tz = (int)((g.nz + sh.tz - 1) / sh.tz);
+    for (int k = 0; k < tz; ++k)
+        for (int jy = 0; jy < ty; ++jy)
+            for (int i = 0; i < tx; ++i) out.push_back(TileRef{job, i, jy, k});
+}
+
+bool launch_fused(const FusedLaunch &L, hipStream_t s) {
+    if (L.ntiles <= 0) return true;
+    if (L.mode == MODE_FP64) return launch_mode<MODE_FP64>(L, s);
+    if (L.mode == MODE_FP32) return launch_mode<MODE_FP32>(L, s);
+    if (L.RP == 16) return launch_shape<MODE_BF16X3, 1, 1>(L, s);
+    return launch_shape<MODE_BF16X3, 2, 1>(L, s);
 }
 
 namespace {

@@ -180,30 +180,77 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
     return p;
 }
 
-// The solve on device buffers (dM, dF in the mode's I/O type).
-void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *st, int iters,
-                void *dF, hipStream_t s) {
-    const Plan pl = make_plan(c, lambda, st);
+// ---------------------------------------------------------------- solve phases
+// A solve is prepare (per-solve coefficients, operand images, projection a1,
+// state initialisation), the iteration loop (a2..a7) and finish (a8). The
+// single-problem entry points run all three; a batch prepares every job,
+// runs one loop whose fused launches cover all jobs of a class, and
+// finishes every job.
+struct Prepared {
+    Plan pl;
+    IterArgs a{};             // z / znew of iteration 0
+    void *z[2] = {nullptr, nullptr};
+    bool monitor = false, aux = false;
+    double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr,
+           *sig = nullptr;
+    void *auxA = nullptr, *auxB = nullptr;
+    const void *dM = nullptr;
+    int iters = 0;
+};
+
+IterArgs args_for(const Prepared &P, int k) {
+    IterArgs a = P.a;
+    a.z = P.z[k & 1];
+    a.znew = P.z[(k & 1) ^ 1];
+    return a;
+}
+
+// Projection and state initialisation only (used again after autotuning).
+void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
+    const Plan &pl = P.pl;
     const int64_t N = c->g.N;
-    const int P = c->P, Q = c->Q, Qp = c->Qp, r = pl.r, RP = pl.RP;
     const size_t esz = pl.mode == MODE_FP64 ? 8 : 4;
-    const bool monitor = st->check_every > 0;
-    const bool aux = (st->flags & SSMAP_KEEP_AUX) != 0;
+    int *bad = (int *)ensure(c, "bad", 256);
+    launch_zero(bad, 1, 4, s);
+    launch_project(pl.mode, P.dM, c->P, (const double *)ensure(c, "Ur", (size_t)c->P * pl.r * 8),
+                   P.sig, (const double *)ensure(c, "acoef", (size_t)pl.RP * 8), pl.r, pl.RP, N,
+                   P.t, P.mperp2, (void *)P.a.ah, P.a.w, P.a.y, bad, s);
+    launch_zero(P.z[0], (size_t)c->Qp * N, (int)esz, s);
+    launch_zero(P.z[1], (size_t)c->Qp * N, (int)esz, s);
+    if (P.aux) {
+        launch_zero(P.auxA, (size_t)c->Qp * N, (int)esz, s);
+        launch_zero(P.auxB, (size_t)c->Qp * N, (int)esz, s);
+    }
+    HIPC(c, hipGetLastError());
+}
+
+Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *st, int iters,
+                 hipStream_t s) {
+    Prepared P;
+    P.pl = make_plan(c, lambda, st);
+    const Plan &pl = P.pl;
+    P.dM = dM;
+    P.iters = iters;
+    const int64_t N = c->g.N;
+    const int Pm = c->P, Q = c->Q, Qp = c->Qp, r = pl.r, RP = pl.RP;
+    const size_t esz = pl.mode == MODE_FP64 ? 8 : 4;
+    P.monitor = st->check_every > 0;
+    P.aux = (st->flags & SSMAP_KEEP_AUX) != 0;
     const size_t zbytes = (size_t)Qp * N * esz;
     const size_t rbytes = (size_t)RP * N * esz;
 
     std::vector<std::pair<std::string, size_t>> need = {
         {"z0", zbytes}, {"z1", zbytes}, {"w", rbytes}, {"y", rbytes}, {"ah", rbytes},
-        {"V", (size_t)Qp * RP * esz}, {"b", (size_t)RP * esz}, {"Ur", (size_t)P * r * 8},
+        {"V", (size_t)Qp * RP * esz}, {"b", (size_t)RP * esz}, {"Ur", (size_t)Pm * r * 8},
         {"sig", (size_t)RP * 8}, {"acoef", (size_t)RP * 8}, {"bad", 256}};
-    if (monitor) {
+    if (P.monitor) {
         need.push_back({"t", (size_t)r * N * 8});
         need.push_back({"mperp2", (size_t)N * 8});
         need.push_back({"V64", (size_t)Qp * RP * 8});
         need.push_back({"partial", (size_t)2048 * ST_COUNT * 8});
         need.push_back({"stat", (size_t)ST_COUNT * 8});
     }
-    if (aux) {
+    if (P.aux) {
         need.push_back({"auxA", zbytes});
         need.push_back({"auxB", zbytes});
     }
@@ -213,21 +260,21 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
         need.push_back({"Vlo", (size_t)Qp * RP * 2});
     }
     plan_check(c, need);
-    void *z[2] = {ensure(c, "z0", zbytes), ensure(c, "z1", zbytes)};
+    P.z[0] = ensure(c, "z0", zbytes);
+    P.z[1] = ensure(c, "z1", zbytes);
     void *w = ensure(c, "w", rbytes), *y = ensure(c, "y", rbytes), *ah = ensure(c, "ah", rbytes);
     void *Vd = ensure(c, "V", (size_t)Qp * RP * esz);
     void *bd = ensure(c, "b", (size_t)RP * esz);
-    double *Ur = (double *)ensure(c, "Ur", (size_t)P * r * 8);
-    double *sig = (double *)ensure(c, "sig", (size_t)RP * 8);
+    double *Ur = (double *)ensure(c, "Ur", (size_t)Pm * r * 8);
+    P.sig = (double *)ensure(c, "sig", (size_t)RP * 8);
     double *acoef = (double *)ensure(c, "acoef", (size_t)RP * 8);
-    int *bad = (int *)ensure(c, "bad", 256);
 
     // ---- per-solve coefficients (float64 on the host), Sec. III-F rules
-    std::vector<double> Vh((size_t)Qp * RP, 0.0), Urh((size_t)P * r), sh(RP, 0.0), ah_(RP, 0.0),
+    std::vector<double> Vh((size_t)Qp * RP, 0.0), Urh((size_t)Pm * r), sh(RP, 0.0), ah_(RP, 0.0),
         bh(RP, 0.0);
     for (int q = 0; q < Q; ++q)
         for (int i = 0; i < r; ++i) Vh[(size_t)q * RP + i] = c->V[(size_t)q * c->kmin + i];
-    for (int p = 0; p < P; ++p)
+    for (int p = 0; p < Pm; ++p)
         for (int i = 0; i < r; ++i) Urh[(size_t)p * r + i] = c->U[(size_t)p * c->kmin + i];
     for (int i = 0; i < r; ++i) {
         const double s2 = c->s[i] * c->s[i];
@@ -235,17 +282,18 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
         ah_[i] = 1.0 / (pl.beta + s2);        // 1/beta - s_i of Eq. (DictVecSVD)
         bh[i] = s2 / (pl.beta + s2);          // beta * s_i of Eq. (DictVecSVD)
     }
+    std::vector<float> Vf, bf;
     if (pl.mode == MODE_FP64) {
         HIPC(c, hipMemcpyAsync(Vd, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
         HIPC(c, hipMemcpyAsync(bd, bh.data(), RP * 8, hipMemcpyHostToDevice, s));
     } else {
-        std::vector<float> Vf(Vh.begin(), Vh.end()), bf(bh.begin(), bh.end());
+        Vf.assign(Vh.begin(), Vh.end());
+        bf.assign(bh.begin(), bh.end());
         HIPC(c, hipMemcpyAsync(Vd, Vf.data(), Vf.size() * 4, hipMemcpyHostToDevice, s));
         HIPC(c, hipMemcpyAsync(bd, bf.data(), RP * 4, hipMemcpyHostToDevice, s));
-        HIPC(c, hipStreamSynchronize(s));       // host staging vectors go out of scope
     }
     HIPC(c, hipMemcpyAsync(Ur, Urh.data(), Urh.size() * 8, hipMemcpyHostToDevice, s));
-    HIPC(c, hipMemcpyAsync(sig, sh.data(), RP * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(P.sig, sh.data(), RP * 8, hipMemcpyHostToDevice, s));
     HIPC(c, hipMemcpyAsync(acoef, ah_.data(), RP * 8, hipMemcpyHostToDevice, s));
     void *Vhi = nullptr, *Vlo = nullptr;
     if (pl.mode == MODE_BF16X3) {
@@ -253,36 +301,60 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
         Vlo = ensure(c, "Vlo", (size_t)Qp * RP * 2);
         launch_split_bf16((const float *)Vd, (uint16_t *)Vhi, (uint16_t *)Vlo, (size_t)Qp * RP, s);
     }
-    void *Vu = nullptr, *Vy = nullptr;
+    void *Vop = nullptr;
+    std::vector<uint16_t> Vop16;
+    std::vector<double> Vop64;
+    std::vector<float> Vop32;
     if (pl.fused && pl.mode == MODE_BF16X3) {
-        std::vector<uint16_t> Vop;
-        fused_operands_bf16(Vh, Qp, RP, Vop);
-        Vu = ensure(c, "Vop", Vop.size() * 2);
-        HIPC(c, hipMemcpy(Vu, Vop.data(), Vop.size() * 2, hipMemcpyHostToDevice));
+        fused_operands_bf16(Vh, Qp, RP, Vop16);
+        Vop = ensure(c, "Vop", Vop16.size() * 2);
+        HIPC(c, hipMemcpyAsync(Vop, Vop16.data(), Vop16.size() * 2, hipMemcpyHostToDevice, s));
     } else if (pl.fused) {
-        std::vector<double> Vop;
-        fused_operands(Vh, Qp, RP, pl.mode == MODE_FP64, Vop);
-        Vu = ensure(c, "Vop", Vop.size() * esz);
+        fused_operands(Vh, Qp, RP, pl.mode == MODE_FP64, Vop64);
+        Vop = ensure(c, "Vop", Vop64.size() * esz);
         if (pl.mode == MODE_FP64) {
-            HIPC(c, hipMemcpy(Vu, Vop.data(), Vop.size() * 8, hipMemcpyHostToDevice));
+            HIPC(c, hipMemcpyAsync(Vop, Vop64.data(), Vop64.size() * 8, hipMemcpyHostToDevice, s));
         } else {
-            std::vector<float> f(Vop.begin(), Vop.end());
-            HIPC(c, hipMemcpy(Vu, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+            Vop32.assign(Vop64.begin(), Vop64.end());
+            HIPC(c, hipMemcpyAsync(Vop, Vop32.data(), Vop32.size() * 4, hipMemcpyHostToDevice, s));
         }
     }
-    double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr;
-    if (monitor) {
-        V64 = (double *)ensure(c, "V64", (size_t)Qp * RP * 8);
-        HIPC(c, hipMemcpyAsync(V64, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
-        t = (double *)ensure(c, "t", (size_t)r * N * 8);
-        mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
-        partial = (double *)ensure(c, "partial", (size_t)2048 * ST_COUNT * 8);
-        stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
+    if (P.monitor) {
+        P.V64 = (double *)ensure(c, "V64", (size_t)Qp * RP * 8);
+        HIPC(c, hipMemcpyAsync(P.V64, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
+        P.t = (double *)ensure(c, "t", (size_t)r * N * 8);
+        P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
+        P.partial = (double *)ensure(c, "partial", (size_t)2048 * ST_COUNT * 8);
+        P.stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
     }
-    HIPC(c, hipStreamSynchronize(s));         // Vh, Urh, ... are host locals
+    if (P.aux) {
+        P.auxA = ensure(c, "auxA", zbytes);
+        P.auxB = ensure(c, "auxB", zbytes);
+    }
+    HIPC(c, hipStreamSynchronize(s));         // host staging vectors are locals
+
+    IterArgs &a = P.a;
+    a.w = w;
+    a.y = y;
+    a.ah = ah;
+    a.V = Vd;
+    a.Vhi = Vhi;
+    a.Vlo = Vlo;
+    a.bcoef = bd;
+    a.Vu = Vop;
+    a.Vy = nullptr;
+    a.r = r;
+    a.RP = RP;
+    a.nchunk = c->nchunk;
+    a.g = c->g;
+    a.tau = pl.tau;
+    a.lam2 = 2.0 * pl.lam;
+    a.beta = pl.beta;
 
     ssmap_stats &S = c->stats;
+    const double setup = S.setup_ms;
     std::memset(&S, 0, sizeof(S));
+    S.setup_ms = setup;
     S.rank = r;
     S.rank_padded = RP;
     S.precision = pl.mode;
@@ -295,108 +367,122 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
 
     // ---- a1: data projection, state initialisation (z^0 = 0, w^0 = a.h, y^0 = 0)
     HIPC(c, hipEventRecord(c->ev[0], s));
-    launch_zero(bad, 1, 4, s);
-    launch_project(pl.mode, dM, P, Ur, sig, acoef, r, RP, N, t, mperp2, ah, w, y, bad, s);
-    launch_zero(z[0], (size_t)Qp * N, (int)esz, s);
-    if (iters >= 1) launch_zero(z[1], (size_t)Qp * N, (int)esz, s);
-    HIPC(c, hipGetLastError());
+    init_state(c, P, s);
     HIPC(c, hipEventRecord(c->ev[1], s));
     int badh = 0;
-    HIPC(c, hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&badh, ensure(c, "bad", 256), 4, hipMemcpyDeviceToHost, s));
     HIPC(c, hipStreamSynchronize(s));
     if (badh) fail(SSMAP_ENONFINITE, "M holds a NaN or Inf");
+    return P;
+}
 
-    void *auxA = nullptr, *auxB = nullptr;
-    if (aux) {
-        auxA = ensure(c, "auxA", zbytes);
-        auxB = ensure(c, "auxB", zbytes);
-        launch_zero(auxA, (size_t)Qp * N, (int)esz, s);
-        launch_zero(auxB, (size_t)Qp * N, (int)esz, s);
-    }
+// Device copies of a one-job launch plan: two IterArgs (even / odd
+// iterations) and the brick table for the default shape.
+FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
+    FusedLaunch L{};
+    L.mode = P.pl.mode;
+    L.r = P.pl.r;
+    L.RP = P.pl.RP;
+    L.shape = default_shape(P.pl.mode, c->g);
+    std::vector<TileRef> tiles;
+    append_tiles(c->g, 0, L.shape, tiles);
+    IterArgs two[2] = {args_for(P, 0), args_for(P, 1)};
+    IterArgs *dj = (IterArgs *)ensure(c, "jobs", sizeof(two));
+    TileRef *dt = (TileRef *)ensure(c, "tiles", tiles.size() * sizeof(TileRef));
+    HIPC(c, hipMemcpyAsync(dj, two, sizeof(two), hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice, s));
+    HIPC(c, hipStreamSynchronize(s));
+    L.jobs = dj;
+    L.tiles = dt;
+    L.ntiles = (int)tiles.size();
+    return L;
+}
 
-    // ---- the LADMM loop (a2 .. a7)
-    IterArgs a{};
-    a.w = w;
-    a.y = y;
-    a.ah = ah;
-    a.V = Vd;
-    a.Vhi = Vhi;
-    a.Vlo = Vlo;
-    a.bcoef = bd;
-    a.Vu = Vu;
-    a.Vy = Vy;
-    a.r = r;
-    a.RP = RP;
-    a.nchunk = c->nchunk;
-    a.g = c->g;
-    a.tau = pl.tau;
-    a.lam2 = 2.0 * pl.lam;
-    a.beta = pl.beta;
-    HIPC(c, hipEventRecord(c->ev[2], s));
-    int cur = 0;
-    for (int k = 0; k < iters; ++k) {
-        a.z = z[cur];
-        a.znew = z[cur ^ 1];
-        a.dprev = nullptr;
-        a.fout = nullptr;
-        a.dout = nullptr;
-        if (aux && k == iters - 2) a.dout = auxA;                 // d^{K-1}
-        if (aux && k == iters - 1) {
-            a.dprev = iters >= 2 ? auxA : nullptr;                 // d^{K-1} (0 when K = 1)
-            a.fout = auxA;                                        // f^K, in place
-            a.dout = auxB;                                        // d^K
-        }
-        if (pl.fused) {
-            // f and d are not part of the fused pass; bracket the last two iterations
-            const size_t cnt = (size_t)Qp * N;
-            if (aux && k == iters - 2) launch_aux_pre(pl.mode, a, auxA, nullptr, nullptr, s);
-            if (aux && k == iters - 1)   // auxB = z + u, auxA: d^{K-1} -> f^K (d^0 = 0 if K = 1)
-                launch_aux_pre(pl.mode, a, auxB, auxA, iters >= 2 ? auxA : nullptr, s);
-            launch_iter_fused(pl.mode, a, s);
-            if (aux && k == iters - 2) launch_aux_post(pl.mode, auxA, a.znew, pl.beta, cnt, s);
-            if (aux && k == iters - 1) launch_aux_post(pl.mode, auxB, a.znew, pl.beta, cnt, s);
-        } else {
-            launch_update_unfused(pl.mode, a, s);
-            launch_projw_unfused(pl.mode, a, s);
-        }
-        if (monitor && ((k + 1) % st->check_every == 0 || k + 1 == iters)) {
-            launch_monitor(pl.mode, z[cur ^ 1], z[cur], V64, sig, t, mperp2, r, RP, c->nchunk,
-                           c->g, partial, 2048, stat, s);
-            HIPC(c, hipGetLastError());
-            HIPC(c, hipMemcpyAsync(c->host_stats, stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
-            HIPC(c, hipStreamSynchronize(s));
-            const double *h = c->host_stats;
-            if (S.n_hist < SSMAP_MAX_HIST) {
-                S.hist_iter[S.n_hist] = k + 1;
-                S.hist_objective[S.n_hist] = 0.5 * h[ST_DATA] + pl.lam * h[ST_REG];
-                S.hist_dual[S.n_hist] = pl.beta * std::sqrt(h[ST_DZ]);
-                S.hist_znorm[S.n_hist] = std::sqrt(h[ST_ZNORM]);
-                S.n_hist++;
-            }
-            if (h[ST_NONFINITE] != 0.0 || !std::isfinite(h[ST_DATA]))
-                fail(SSMAP_ENONFINITE, "non-finite iterate at iteration " + std::to_string(k + 1));
-        }
-        cur ^= 1;
-    }
+void monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
+    const Plan &pl = P.pl;
+    launch_monitor(pl.mode, P.z[(k + 1) & 1], P.z[k & 1], P.V64, P.sig, P.t, P.mperp2, pl.r, pl.RP,
+                   c->nchunk, c->g, P.partial, 2048, P.stat, s);
     HIPC(c, hipGetLastError());
-    HIPC(c, hipEventRecord(c->ev[3], s));
-    // ---- a8: z^K to the voxel-major output
-    launch_output(pl.mode, z[cur], dF, Q, N, false, s);
+    HIPC(c, hipMemcpyAsync(c->host_stats, P.stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    const double *h = c->host_stats;
+    ssmap_stats &S = c->stats;
+    if (S.n_hist < SSMAP_MAX_HIST) {
+        S.hist_iter[S.n_hist] = k + 1;
+        S.hist_objective[S.n_hist] = 0.5 * h[ST_DATA] + pl.lam * h[ST_REG];
+        S.hist_dual[S.n_hist] = pl.beta * std::sqrt(h[ST_DZ]);
+        S.hist_znorm[S.n_hist] = std::sqrt(h[ST_ZNORM]);
+        S.n_hist++;
+    }
+    if (h[ST_NONFINITE] != 0.0 || !std::isfinite(h[ST_DATA]))
+        fail(SSMAP_ENONFINITE, "non-finite iterate at iteration " + std::to_string(k + 1));
+}
+
+// One iteration of one job outside a shared launch (unfused kernels, or the
+// fused single-job launch with the aux passes around it).
+void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipStream_t s) {
+    const Plan &pl = P.pl;
+    IterArgs a = args_for(P, k);
+    const int iters = P.iters;
+    if (P.aux && k == iters - 2) a.dout = P.auxA;                    // d^{K-1}
+    if (P.aux && k == iters - 1) {
+        a.dprev = iters >= 2 ? P.auxA : nullptr;                     // d^{K-1} (0 when K = 1)
+        a.fout = P.auxA;                                            // f^K, in place
+        a.dout = P.auxB;                                            // d^K
+    }
+    if (pl.fused) {
+        // f and d are not part of the fused pass; bracket the last two iterations
+        const size_t cnt = (size_t)c->Qp * c->g.N;
+        if (P.aux && k == iters - 2) launch_aux_pre(pl.mode, a, P.auxA, nullptr, nullptr, s);
+        if (P.aux && k == iters - 1)   // auxB = z + u, auxA: d^{K-1} -> f^K (d^0 = 0 if K = 1)
+            launch_aux_pre(pl.mode, a, P.auxB, P.auxA, iters >= 2 ? P.auxA : nullptr, s);
+        FusedLaunch Lk = *L;
+        Lk.jobs = L->jobs + (k & 1);
+        if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
+        if (P.aux && k == iters - 2) launch_aux_post(pl.mode, P.auxA, a.znew, pl.beta, cnt, s);
+        if (P.aux && k == iters - 1) launch_aux_post(pl.mode, P.auxB, a.znew, pl.beta, cnt, s);
+    } else {
+        launch_update_unfused(pl.mode, a, s);
+        launch_projw_unfused(pl.mode, a, s);
+    }
+}
+
+void finish(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
+    const int iters = P.iters;
+    launch_output(P.pl.mode, P.z[iters & 1], dF, c->Q, c->g.N, false, s);
     HIPC(c, hipGetLastError());
     HIPC(c, hipEventRecord(c->ev[4], s));
     HIPC(c, hipStreamSynchronize(s));
+    ssmap_stats &S = c->stats;
     S.iters = iters;
+    S.device_bytes = (double)c->held;
+    if (P.aux) {
+        c->aux_valid = true;
+        c->aux_mode = P.pl.mode;
+        c->aux_iters = iters;
+        c->aux_f = P.auxA;
+        c->aux_d = P.auxB;
+    }
+}
+
+// The solve of one problem on device buffers (dM, dF in the mode's I/O type).
+void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *st, int iters,
+                void *dF, hipStream_t s) {
+    Prepared P = prepare(c, dM, lambda, st, iters, s);
+    FusedLaunch L{};
+    if (P.pl.fused) L = single_launch(c, P, s);
+    HIPC(c, hipEventRecord(c->ev[2], s));
+    for (int k = 0; k < iters; ++k) {
+        step_job(c, P, &L, k, s);
+        if (P.monitor && ((k + 1) % st->check_every == 0 || k + 1 == iters)) monitor_step(c, P, k, s);
+    }
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipEventRecord(c->ev[3], s));
+    finish(c, P, dF, s);
+    ssmap_stats &S = c->stats;
     S.project_ms = elapsed_ms(c->ev[0], c->ev[1]);
     S.iterate_ms = elapsed_ms(c->ev[2], c->ev[3]);
     S.output_ms = elapsed_ms(c->ev[3], c->ev[4]);
-    S.device_bytes = (double)c->held;
-    if (aux) {
-        c->aux_valid = true;
-        c->aux_mode = pl.mode;
-        c->aux_iters = iters;
-        c->aux_f = auxA;
-        c->aux_d = auxB;
-    }
 }
 
 template <typename Fn>
@@ -432,6 +518,227 @@ void free_ctx(ssmap_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     if (c->host_stats) (void)hipHostFree(c->host_stats);
     delete c;
+}
+
+// ---------------------------------------------------------------- batches
+struct BatchClass {
+    int mode = 0, r = 0, RP = 0;
+    bool planar = false;
+    std::vector<int> jobs;
+    FusedShape shape{16, 1};
+    int ntiles = 0;
+};
+
+}  // namespace
+
+struct ssmap_batch {
+    ssmap_ctx arena;                      // device buffers of the shared launch plans
+    std::vector<ssmap_ctx *> jobs;
+    std::string err;
+    bool poisoned = false;
+    ssmap_batch_stats stats{};
+    hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+std::string g_batch_create_error;
+
+// Key of a shared-launch class: the fused kernel template (precision and the
+// u K-step bucket of the rank) and whether the grids are planar.
+int rank_bucket(int r) { return r <= 16 ? 0 : r <= 20 ? 1 : r <= 24 ? 2 : 3; }
+
+void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector<Prepared> &Ps,
+                  FusedShape shape, FusedLaunch &L, hipStream_t s) {
+    std::vector<IterArgs> args(2 * C.jobs.size());
+    std::vector<TileRef> tiles;
+    for (size_t k = 0; k < C.jobs.size(); ++k) {
+        const int j = C.jobs[k];
+        args[k] = args_for(Ps[j], 0);                        // even iterations
+        args[C.jobs.size() + k] = args_for(Ps[j], 1);        // odd iterations
+        append_tiles(b->jobs[j]->g, (int)k, shape, tiles);
+    }
+    ssmap_ctx *A = &b->arena;
+    const std::string tag = std::to_string(ci);
+    IterArgs *dj = (IterArgs *)ensure(A, "cls_jobs" + tag, args.size() * sizeof(IterArgs));
+    TileRef *dt = (TileRef *)ensure(A, "cls_tiles" + tag, tiles.size() * sizeof(TileRef));
+    HIPC(A, hipMemcpyAsync(dj, args.data(), args.size() * sizeof(IterArgs), hipMemcpyHostToDevice, s));
+    HIPC(A, hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice, s));
+    HIPC(A, hipStreamSynchronize(s));
+    L = FusedLaunch{};
+    L.mode = C.mode;
+    L.r = C.r;
+    L.RP = C.RP;
+    L.shape = shape;
+    L.jobs = dj;
+    L.tiles = dt;
+    L.ntiles = (int)tiles.size();
+}
+
+// One shared launch of iteration k: jobs[0 .. n) hold the even-iteration
+// arguments, jobs[n .. 2n) the odd ones; a brick names its job by index.
+void launch_class(ssmap_batch *b, const FusedLaunch &L, size_t njobs, int k, hipStream_t s) {
+    FusedLaunch Lk = L;
+    Lk.jobs = L.jobs + ((k & 1) ? njobs : 0);
+    if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
+    (void)b;
+}
+
+void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambda,
+                      const ssmap_steps *steps, int iters, void *const *dF, hipStream_t s) {
+    const int nj = (int)b->jobs.size();
+    bool tune = false;
+    for (int j = 0; j < nj; ++j) {
+        if (!dM[j] || !dF[j]) fail(SSMAP_EINVAL, "NULL buffer for job " + std::to_string(j));
+        validate_steps(b->jobs[j], lambda[j], &steps[j], iters);
+        if (steps[j].check_every != 0 || (steps[j].flags & SSMAP_KEEP_AUX))
+            fail(SSMAP_EINVAL, "batches take no monitoring and no SSMAP_KEEP_AUX");
+        tune |= (steps[j].flags & SSMAP_AUTOTUNE) != 0;
+    }
+    ssmap_batch_stats &S = b->stats;
+    std::memset(&S, 0, sizeof(S));
+    S.njobs = nj;
+    S.iters = iters;
+    // ---- prepare every job (coefficients, operand images, projection, z^0 = 0)
+    HIPC(&b->arena, hipEventRecord(b->ev[0], s));
+    std::vector<Prepared> Ps;
+    Ps.reserve(nj);
+    for (int j = 0; j < nj; ++j) {
+        try {
+            Ps.push_back(prepare(b->jobs[j], dM[j], lambda[j], &steps[j], iters, s));
+        } catch (const Fail &f) {
+            throw Fail{f.status, "job " + std::to_string(j) + ": " + f.msg};
+        }
+        S.voxels += (double)b->jobs[j]->g.N;
+    }
+    HIPC(&b->arena, hipEventRecord(b->ev[1], s));
+    // ---- group the fused jobs into shared-launch classes
+    std::vector<BatchClass> classes;
+    std::vector<int> solo;
+    for (int j = 0; j < nj; ++j) {
+        const Plan &pl = Ps[j].pl;
+        if (!pl.fused) {
+            solo.push_back(j);
+            continue;
+        }
+        const bool planar = b->jobs[j]->g.nz == 1;
+        int found = -1;
+        for (size_t c = 0; c < classes.size(); ++c)
+            if (classes[c].mode == pl.mode && classes[c].RP == pl.RP && classes[c].planar == planar &&
+                rank_bucket(classes[c].r) == rank_bucket(pl.r))
+                found = (int)c;
+        if (found < 0) {
+            if (classes.size() >= SSMAP_MAX_CLASSES) {
+                solo.push_back(j);
+                continue;
+            }
+            BatchClass C;
+            C.mode = pl.mode;
+            C.r = pl.r;
+            C.RP = pl.RP;
+            C.planar = planar;
+            classes.push_back(C);
+            found = (int)classes.size() - 1;
+        }
+        BatchClass &C = classes[found];
+        C.r = std::max(C.r, pl.r);        // the bucket's K-step count covers every member
+        C.jobs.push_back(j);
+    }
+    // ---- brick shape per class: default, or the fastest candidate when tuning
+    std::vector<FusedLaunch> Ls(classes.size());
+    auto t_tune = std::chrono::steady_clock::now();
+    for (size_t c = 0; c < classes.size(); ++c) {
+        BatchClass &C = classes[c];
+        Grid g0 = b->jobs[C.jobs[0]]->g;
+        FusedShape best = default_shape(C.mode, g0);
+        const auto cands = candidate_shapes(C.mode, C.planar);
+        if (tune && cands.size() > 1 && iters > 0) {
+            float best_ms = 1e30f;
+            for (const FusedShape &sh : cands) {
+                FusedLaunch L;
+                upload_class(b, (int)c, C, Ps, sh, L, s);
+                launch_class(b, L, C.jobs.size(), 0, s);             // warm-up
+                HIPC(&b->arena, hipEventRecord(b->ev[4], s));
+                for (int k = 1; k <= 3; ++k) launch_class(b, L, C.jobs.size(), k, s);
+                HIPC(&b->arena, hipEventRecord(b->ev[5], s));
+                HIPC(&b->arena, hipEventSynchronize(b->ev[5]));
+                const float ms = (float)elapsed_ms(b->ev[4], b->ev[5]);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = sh;
+                }
+            }
+            // the search advanced these jobs' states: start them again from z^0
+            for (int j : C.jobs) init_state(b->jobs[j], Ps[j], s);
+        }
+        C.shape = best;
+        upload_class(b, (int)c, C, Ps, best, Ls[c], s);
+        C.ntiles = Ls[c].ntiles;
+    }
+    HIPC(&b->arena, hipStreamSynchronize(s));
+    if (tune)
+        S.autotune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                  t_tune).count();
+    // single-job launch plans of the solo jobs (unfused, or beyond the class limit)
+    std::vector<FusedLaunch> solo_L(solo.size());
+    for (size_t i = 0; i < solo.size(); ++i)
+        if (Ps[solo[i]].pl.fused) solo_L[i] = single_launch(b->jobs[solo[i]], Ps[solo[i]], s);
+    // ---- the shared iteration loop
+    HIPC(&b->arena, hipEventRecord(b->ev[2], s));
+    for (int k = 0; k < iters; ++k) {
+        for (size_t c = 0; c < classes.size(); ++c) launch_class(b, Ls[c], classes[c].jobs.size(), k, s);
+        for (size_t i = 0; i < solo.size(); ++i) step_job(b->jobs[solo[i]], Ps[solo[i]], &solo_L[i], k, s);
+    }
+    HIPC(&b->arena, hipGetLastError());
+    HIPC(&b->arena, hipEventRecord(b->ev[3], s));
+    for (int j = 0; j < nj; ++j) finish(b->jobs[j], Ps[j], dF[j], s);
+    HIPC(&b->arena, hipEventRecord(b->ev[4], s));
+    HIPC(&b->arena, hipStreamSynchronize(s));
+    S.project_ms = elapsed_ms(b->ev[0], b->ev[1]);
+    S.iterate_ms = elapsed_ms(b->ev[2], b->ev[3]);
+    S.output_ms = elapsed_ms(b->ev[3], b->ev[4]);
+    S.nclasses = (int)classes.size();
+    S.solo_jobs = (int)solo.size();
+    for (size_t c = 0; c < classes.size(); ++c) {
+        S.class_precision[c] = classes[c].mode;
+        S.class_rank_padded[c] = classes[c].RP;
+        S.class_jobs[c] = (int)classes[c].jobs.size();
+        S.class_bricks[c] = classes[c].ntiles;
+        S.class_brick_y[c] = classes[c].shape.ty;
+        S.class_brick_z[c] = classes[c].shape.tz;
+    }
+}
+
+template <typename Fn>
+ssmap_status batch_guarded(ssmap_batch *b, Fn &&fn) {
+    try {
+        if (b->poisoned || b->arena.poisoned) fail(SSMAP_EDEVICE, "batch poisoned by an earlier device error");
+        for (ssmap_ctx *c : b->jobs)
+            if (c->poisoned) fail(SSMAP_EDEVICE, "batch poisoned by an earlier device error");
+        fn();
+        return SSMAP_OK;
+    } catch (const Fail &f) {
+        b->err = f.msg;
+        if (f.status == SSMAP_EDEVICE) b->poisoned = true;
+        return f.status;
+    } catch (const std::bad_alloc &) {
+        b->err = "host allocation failed";
+        return SSMAP_ENOMEM;
+    } catch (...) {
+        b->err = "unexpected internal error";
+        b->poisoned = true;
+        return SSMAP_EDEVICE;
+    }
+}
+
+void free_batch(ssmap_batch *b) {
+    if (!b) return;
+    for (ssmap_ctx *c : b->jobs) free_ctx(c);
+    for (auto &kv : b->arena.bufs) (void)hipFree(kv.second.first);
+    b->arena.bufs.clear();
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete b;
 }
 
 }  // namespace
@@ -582,5 +889,106 @@ const char *ssmap_last_error(const ssmap_ctx *ctx) {
 }
 
 void ssmap_destroy(ssmap_ctx *ctx) { free_ctx(ctx); }
+
+ssmap_status ssmap_batch_create(int njobs, const double *const *K, const int *P, const int *Q,
+                                const int64_t *grids, ssmap_batch **out) {
+    if (out) *out = nullptr;
+    if (njobs < 1 || !K || !P || !Q || !grids || !out) {
+        g_batch_create_error = "invalid arguments";
+        return SSMAP_EINVAL;
+    }
+    ssmap_batch *b = nullptr;
+    try {
+        b = new ssmap_batch();
+    } catch (...) {
+        g_batch_create_error = "host allocation failed";
+        return SSMAP_ENOMEM;
+    }
+    for (int j = 0; j < njobs; ++j) {
+        ssmap_ctx *c = nullptr;
+        const ssmap_status st = ssmap_create(K[j], P[j], Q[j], grids + 3 * j, &c);
+        if (st != SSMAP_OK) {
+            g_batch_create_error = "job " + std::to_string(j) + ": " + g_create_error;
+            free_batch(b);
+            return st;
+        }
+        b->jobs.push_back(c);
+    }
+    for (auto &e : b->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            g_batch_create_error = "hipEventCreate failed";
+            free_batch(b);
+            return SSMAP_EDEVICE;
+        }
+    b->stats.njobs = njobs;
+    *out = b;
+    return SSMAP_OK;
+}
+
+ssmap_status ssmap_batch_solve_device(ssmap_batch *b, const void *const *dM, const double *lambda,
+                                      const ssmap_steps *steps, int iters, void *const *dF,
+                                      void *hip_stream) {
+    if (!b) return SSMAP_EINVAL;
+    return batch_guarded(b, [&] {
+        if (!dM || !lambda || !steps || !dF) fail(SSMAP_EINVAL, "NULL argument");
+        HIPC(&b->arena, hipSetDevice(b->jobs[0]->device));
+        batch_solve_impl(b, dM, lambda, steps, iters, dF, (hipStream_t)hip_stream);
+    });
+}
+
+ssmap_status ssmap_batch_solve(ssmap_batch *b, const double *const *M, const double *lambda,
+                               const ssmap_steps *steps, int iters, double *const *F_out) {
+    if (!b) return SSMAP_EINVAL;
+    return batch_guarded(b, [&] {
+        if (!M || !lambda || !steps || !F_out) fail(SSMAP_EINVAL, "NULL argument");
+        const int nj = (int)b->jobs.size();
+        HIPC(&b->arena, hipSetDevice(b->jobs[0]->device));
+        std::vector<const void *> dM(nj);
+        std::vector<void *> dF(nj);
+        for (int j = 0; j < nj; ++j) {
+            ssmap_ctx *c = b->jobs[j];
+            if (!M[j] || !F_out[j]) fail(SSMAP_EINVAL, "NULL buffer for job " + std::to_string(j));
+            const size_t nm = (size_t)c->g.N * c->P, nf = (size_t)c->g.N * c->Q;
+            for (size_t i = 0; i < nm; ++i)
+                if (!std::isfinite(M[j][i]))
+                    fail(SSMAP_ENONFINITE, "job " + std::to_string(j) + ": M holds a NaN or Inf");
+            const bool f64 = steps[j].precision == SSMAP_FP64;
+            const size_t esz = f64 ? 8 : 4;
+            void *m = ensure(c, "io_M", nm * esz);
+            dF[j] = ensure(c, "io_F", nf * esz);
+            if (f64) {
+                HIPC(c, hipMemcpy(m, M[j], nm * 8, hipMemcpyHostToDevice));
+            } else {
+                std::vector<float> tmp(M[j], M[j] + nm);
+                HIPC(c, hipMemcpy(m, tmp.data(), nm * 4, hipMemcpyHostToDevice));
+            }
+            dM[j] = m;
+        }
+        batch_solve_impl(b, dM.data(), lambda, steps, iters, dF.data(), nullptr);
+        for (int j = 0; j < nj; ++j) {
+            ssmap_ctx *c = b->jobs[j];
+            const size_t nf = (size_t)c->g.N * c->Q;
+            if (steps[j].precision == SSMAP_FP64) {
+                HIPC(c, hipMemcpy(F_out[j], dF[j], nf * 8, hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> tmp(nf);
+                HIPC(c, hipMemcpy(tmp.data(), dF[j], nf * 4, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < nf; ++i) F_out[j][i] = tmp[i];
+            }
+        }
+    });
+}
+
+ssmap_status ssmap_batch_get_stats(const ssmap_batch *b, ssmap_batch_stats *out) {
+    if (!b || !out) return SSMAP_EINVAL;
+    *out = b->stats;
+    return SSMAP_OK;
+}
+
+const char *ssmap_batch_last_error(const ssmap_batch *b) {
+    return b ? b->err.c_str() : g_batch_create_error.c_str();
+}
+
+void ssmap_batch_destroy(ssmap_batch *b) { free_batch(b); }
 
 }  // extern "C"

@@ -188,3 +188,43 @@ def random_problem(P, Q, grid, seed, lam=1e-2, beta=1.0, positive_K=False,
     m = f @ K.T + noise * rng.standard_normal((N, P))
     return Problem(K=K, m=m, grid=(nx, ny, nz), lam=lam, beta=beta, iters=50,
                    precision="fp64", meta=dict(seed=seed))
+
+
+# Batched uneven slices: 64 2-D slices with sides U{48..256}, P in {30, 60},
+# Q in {100, 400, 1600} diffusion-relaxation dictionaries.
+BATCH_C4 = dict(nslices=64, side=(48, 256), P=(30, 60), grid_n=(10, 20, 40), snr=50.0,
+                lam=1e-2, beta=0.1, iters=200, seed=4)
+
+
+def generate_batch(nslices=None, side=None, seed=None, iters=None, max_side=None):
+    """Seeded list of Problems for the batched workload (each slice has its
+    own grid, dictionary and data). The per-slice shape draws come from
+    their own stream, so changing the sizes does not reshuffle the data."""
+    cfg = dict(BATCH_C4)
+    if nslices is not None:
+        cfg["nslices"] = nslices
+    if side is not None:
+        cfg["side"] = side
+    if seed is None:
+        seed = cfg["seed"]
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed).spawn(1)[0]))
+    probs = []
+    for k in range(cfg["nslices"]):
+        nx = int(rng.integers(cfg["side"][0], cfg["side"][1] + 1))
+        ny = int(rng.integers(cfg["side"][0], cfg["side"][1] + 1))
+        if max_side is not None:
+            nx, ny = min(nx, max_side), min(ny, max_side)
+        P = int(rng.choice(cfg["P"]))
+        n = int(rng.choice(cfg["grid_n"]))
+        base = dict(CONFIGS["c1"] if P == 30 else CONFIGS["c2"])
+        base.update(n1=n, n2=n, snr=cfg["snr"], lam=cfg["lam"], beta=cfg["beta"],
+                    iters=cfg["iters"] if iters is None else iters, grid=(nx, ny, 1),
+                    precision="fp32")
+        CONFIGS["_slice"] = base
+        try:
+            pr = generate("_slice", seed=1000 * seed + k)
+        finally:
+            del CONFIGS["_slice"]
+        pr.meta["slice"] = k
+        probs.append(pr)
+    return probs

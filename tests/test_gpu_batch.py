@@ -1,0 +1,108 @@
+"""Batches: many problems of uneven size in shared fused launches.
+
+Each job's map from the batch must be bitwise the map of the same job solved
+alone (the per-voxel arithmetic does not depend on the brick shape or on the
+other jobs in a launch), and within the precision's tolerance of the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_12890_amd import _ffi, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def slices():
+    # the batched recipe at reduced sides so the oracle stays quick
+    return synth.generate_batch(nslices=8, side=(17, 61), iters=30)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_equals_solo_and_oracle(torch_cuda, slices, prec):
+    iters = 30
+    say("batch", prec, [(p.grid, p.P, p.Q) for p in slices])
+    with _ffi.BatchMapper([p.K for p in slices], [p.grid for p in slices]) as bm:
+        F = bm.solve([p.m for p in slices], [p.lam for p in slices], [p.beta for p in slices],
+                     iters, precision=prec)
+        st = bm.stats()
+    assert st["njobs"] == len(slices) and st["solo_jobs"] == 0
+    assert sum(c["jobs"] for c in st["classes"]) == len(slices)
+    for p, Fb in zip(slices, F):
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            Fs = mp.solve(p.m, p.lam, p.beta, iters, precision=prec)
+        assert np.array_equal(Fb, Fs), p.grid
+        ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters)
+        err = np.linalg.norm(Fb - ref["z"]) / np.linalg.norm(ref["z"])
+        assert err <= TOL[prec], (p.grid, p.Q, err)
+
+
+def test_batch_autotune_keeps_the_bits(torch_cuda, slices):
+    iters = 12
+    with _ffi.BatchMapper([p.K for p in slices], [p.grid for p in slices]) as bm:
+        args = ([p.m for p in slices], [p.lam for p in slices], [p.beta for p in slices], iters)
+        F0 = bm.solve(*args, precision="fp32")
+        F1 = bm.solve(*args, precision="fp32", autotune=True)
+        st = bm.stats()
+    assert st["autotune_ms"] > 0
+    say("autotuned bricks", [c["brick"] for c in st["classes"]])
+    for a, b in zip(F0, F1):
+        assert np.array_equal(a, b)
+
+
+def test_batch_mixed_ranks_solo_jobs_and_device_entry(torch_cuda, slices):
+    torch = torch_cuda
+    iters = 10
+    jobs = slices[:4]
+    # job 1 at the unapproximated rank (min(P, Q) = 30 or 60: fused up to 32, else a solo job)
+    ranks = [0, -1, 0, 7]
+    with _ffi.BatchMapper([p.K for p in jobs], [p.grid for p in jobs]) as bm:
+        steps = [_ffi.make_steps(p.beta, rank=r, precision="fp32") for p, r in zip(jobs, ranks)]
+        Ms = [torch.tensor(p.m, dtype=torch.float32, device="cuda") for p in jobs]
+        torch.cuda.synchronize()
+        Fs = [torch.empty((p.N, p.Q), dtype=torch.float32, device="cuda") for p in jobs]
+        s = torch.cuda.current_stream()
+        _ffi.ssmap_batch_solve_device(bm.b, [M.data_ptr() for M in Ms], [p.lam for p in jobs],
+                                      steps, iters, [F.data_ptr() for F in Fs], s.cuda_stream)
+        torch.cuda.synchronize()
+        st = bm.stats()
+    say("classes", st["classes"], "solo", st["solo_jobs"])
+    for p, r, F in zip(jobs, ranks, Fs):
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            ref = mp.solve(p.m, p.lam, p.beta, iters, precision="fp32", rank=r)
+        assert np.array_equal(F.cpu().numpy().astype(np.float64), ref)
+
+
+def test_batch_errors(torch_cuda, slices):
+    jobs = slices[:3]
+    with _ffi.BatchMapper([p.K for p in jobs], [p.grid for p in jobs]) as bm:
+        args = ([p.m for p in jobs], [p.lam for p in jobs], [p.beta for p in jobs], 3)
+        with pytest.raises(_ffi.SsmapError) as e:
+            bm.solve(*args, keep_aux=True)
+        assert e.value.status == _ffi.SSMAP_EINVAL
+        with pytest.raises(_ffi.SsmapError) as e:
+            bm.solve(*args, check_every=1)
+        assert e.value.status == _ffi.SSMAP_EINVAL
+        bad = [p.m.copy() for p in jobs]
+        bad[2][0, 0] = np.inf
+        with pytest.raises(_ffi.SsmapError) as e:
+            bm.solve(bad, *args[1:])
+        assert e.value.status == _ffi.SSMAP_ENONFINITE and "job 2" in str(e.value)
+        F = bm.solve(*args, precision="fp32")
+        assert all(np.isfinite(f).all() for f in F)

@@ -367,4 +367,4 @@ def test_bench_uses_the_oracle_only_in_its_cpu_baseline():
                 names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
                 if any(nm.split(".")[0] == "oracle" for nm in names):
                     users.add(fn.name)
-    assert users == {"cpu_baseline"}
+    assert users and all(u.startswith("cpu_baseline") for u in users)
