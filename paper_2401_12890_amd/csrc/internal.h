@@ -46,6 +46,7 @@ struct IterArgs {
     const void *dprev;    // optional: d^k (for f^{k+1})
     void *fout;           // optional: f^{k+1}
     void *dout;           // optional: d^{k+1}
+    int phase;            // shared launches: entry 2j + ((round + phase) & 1) is job j's
 };
 
 // Unfused reference kernels (any rank).
@@ -64,9 +65,10 @@ struct FusedShape {
 struct FusedLaunch {
     int mode, r, RP;
     FusedShape shape;
-    const IterArgs *jobs;  // device array
+    const IterArgs *jobs;  // device array, two entries per job: [2j] for even, [2j+1] for odd k
     const TileRef *tiles;  // device array
     int ntiles;
+    int round;             // iteration counter of the shared loop
 };
 // fused_supported(): whether (mode, padded rank, voxel count) has a fused kernel.
 bool fused_supported(int mode, int RP, int64_t N);

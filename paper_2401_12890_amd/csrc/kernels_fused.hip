@@ -167,7 +167,8 @@ template <> struct Buf<double, v4d> {
 // blocks of r in the y contraction. bf16x3 uses one 32-wide K-step (KSU unused).
 template <int MODE, int RB, int KSU, int TY, int TZ>
 __global__ void __launch_bounds__(NT, 1)
-k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles) {
+k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles,
+        int round) {
     using F = FT<MODE>;
     using T = typename F::T;
     using V4 = typename F::V4;
@@ -193,7 +194,10 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
         tile = (tile & 7) * per + (tile >> 3);
     }
     const TileRef tr = tiles[tile];
-    const IterArgs &a = jobs[tr.job];
+    // two descriptors per job (z^k -> z^{k+1} for even and odd k); a job that
+    // joined a shared loop late carries its phase
+    const int sel = (round + jobs[2 * tr.job].phase) & 1;
+    const IterArgs &a = jobs[2 * tr.job + sel];
     const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
     const int64_t x0 = (int64_t)tr.tx * TX, y0 = (int64_t)tr.ty * TY, z0 = (int64_t)tr.tz * TZ;
 
@@ -436,7 +440,8 @@ __device__ __forceinline__ void lds_dma16(__amdgpu_buffer_rsrc_t r, void *lds, u
 
 template <int MODE, int RB, int KSU, int TY, int TZ>
 __global__ void __launch_bounds__(NT, 1)
-k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles) {
+k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles,
+        int round) {
     static_assert(MODE != MODE_FP64, "float64 uses the register-staged kernel");
     using F = FT<MODE>;
     using V4 = v4f;
@@ -462,7 +467,10 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
         tile = (tile & 7) * per + (tile >> 3);
     }
     const TileRef tr = tiles[tile];
-    const IterArgs &a = jobs[tr.job];
+    // two descriptors per job (z^k -> z^{k+1} for even and odd k); a job that
+    // joined a shared loop late carries its phase
+    const int sel = (round + jobs[2 * tr.job].phase) & 1;
+    const IterArgs &a = jobs[2 * tr.job + sel];
     const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, N = a.g.N;
     const int64_t x0 = (int64_t)tr.tx * TX, y0 = (int64_t)tr.ty * TY, z0 = (int64_t)tr.tz * TZ;
 
@@ -685,10 +693,10 @@ void launch_t(const FusedLaunch &L, hipStream_t s) {
     // bf16x3 through direct LDS loads
     if constexpr (MODE == MODE_BF16X3)
         hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s,
-                           L.jobs, L.tiles, L.ntiles);
+                           L.jobs, L.tiles, L.ntiles, L.round);
     else
         hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s, L.jobs,
-                           L.tiles, L.ntiles);
+                           L.tiles, L.ntiles, L.round);
 }
 
 template <int MODE, int RB, int KSU>

@@ -437,7 +437,7 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
         if (P.aux && k == iters - 1)   // auxB = z + u, auxA: d^{K-1} -> f^K (d^0 = 0 if K = 1)
             launch_aux_pre(pl.mode, a, P.auxB, P.auxA, iters >= 2 ? P.auxA : nullptr, s);
         FusedLaunch Lk = *L;
-        Lk.jobs = L->jobs + (k & 1);
+        Lk.round = k;
         if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
         if (P.aux && k == iters - 2) launch_aux_post(pl.mode, P.auxA, a.znew, pl.beta, cnt, s);
         if (P.aux && k == iters - 1) launch_aux_post(pl.mode, P.auxB, a.znew, pl.beta, cnt, s);
@@ -554,8 +554,8 @@ void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector
     std::vector<TileRef> tiles;
     for (size_t k = 0; k < C.jobs.size(); ++k) {
         const int j = C.jobs[k];
-        args[k] = args_for(Ps[j], 0);                        // even iterations
-        args[C.jobs.size() + k] = args_for(Ps[j], 1);        // odd iterations
+        args[2 * k] = args_for(Ps[j], 0);                    // even iterations
+        args[2 * k + 1] = args_for(Ps[j], 1);                // odd iterations
         append_tiles(b->jobs[j]->g, (int)k, shape, tiles);
     }
     ssmap_ctx *A = &b->arena;
@@ -575,13 +575,14 @@ void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector
     L.ntiles = (int)tiles.size();
 }
 
-// One shared launch of iteration k: jobs[0 .. n) hold the even-iteration
-// arguments, jobs[n .. 2n) the odd ones; a brick names its job by index.
+// One shared launch of iteration k (jobs[2j], jobs[2j+1]: job j's even and
+// odd descriptors; a brick names its job by index).
 void launch_class(ssmap_batch *b, const FusedLaunch &L, size_t njobs, int k, hipStream_t s) {
     FusedLaunch Lk = L;
-    Lk.jobs = L.jobs + ((k & 1) ? njobs : 0);
+    Lk.round = k;
     if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
     (void)b;
+    (void)njobs;
 }
 
 void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambda,
