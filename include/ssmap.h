@@ -228,6 +228,88 @@ const char *ssmap_batch_last_error(const ssmap_batch *b);
 /* Release the batch, its contexts and device memory. NULL is a no-op. */
 void ssmap_batch_destroy(ssmap_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Serving: independent mapping jobs arriving over time (the per-job problem
+ * of Eq. (spat) solved by Algorithm 2 for a fixed iteration count). A job's
+ * state (z ping-pong and its r-vectors) stays in device memory from
+ * admission to retirement. Admission is first in, first out under a device-
+ * memory budget reserved at creation; a job that does not fit waits, and so
+ * do the jobs behind it. Running jobs of one class (precision, padded rank,
+ * u K-step bucket, brick shape) advance together, one iteration per shared
+ * fused launch; a job joins its class at an iteration boundary and leaves
+ * after its last iteration while the others keep running (continuous
+ * batching). Classes are spread over up to four HIP streams and progress
+ * independently of one another. A served job's result is exactly that of
+ * ssmap_solve_device with kernel SSMAP_KERNEL_FUSED on the same input (same
+ * kernels, same arithmetic order). A server is not thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct ssmap_server ssmap_server;
+
+typedef struct {
+    double hbm_budget;      /* bytes of device memory for job state, reserved at create (>= 256) */
+    int streams;            /* HIP streams the classes are spread over, 1..4 (0 -> 4)           */
+    int reserved[3];
+} ssmap_server_opts;
+
+enum { SSMAP_JOB_QUEUED = 0, SSMAP_JOB_RUNNING = 1, SSMAP_JOB_DONE = 2 };
+
+typedef struct {
+    int state;              /* SSMAP_JOB_*                                                        */
+    int status;             /* SSMAP_OK, or SSMAP_ENONFINITE when M held a NaN or Inf (F undefined) */
+    int rank, rank_padded, precision, iters;
+    double xi_p;
+    double state_bytes;     /* device bytes the job holds while running                          */
+    double submit_ms;       /* host clock at submit, ms since ssmap_server_create                 */
+    double admit_ms;        /* host clock when the job's first kernels were enqueued              */
+    double done_ms;         /* device clock (event) when F was complete; valid once SSMAP_JOB_DONE */
+} ssmap_job_info;
+
+typedef struct {
+    int64_t submitted, admitted, completed;
+    int64_t launches;       /* shared fused launches enqueued                                     */
+    int classes, streams;
+    double budget_bytes, in_use_bytes, peak_bytes;
+    double voxel_iterations;   /* sum of N * iters over completed jobs                           */
+} ssmap_server_stats;
+
+/* Reserve the budget and create the streams on the current device. */
+ssmap_status ssmap_server_create(const ssmap_server_opts *opts, ssmap_server **out);
+
+/* Factor a dictionary once (K: P*Q float64 row-major, copied; thin SVD on the
+ * host) for every job that names it; returns its id through *dict_id. */
+ssmap_status ssmap_server_add_dictionary(ssmap_server *sv, const double *K, int P, int Q,
+                                         int *dict_id);
+
+/* Queue a job on dictionary dict_id and grid {nx, ny, nz}. dM (N*P,
+ * voxel-major) and dF (N*Q, voxel-major; receives z^iters) are device buffers
+ * in the precision's I/O type (float64 for SSMAP_FP64, else float32), borrowed
+ * until the job is done. lambda, steps and iters as in ssmap_solve, with
+ * steps->check_every = 0, steps->flags = 0 and kernel AUTO or FUSED; EINVAL
+ * when no fused kernel covers the precision, rank and size; ENOMEM when the
+ * job alone needs more than the budget. Returns the job id. */
+ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t grid[3],
+                                 const void *dM, double lambda, const ssmap_steps *steps,
+                                 int iters, void *dF, int64_t *job_id);
+
+/* Admit the queued jobs that fit, then enqueue about horizon_ms of iterations
+ * for every class. Asynchronous: the host blocks only to keep at most two such
+ * chunks per class in flight. *n_pending (may be NULL) = jobs not yet done. */
+ssmap_status ssmap_server_pump(ssmap_server *sv, double horizon_ms, int *n_pending);
+
+/* State, status and timings of one job. */
+ssmap_status ssmap_server_poll(ssmap_server *sv, int64_t job_id, ssmap_job_info *out);
+
+/* Pump until every submitted job is done and the device work has finished. */
+ssmap_status ssmap_server_drain(ssmap_server *sv);
+
+ssmap_status ssmap_server_get_stats(const ssmap_server *sv, ssmap_server_stats *out);
+
+/* Message for the last failure on sv (or of the last failed ssmap_server_create when sv is NULL). */
+const char *ssmap_server_last_error(const ssmap_server *sv);
+
+/* Wait for the device work, then release the server and its memory. NULL is a no-op. */
+void ssmap_server_destroy(ssmap_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

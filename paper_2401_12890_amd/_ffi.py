@@ -31,7 +31,10 @@ EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_get_aux",
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
            "ssmap_destroy", "ssmap_version",
            "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
-           "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy"]
+           "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy",
+           "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
+           "ssmap_server_pump", "ssmap_server_poll", "ssmap_server_drain",
+           "ssmap_server_get_stats", "ssmap_server_last_error", "ssmap_server_destroy"]
 SSMAP_AUTOTUNE = 2
 MAX_CLASSES = 16
 
@@ -66,6 +69,30 @@ class BatchStats(ctypes.Structure):
                 ("class_bricks", ctypes.c_int * MAX_CLASSES),
                 ("class_brick_y", ctypes.c_int * MAX_CLASSES),
                 ("class_brick_z", ctypes.c_int * MAX_CLASSES)]
+
+
+JOB_STATES = {0: "queued", 1: "running", 2: "done"}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_double), ("streams", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("rank", ctypes.c_int),
+                ("rank_padded", ctypes.c_int), ("precision", ctypes.c_int), ("iters", ctypes.c_int),
+                ("xi_p", ctypes.c_double), ("state_bytes", ctypes.c_double),
+                ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("classes", ctypes.c_int), ("streams", ctypes.c_int),
+                ("budget_bytes", ctypes.c_double), ("in_use_bytes", ctypes.c_double),
+                ("peak_bytes", ctypes.c_double), ("voxel_iterations", ctypes.c_double)]
 
 
 class SsmapError(RuntimeError):
@@ -120,6 +147,26 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_batch_last_error.restype = ctypes.c_char_p
     lib.ssmap_batch_destroy.argtypes = [vp]
     lib.ssmap_batch_destroy.restype = None
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.ssmap_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.ssmap_server_create.restype = ip
+    lib.ssmap_server_add_dictionary.argtypes = [vp, dp, ip, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.ssmap_server_add_dictionary.restype = ip
+    lib.ssmap_server_submit.argtypes = [vp, ip, i64p, vp, ctypes.c_double, ctypes.POINTER(Steps),
+                                        ip, vp, i64p]
+    lib.ssmap_server_submit.restype = ip
+    lib.ssmap_server_pump.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+    lib.ssmap_server_pump.restype = ip
+    lib.ssmap_server_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(JobInfo)]
+    lib.ssmap_server_poll.restype = ip
+    lib.ssmap_server_drain.argtypes = [vp]
+    lib.ssmap_server_drain.restype = ip
+    lib.ssmap_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.ssmap_server_get_stats.restype = ip
+    lib.ssmap_server_last_error.argtypes = [vp]
+    lib.ssmap_server_last_error.restype = ctypes.c_char_p
+    lib.ssmap_server_destroy.argtypes = [vp]
+    lib.ssmap_server_destroy.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -373,6 +420,150 @@ class BatchMapper:
         if self.b:
             ssmap_batch_destroy(self.b)
             self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+def _scheck(sv, st):
+    if st != SSMAP_OK:
+        raise SsmapError(st, load().ssmap_server_last_error(sv).decode())
+
+
+def ssmap_server_create(hbm_budget: float, streams: int = 0) -> int:
+    lib = load()
+    opts = ServerOpts(float(hbm_budget), int(streams))
+    out = ctypes.c_void_p()
+    st = lib.ssmap_server_create(ctypes.byref(opts), ctypes.byref(out))
+    if st != SSMAP_OK:
+        raise SsmapError(st, lib.ssmap_server_last_error(None).decode())
+    return out.value
+
+
+def ssmap_server_add_dictionary(sv, K: np.ndarray) -> int:
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    d = ctypes.c_int()
+    _scheck(sv, load().ssmap_server_add_dictionary(sv, _dptr(K), K.shape[0], K.shape[1],
+                                                    ctypes.byref(d)))
+    return d.value
+
+
+def ssmap_server_submit(sv, dict_id, grid, dM, lam, steps, iters, dF) -> int:
+    g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    jid = ctypes.c_int64()
+    _scheck(sv, load().ssmap_server_submit(sv, int(dict_id), g, ctypes.c_void_p(dM), float(lam),
+                                           ctypes.byref(steps), int(iters), ctypes.c_void_p(dF),
+                                           ctypes.byref(jid)))
+    return jid.value
+
+
+def ssmap_server_pump(sv, horizon_ms: float) -> int:
+    n = ctypes.c_int()
+    _scheck(sv, load().ssmap_server_pump(sv, float(horizon_ms), ctypes.byref(n)))
+    return n.value
+
+
+def ssmap_server_poll(sv, job_id) -> dict:
+    i = JobInfo()
+    _scheck(sv, load().ssmap_server_poll(sv, int(job_id), ctypes.byref(i)))
+    return dict(state=JOB_STATES[i.state], status=i.status, rank=i.rank,
+                rank_padded=i.rank_padded, precision=i.precision, iters=i.iters, xi_p=i.xi_p,
+                state_bytes=i.state_bytes, submit_ms=i.submit_ms, admit_ms=i.admit_ms,
+                done_ms=i.done_ms)
+
+
+def ssmap_server_drain(sv) -> None:
+    _scheck(sv, load().ssmap_server_drain(sv))
+
+
+def ssmap_server_get_stats(sv) -> dict:
+    s = ServerStats()
+    _scheck(sv, load().ssmap_server_get_stats(sv, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+
+def ssmap_server_last_error(sv) -> str:
+    return load().ssmap_server_last_error(sv).decode()
+
+
+def ssmap_server_destroy(sv) -> None:
+    load().ssmap_server_destroy(sv)
+
+
+class Server:
+    """Served jobs on device tensors (owns an ssmap server). Keeps each job's
+    M and F tensors alive until the job is done."""
+
+    def __init__(self, hbm_budget: float, streams: int = 0):
+        self.sv = ssmap_server_create(hbm_budget, streams)
+        self.dicts = {}
+        self.live = {}
+
+    def add_dictionary(self, K: np.ndarray) -> int:
+        d = ssmap_server_add_dictionary(self.sv, K)
+        self.dicts[d] = np.asarray(K).shape
+        return d
+
+    def submit(self, dict_id, grid, M, lam, beta, iters, F=None, ready=False, **kw) -> int:
+        """Queue a job on device tensor M (N, P), float64 for fp64 and float32
+        otherwise; returns its id. Unless `ready`, the current torch stream is
+        synchronized first so that M is complete when the server reads it."""
+        import torch
+        P, Q = self.dicts[dict_id]
+        N = int(grid[0]) * int(grid[1]) * int(grid[2])
+        steps = make_steps(beta, **kw)
+        dt = torch.float64 if steps.precision == 0 else torch.float32
+        if not (M.is_cuda and M.is_contiguous() and M.dtype == dt and tuple(M.shape) == (N, P)):
+            raise ValueError(f"M must be a contiguous (N, P) device tensor of {dt}")
+        if F is None:
+            F = torch.empty((N, Q), dtype=dt, device=M.device)
+        if not (F.is_cuda and F.is_contiguous() and F.dtype == dt and tuple(F.shape) == (N, Q)):
+            raise ValueError(f"F must be a contiguous (N, Q) device tensor of {dt}")
+        if not ready:
+            torch.cuda.current_stream(M.device).synchronize()
+        jid = ssmap_server_submit(self.sv, dict_id, grid, M.data_ptr(), lam, steps, iters,
+                                  F.data_ptr())
+        self.live[jid] = (M, F)
+        return jid
+
+    def pump(self, horizon_ms: float = 5.0) -> int:
+        return ssmap_server_pump(self.sv, horizon_ms)
+
+    def poll(self, job_id) -> dict:
+        info = ssmap_server_poll(self.sv, job_id)
+        return info
+
+    def result(self, job_id):
+        """F of a finished job (None while it runs); releases the job's tensors."""
+        info = ssmap_server_poll(self.sv, job_id)
+        if info["state"] != "done":
+            return None
+        if info["status"] != SSMAP_OK:
+            raise SsmapError(info["status"], f"job {job_id} failed")
+        M, F = self.live.pop(job_id)
+        return F
+
+    def drain(self) -> None:
+        ssmap_server_drain(self.sv)
+
+    def stats(self) -> dict:
+        return ssmap_server_get_stats(self.sv)
+
+    def close(self):
+        if self.sv:
+            ssmap_server_destroy(self.sv)
+            self.sv = None
+            self.live.clear()
 
     def __enter__(self):
         return self

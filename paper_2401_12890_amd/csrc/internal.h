@@ -108,6 +108,29 @@ int monitor_blocks(int64_t N);
 void launch_output(int mode, const void *z, void *F, int Q, int64_t N, bool to_double,
                    hipStream_t s);
 
+// ---- host-side plan rules shared by the solver and the server
+constexpr double kEpsXi = 1e-10;      // epsilon of Eq. (sigma_cond)
+constexpr double kXiFactor = 0.75;    // xi_p > 0.75 lambda ||D^T D|| (Sec. III-F)
+constexpr double kRankTol = 5e-5;     // 0.005 % Frobenius error (Sec. III-F)
+
+// Rank rule of Sec. III-F: rank > 0 is taken as given, -1 means min(P, Q),
+// 0 the smallest r with ||K - K_r||_F < kRankTol ||K||_F (strict).
+int rank_rule(const std::vector<double> &s, int rank);
+// ||D^T D||_2 of the face-neighbour box grid with free boundary (D^T D = 2L).
+double dtd_norm_closed(const Grid &g);
+
+// Solve constants of one (dictionary, precision, rank, beta): float64 copies
+// (V_r padded to Qp x RP, U_r P x r, singular values and a_i padded to RP)
+// and byte images in the mode's state type (V, b_i, fused V operand blocks;
+// Vop is empty unless `fused`).
+struct HostConsts {
+    std::vector<double> Vh, Ur, sig, a;
+    std::vector<uint8_t> V, b, Vop;
+};
+void host_consts(int mode, const std::vector<double> &U, const std::vector<double> &s,
+                 const std::vector<double> &V, int kmin, int P, int Q, int Qp, int r, int RP,
+                 double beta, bool fused, HostConsts &out);
+
 // Fill a device array of `count` elements of `elem_bytes` (4 or 8) with zero.
 void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s);
 

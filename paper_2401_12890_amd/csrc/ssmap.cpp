@@ -18,11 +18,80 @@
 
 using namespace ssmap;
 
-namespace {
+namespace ssmap {
 
-constexpr double kEpsXi = 1e-10;      // epsilon of Eq. (sigma_cond)
-constexpr double kXiFactor = 0.75;    // xi_p > 0.75 lambda ||D^T D|| (Sec. III-F)
-constexpr double kRankTol = 5e-5;     // 0.005 % Frobenius error (Sec. III-F)
+int rank_rule(const std::vector<double> &s, int rank) {
+    const int k = (int)s.size();
+    if (rank == -1) return k;
+    if (rank > 0) return rank;
+    // tails from the end: tail[r] = sum_{i >= r} s_i^2
+    std::vector<double> tail(k + 1, 0.0);
+    for (int i = k - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
+    const double total = tail[0];
+    for (int r = 1; r <= k; ++r)
+        if (std::sqrt(tail[r]) < kRankTol * std::sqrt(total)) return r;
+    return k;
+}
+
+double dtd_norm_closed(const Grid &g) {
+    // D^T D = 2 (L_x (+) L_y (+) L_z); a path of n voxels has largest
+    // Laplacian eigenvalue 2 + 2 cos(pi / n) (0 when n = 1).
+    double lam = 0.0;
+    for (int64_t n : {g.nx, g.ny, g.nz})
+        if (n > 1) lam += 2.0 + 2.0 * std::cos(M_PI / (double)n);
+    return 2.0 * lam;
+}
+
+// Solve constants of one (dictionary, precision, rank, beta) in float64 and in
+// the state type of the mode: a_i = 1/(beta + s_i^2), b_i = s_i^2/(beta + s_i^2)
+// (the 1/beta - s_i and beta s_i of Eq. (DictVecSVD)), V_r zero-padded to
+// Qp x RP, U_r, the singular values, and the fused kernel's V operand blocks.
+void host_consts(int mode, const std::vector<double> &U, const std::vector<double> &s,
+                 const std::vector<double> &V, int kmin, int P, int Q, int Qp, int r, int RP,
+                 double beta, bool fused, HostConsts &out) {
+    out.Vh.assign((size_t)Qp * RP, 0.0);
+    out.Ur.assign((size_t)P * r, 0.0);
+    out.sig.assign(RP, 0.0);
+    out.a.assign(RP, 0.0);
+    std::vector<double> bh(RP, 0.0);
+    for (int q = 0; q < Q; ++q)
+        for (int i = 0; i < r; ++i) out.Vh[(size_t)q * RP + i] = V[(size_t)q * kmin + i];
+    for (int p = 0; p < P; ++p)
+        for (int i = 0; i < r; ++i) out.Ur[(size_t)p * r + i] = U[(size_t)p * kmin + i];
+    for (int i = 0; i < r; ++i) {
+        const double s2 = s[i] * s[i];
+        out.sig[i] = s[i];
+        out.a[i] = 1.0 / (beta + s2);
+        bh[i] = s2 / (beta + s2);
+    }
+    auto as_bytes = [](const auto &v, std::vector<uint8_t> &dst) {
+        dst.resize(v.size() * sizeof(v[0]));
+        if (!v.empty()) std::memcpy(dst.data(), v.data(), dst.size());
+    };
+    out.Vop.clear();
+    if (mode == MODE_FP64) {
+        as_bytes(out.Vh, out.V);
+        as_bytes(bh, out.b);
+    } else {
+        as_bytes(std::vector<float>(out.Vh.begin(), out.Vh.end()), out.V);
+        as_bytes(std::vector<float>(bh.begin(), bh.end()), out.b);
+    }
+    if (!fused) return;
+    if (mode == MODE_BF16X3) {
+        std::vector<uint16_t> v16;
+        fused_operands_bf16(out.Vh, Qp, RP, v16);
+        as_bytes(v16, out.Vop);
+    } else {
+        std::vector<double> v64;
+        fused_operands(out.Vh, Qp, RP, mode == MODE_FP64, v64);
+        if (mode == MODE_FP64) as_bytes(v64, out.Vop);
+        else as_bytes(std::vector<float>(v64.begin(), v64.end()), out.Vop);
+    }
+}
+
+}  // namespace ssmap
+
+namespace {
 
 struct Fail {
     ssmap_status status;
@@ -114,28 +183,6 @@ void plan_check(ssmap_ctx *c, const std::vector<std::pair<std::string, size_t>> 
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && extra > freeb)
         fail(SSMAP_ENOMEM, "solve needs " + std::to_string(extra) + " more device bytes than free");
-}
-
-int rank_rule(const std::vector<double> &s, int rank) {
-    const int k = (int)s.size();
-    if (rank == -1) return k;
-    if (rank > 0) return rank;
-    // tails from the end: tail[r] = sum_{i >= r} s_i^2
-    std::vector<double> tail(k + 1, 0.0);
-    for (int i = k - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
-    const double total = tail[0];
-    for (int r = 1; r <= k; ++r)
-        if (std::sqrt(tail[r]) < kRankTol * std::sqrt(total)) return r;
-    return k;
-}
-
-double dtd_norm_closed(const Grid &g) {
-    // D^T D = 2 (L_x (+) L_y (+) L_z); a path of n voxels has largest
-    // Laplacian eigenvalue 2 + 2 cos(pi / n) (0 when n = 1).
-    double lam = 0.0;
-    for (int64_t n : {g.nx, g.ny, g.nz})
-        if (n > 1) lam += 2.0 + 2.0 * std::cos(M_PI / (double)n);
-    return 2.0 * lam;
 }
 
 struct Plan {
@@ -270,31 +317,13 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     double *acoef = (double *)ensure(c, "acoef", (size_t)RP * 8);
 
     // ---- per-solve coefficients (float64 on the host), Sec. III-F rules
-    std::vector<double> Vh((size_t)Qp * RP, 0.0), Urh((size_t)Pm * r), sh(RP, 0.0), ah_(RP, 0.0),
-        bh(RP, 0.0);
-    for (int q = 0; q < Q; ++q)
-        for (int i = 0; i < r; ++i) Vh[(size_t)q * RP + i] = c->V[(size_t)q * c->kmin + i];
-    for (int p = 0; p < Pm; ++p)
-        for (int i = 0; i < r; ++i) Urh[(size_t)p * r + i] = c->U[(size_t)p * c->kmin + i];
-    for (int i = 0; i < r; ++i) {
-        const double s2 = c->s[i] * c->s[i];
-        sh[i] = c->s[i];
-        ah_[i] = 1.0 / (pl.beta + s2);        // 1/beta - s_i of Eq. (DictVecSVD)
-        bh[i] = s2 / (pl.beta + s2);          // beta * s_i of Eq. (DictVecSVD)
-    }
-    std::vector<float> Vf, bf;
-    if (pl.mode == MODE_FP64) {
-        HIPC(c, hipMemcpyAsync(Vd, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
-        HIPC(c, hipMemcpyAsync(bd, bh.data(), RP * 8, hipMemcpyHostToDevice, s));
-    } else {
-        Vf.assign(Vh.begin(), Vh.end());
-        bf.assign(bh.begin(), bh.end());
-        HIPC(c, hipMemcpyAsync(Vd, Vf.data(), Vf.size() * 4, hipMemcpyHostToDevice, s));
-        HIPC(c, hipMemcpyAsync(bd, bf.data(), RP * 4, hipMemcpyHostToDevice, s));
-    }
-    HIPC(c, hipMemcpyAsync(Ur, Urh.data(), Urh.size() * 8, hipMemcpyHostToDevice, s));
-    HIPC(c, hipMemcpyAsync(P.sig, sh.data(), RP * 8, hipMemcpyHostToDevice, s));
-    HIPC(c, hipMemcpyAsync(acoef, ah_.data(), RP * 8, hipMemcpyHostToDevice, s));
+    HostConsts hc;
+    host_consts(pl.mode, c->U, c->s, c->V, c->kmin, Pm, Q, Qp, r, RP, pl.beta, pl.fused, hc);
+    HIPC(c, hipMemcpyAsync(Vd, hc.V.data(), hc.V.size(), hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(bd, hc.b.data(), hc.b.size(), hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(Ur, hc.Ur.data(), hc.Ur.size() * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(P.sig, hc.sig.data(), RP * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(acoef, hc.a.data(), RP * 8, hipMemcpyHostToDevice, s));
     void *Vhi = nullptr, *Vlo = nullptr;
     if (pl.mode == MODE_BF16X3) {
         Vhi = ensure(c, "Vhi", (size_t)Qp * RP * 2);
@@ -302,26 +331,13 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         launch_split_bf16((const float *)Vd, (uint16_t *)Vhi, (uint16_t *)Vlo, (size_t)Qp * RP, s);
     }
     void *Vop = nullptr;
-    std::vector<uint16_t> Vop16;
-    std::vector<double> Vop64;
-    std::vector<float> Vop32;
-    if (pl.fused && pl.mode == MODE_BF16X3) {
-        fused_operands_bf16(Vh, Qp, RP, Vop16);
-        Vop = ensure(c, "Vop", Vop16.size() * 2);
-        HIPC(c, hipMemcpyAsync(Vop, Vop16.data(), Vop16.size() * 2, hipMemcpyHostToDevice, s));
-    } else if (pl.fused) {
-        fused_operands(Vh, Qp, RP, pl.mode == MODE_FP64, Vop64);
-        Vop = ensure(c, "Vop", Vop64.size() * esz);
-        if (pl.mode == MODE_FP64) {
-            HIPC(c, hipMemcpyAsync(Vop, Vop64.data(), Vop64.size() * 8, hipMemcpyHostToDevice, s));
-        } else {
-            Vop32.assign(Vop64.begin(), Vop64.end());
-            HIPC(c, hipMemcpyAsync(Vop, Vop32.data(), Vop32.size() * 4, hipMemcpyHostToDevice, s));
-        }
+    if (pl.fused) {
+        Vop = ensure(c, "Vop", hc.Vop.size());
+        HIPC(c, hipMemcpyAsync(Vop, hc.Vop.data(), hc.Vop.size(), hipMemcpyHostToDevice, s));
     }
     if (P.monitor) {
         P.V64 = (double *)ensure(c, "V64", (size_t)Qp * RP * 8);
-        HIPC(c, hipMemcpyAsync(P.V64, Vh.data(), Vh.size() * 8, hipMemcpyHostToDevice, s));
+        HIPC(c, hipMemcpyAsync(P.V64, hc.Vh.data(), hc.Vh.size() * 8, hipMemcpyHostToDevice, s));
         P.t = (double *)ensure(c, "t", (size_t)r * N * 8);
         P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
         P.partial = (double *)ensure(c, "partial", (size_t)2048 * ST_COUNT * 8);

@@ -58,3 +58,23 @@ def test_argument_errors_before_any_device_work():
     assert e.value.status == _ffi.SSMAP_ENONFINITE
     lib.ssmap_destroy(None)                      # NULL is a no-op
     assert lib.ssmap_solve(None, None, 0.0, None, 0, None) == _ffi.SSMAP_EINVAL
+
+
+def test_server_structs_and_argument_errors():
+    import ctypes
+    # ssmap_server_opts: double + 4 ints; ssmap_job_info: 6 ints + 5 doubles;
+    # ssmap_server_stats: 4 int64 + 2 ints + 4 doubles
+    assert ctypes.sizeof(_ffi.ServerOpts) == 8 + 4 * 4
+    assert ctypes.sizeof(_ffi.JobInfo) == 6 * 4 + 5 * 8
+    assert ctypes.sizeof(_ffi.ServerStats) == 4 * 8 + 2 * 4 + 4 * 8
+    lib = _ffi.load()
+    for budget, streams in [(0.0, 0), (float("nan"), 0), (1e9, 5), (1e9, -1)]:
+        with pytest.raises(_ffi.SsmapError) as e:
+            _ffi.ssmap_server_create(budget, streams)
+        assert e.value.status == _ffi.SSMAP_EINVAL
+    assert lib.ssmap_server_create(None, None) == _ffi.SSMAP_EINVAL
+    lib.ssmap_server_destroy(None)               # NULL is a no-op
+    assert lib.ssmap_server_pump(None, 1.0, None) == _ffi.SSMAP_EINVAL
+    assert lib.ssmap_server_drain(None) == _ffi.SSMAP_EINVAL
+    assert lib.ssmap_server_poll(None, 0, None) == _ffi.SSMAP_EINVAL
+    assert lib.ssmap_server_get_stats(None, None) == _ffi.SSMAP_EINVAL

@@ -1,0 +1,185 @@
+"""Serving: jobs arriving over time, admitted under a device-memory budget and
+advanced together in shared fused launches (continuous batching).
+
+A served job's map must be bitwise the map of the same job solved alone with
+the fused kernel (the per-voxel arithmetic does not depend on which other jobs
+share a launch, on the round a job joins at, or on the stream), and within
+the precision's tolerance of the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_12890_amd import _ffi, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}
+TORCH_T = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def jobs():
+    """(problem, precision, iters): planar slices of the batched recipe plus
+    volumetric crops of the three configuration generators, ragged sizes."""
+    out = []
+    for k, p in enumerate(synth.generate_batch(nslices=6, side=(17, 45), iters=25)):
+        out.append((p, "fp32" if k % 2 == 0 else "bf16x3", 20 + 3 * k))
+    out.append((synth.generate("c1", grid=(20, 13, 1)), "fp64", 31))
+    out.append((synth.generate("c2", grid=(19, 11, 5)), "fp32", 17))
+    out.append((synth.generate("c3", grid=(13, 9, 6)), "bf16x3", 14))
+    out.append((synth.generate("c1", grid=(9, 7, 5)), "fp64", 22))
+    return out
+
+
+@pytest.fixture(scope="module")
+def solo(torch_cuda, jobs):
+    """Each job solved alone through the single-problem entry point."""
+    torch = torch_cuda
+    refs = []
+    for p, prec, iters in jobs:
+        M = torch.tensor(p.m, dtype=getattr(torch, TORCH_T[prec]), device="cuda")
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            F = mp.solve_torch(M, p.lam, p.beta, iters, precision=prec, kernel="fused")
+            torch.cuda.synchronize()
+        refs.append(F)
+    return refs
+
+
+def device_inputs(torch, jobs):
+    Ms = [torch.tensor(p.m, dtype=getattr(torch, TORCH_T[prec]), device="cuda")
+          for p, prec, _ in jobs]
+    torch.cuda.synchronize()
+    return Ms
+
+
+def serve(torch, jobs, budget, streams, stagger):
+    """Submit the jobs (half, then the rest after a few pumps when staggered),
+    drain, return the maps, the job infos and the server stats."""
+    Ms = device_inputs(torch, jobs)
+    with _ffi.Server(budget, streams) as sv:
+        dict_of = {}
+        ids = []
+        for j, ((p, prec, iters), M) in enumerate(zip(jobs, Ms)):
+            key = id(p.K)
+            if key not in dict_of:
+                dict_of[key] = sv.add_dictionary(p.K)
+            ids.append(sv.submit(dict_of[key], p.grid, M, p.lam, p.beta, iters, ready=True,
+                                 precision=prec))
+            if stagger and j == len(jobs) // 2:
+                for _ in range(3):
+                    sv.pump(0.2)
+        sv.drain()
+        infos = [sv.poll(i) for i in ids]
+        Fs = [sv.result(i) for i in ids]
+        st = sv.stats()
+    return Fs, infos, st
+
+
+@pytest.mark.parametrize("streams,stagger", [(4, True), (1, False), (2, True)])
+def test_served_jobs_equal_solo(torch_cuda, jobs, solo, streams, stagger):
+    torch = torch_cuda
+    say("serve", streams, stagger, [(p.grid, p.Q, prec, it) for p, prec, it in jobs])
+    Fs, infos, st = serve(torch, jobs, 4e9, streams, stagger)
+    assert st["completed"] == len(jobs) and st["submitted"] == len(jobs)
+    assert st["in_use_bytes"] == 0 and st["peak_bytes"] <= st["budget_bytes"]
+    for (p, prec, iters), F, ref, info in zip(jobs, Fs, solo, infos):
+        assert info["state"] == "done" and info["status"] == _ffi.SSMAP_OK
+        assert info["iters"] == iters
+        assert info["submit_ms"] <= info["admit_ms"]
+        assert torch.equal(F, ref), (p.grid, prec)
+
+
+def test_served_jobs_match_oracle(torch_cuda, jobs, solo):
+    torch = torch_cuda
+    Fs, _, _ = serve(torch, jobs, 4e9, 4, True)
+    for (p, prec, iters), F in zip(jobs, Fs):
+        ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters)
+        z = F.double().cpu().numpy()
+        err = np.linalg.norm(z - ref["z"]) / np.linalg.norm(ref["z"])
+        say("oracle", p.grid, prec, iters, err)
+        assert err <= TOL[prec], (p.grid, prec, err)
+
+
+def test_small_budget_queues_and_reuses_memory(torch_cuda, jobs, solo):
+    torch = torch_cuda
+    Ms = device_inputs(torch, jobs)
+    # a budget that holds the largest job and little else: admission must wait
+    # for retirements, and freed ranges are reused across streams
+    with _ffi.Server(4e9, 4) as probe:
+        sizes = []
+        for (p, prec, iters), M in zip(jobs, Ms):
+            d = probe.add_dictionary(p.K)
+            jid = probe.submit(d, p.grid, M, p.lam, p.beta, 0, ready=True, precision=prec)
+            sizes.append(probe.poll(jid)["state_bytes"])
+        probe.drain()
+    budget = 1.2 * max(sizes)
+    say("budget", budget, "job bytes", sizes)
+    Fs, infos, st = serve(torch, jobs, budget, 4, False)
+    assert st["peak_bytes"] <= budget
+    assert st["completed"] == len(jobs)
+    for F, ref in zip(Fs, solo):
+        assert torch.equal(F, ref)
+    # strict arrival order: each job is admitted no earlier than the one before it
+    admits = [i["admit_ms"] for i in infos]
+    assert admits == sorted(admits)
+
+
+def test_zero_iterations_nonfinite_and_rejections(torch_cuda, jobs):
+    torch = torch_cuda
+    p, prec, _ = jobs[0]
+    M = torch.tensor(p.m, dtype=torch.float32, device="cuda")
+    Mbad = M.clone()
+    Mbad[3, 1] = float("nan")
+    torch.cuda.synchronize()
+    with _ffi.Server(1e9, 2) as sv:
+        d = sv.add_dictionary(p.K)
+        F0 = torch.full((p.N, p.Q), 7.0, device="cuda")
+        j0 = sv.submit(d, p.grid, M, p.lam, p.beta, 0, F=F0, ready=True, precision="fp32")
+        jb = sv.submit(d, p.grid, Mbad, p.lam, p.beta, 5, ready=True, precision="fp32")
+        jg = sv.submit(d, p.grid, M, p.lam, p.beta, 5, ready=True, precision="fp32")
+        bad = [dict(check_every=1), dict(keep_aux=True), dict(autotune=True),
+               dict(kernel="unfused"), dict(rank=p.K.shape[0] + 1)]
+        for kw in bad:
+            with pytest.raises(_ffi.SsmapError) as e:
+                sv.submit(d, p.grid, M, p.lam, p.beta, 5, ready=True,
+                          **dict(dict(precision="fp32"), **kw))
+            assert e.value.status == _ffi.SSMAP_EINVAL, kw
+        p2 = jobs[7][0]                                  # P = 60: rank 60 has no fused kernel
+        d2 = sv.add_dictionary(p2.K)
+        M2 = torch.tensor(p2.m, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        with pytest.raises(_ffi.SsmapError) as e:
+            sv.submit(d2, p2.grid, M2, p2.lam, p2.beta, 5, ready=True, precision="fp32", rank=-1)
+        assert e.value.status == _ffi.SSMAP_EINVAL
+        with pytest.raises(_ffi.SsmapError) as e:        # alone above the budget
+            _ffi.ssmap_server_submit(sv.sv, d, (2048, 2048, 1), M.data_ptr(), p.lam,
+                                     _ffi.make_steps(p.beta, precision="fp32"), 5, M.data_ptr())
+        assert e.value.status == _ffi.SSMAP_ENOMEM
+        with pytest.raises(_ffi.SsmapError) as e:
+            _ffi.ssmap_server_submit(sv.sv, 99, p.grid, M.data_ptr(), p.lam,
+                                     _ffi.make_steps(p.beta, precision="fp32"), 5, M.data_ptr())
+        assert e.value.status == _ffi.SSMAP_EINVAL
+        sv.drain()
+        assert sv.poll(j0)["state"] == "done"
+        assert torch.count_nonzero(sv.result(j0)).item() == 0
+        assert sv.poll(jb)["status"] == _ffi.SSMAP_ENONFINITE
+        with pytest.raises(_ffi.SsmapError):
+            sv.result(jb)
+        assert sv.poll(jg)["status"] == _ffi.SSMAP_OK
+        assert torch.isfinite(sv.result(jg)).all()
+        with pytest.raises(_ffi.SsmapError):
+            sv.poll(12345)
