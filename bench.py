@@ -33,6 +33,9 @@ WORKLOADS = {
     "c1": "2-D diffusion-relaxation 32x32, P=30, Q=100 (10x10), fp64, 500 iters",
     "c4": "64 uneven 2-D slices (sides 48..256), P in {30,60}, Q in {100,400,1600}, one batch, "
           "200 iters",
+    "c5": "served stream: Poisson arrivals, N log-uniform 1e3..1e6 (2-D up to 65,536, else "
+          "nz=32), Q in {100 fp64 500 it, 400 fp32 300 it, 1024 bf16x3 300 it, "
+          "1600 fp32 300 it}",
 }
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 state)"}
 
@@ -238,6 +241,189 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_serve(probs):
+    """The FP64 oracle, untuned, on one small job of each dictionary class of
+    the served stream (cropped to at most 48 x 48 voxels)."""
+    import oracle
+    from paper_2401_12890_amd import synth
+    sub = []
+    for sp in probs:
+        g = (min(sp["grid"][0], 48), min(sp["grid"][1], 48), 1)
+        sub.append(synth.serving_problem(dict(sp, grid=g), single=False))
+    t0 = time.perf_counter()
+    for p in sub:
+        oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, 1)
+    one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for p in sub:
+        oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, 4)
+    four = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": sum(p.N for p in sub) * 3 / max(four - one, 1e-9),
+            "unit": "voxel-iterations/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one job per dictionary class cropped to <= 48x48 "
+                      f"({sum(p.N for p in sub)} voxels, Q={[p.Q for p in sub]}), 3 float64 "
+                      f"iterations after one"}
+
+
+def bench_serve(args):
+    """Served stream: jobs are submitted at their Poisson arrival times to a
+    server that admits them first in, first out under a device-memory budget
+    and advances all running jobs in shared fused launches (continuous
+    batching over four streams). Reported: throughput over the makespan,
+    p50 / p99 arrival-to-completion latency, the offered load, and the same
+    stream served one job at a time (service times measured on the same
+    server, queueing replayed for the same arrivals)."""
+    import numpy as np
+    import torch
+
+    from paper_2401_12890_amd import _ffi, synth
+    prec_of = {"c1": "fp64", "c2": "fp32", "c3": "bf16x3"}
+    specs = synth.serving_stream(njobs=args.jobs, rate=args.rate)
+    log(f"generating {len(specs)} served jobs")
+    jobs, Ks = [], {}
+    for k, sp in enumerate(specs):
+        prec = prec_of[sp["recipe"]]
+        p = synth.serving_problem(sp, single=prec != "fp64")
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        M = torch.from_numpy(np.ascontiguousarray(p.m)).to(device="cuda", dtype=dt)
+        F = torch.empty((p.N, p.Q), dtype=dt, device="cuda")
+        Ks.setdefault(sp["Q"], p.K)
+        jobs.append(dict(spec=sp, prec=prec, iters=p.iters, lam=p.lam, beta=p.beta, M=M, F=F,
+                         grid=p.grid, N=p.N, P=p.P, Q=p.Q))
+        if k % 10 == 9:
+            log(f"  {k + 1} jobs generated")
+    torch.cuda.synchronize()
+    budget = args.budget_gb * 1e9
+
+    def server():
+        sv = _ffi.Server(budget, args.streams)
+        dicts = {Q: sv.add_dictionary(K) for Q, K in Ks.items()}
+        seen = set()
+        for j in jobs:                    # warm every class: kernels and device constants
+            key = (j["Q"], j["grid"][2] == 1)
+            if key in seen:
+                continue
+            seen.add(key)
+            g = (16, 16, 1) if key[1] else (8, 8, 4)
+            sv.submit(dicts[j["Q"]], g, j["M"][:256], j["lam"], j["beta"], 2, ready=True,
+                      precision=j["prec"])
+        sv.drain()
+        return sv, dicts
+
+    def submit(sv, dicts, j):
+        return sv.submit(dicts[j["Q"]], j["grid"], j["M"], j["lam"], j["beta"], j["iters"],
+                         F=j["F"], ready=True, precision=j["prec"])
+
+    # ---- continuous batching at the arrival times
+    sv, dicts = server()
+    n = len(jobs)
+    ids, sub_wall = [None] * n, [0.0] * n
+    log(f"serving {n} jobs at {args.rate} jobs/s")
+    t0 = time.perf_counter()
+    nxt = 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < n and specs[nxt]["t"] <= now:
+            ids[nxt] = submit(sv, dicts, jobs[nxt])
+            sub_wall[nxt] = time.perf_counter() - t0
+            nxt += 1
+        pending = sv.pump(args.horizon)
+        if nxt == n and pending == 0:
+            break
+        if pending == 0 and nxt < n:
+            time.sleep(max(0.0, specs[nxt]["t"] - (time.perf_counter() - t0)))
+    sv.drain()
+    wall = time.perf_counter() - t0
+    infos = [sv.poll(i) for i in ids]
+    stats = sv.stats()
+    off = infos[0]["submit_ms"] - sub_wall[0] * 1e3      # server clock - loop clock
+    arrive = [off + sp["t"] * 1e3 for sp in specs]
+    lat = [inf["done_ms"] - a for inf, a in zip(infos, arrive)]
+    makespan_ms = max(inf["done_ms"] for inf in infos) - arrive[0]
+    vox_it = sum(j["N"] * j["iters"] for j in jobs)
+    value = vox_it / (makespan_ms / 1e3)
+    ranks = [inf["rank"] for inf in infos]
+    alg = sum(alg_bytes_per_voxel_iter(j["Q"], r, 8 if j["prec"] == "fp64" else 4) * j["N"] *
+              j["iters"] for j, r in zip(jobs, ranks))
+    log(f"continuous batching: makespan {makespan_ms:.0f} ms, p50 {percentile(lat, 50):.0f} ms, "
+        f"p99 {percentile(lat, 99):.0f} ms, {stats['launches']} launches")
+
+    # ---- parity: served maps equal the same jobs solved alone (smallest job per class)
+    parity = None
+    if not args.no_parity:
+        smallest = {}
+        for k, j in enumerate(jobs):
+            key = (j["Q"], j["prec"])
+            if key not in smallest or j["N"] < jobs[smallest[key]]["N"]:
+                smallest[key] = k
+        same = []
+        for k in smallest.values():
+            j = jobs[k]
+            Fserved = sv.result(ids[k])
+            with _ffi.Mapper(Ks[j["Q"]], j["grid"]) as mp:
+                Fsolo = mp.solve_torch(j["M"], j["lam"], j["beta"], j["iters"],
+                                       precision=j["prec"], kernel="fused")
+                torch.cuda.synchronize()
+            same.append(bool(torch.equal(Fserved, Fsolo)))
+            del Fsolo
+        parity = {"kind": "served map bitwise equal to the same job solved alone (fused kernel)",
+                  "jobs": [dict(N=jobs[k]["N"], Q=jobs[k]["Q"], precision=jobs[k]["prec"])
+                           for k in smallest.values()], "equal": same}
+    sv.close()
+
+    # ---- one job at a time on the same kind of server: service times
+    sv, dicts = server()
+    service = []
+    for j in jobs:
+        i = submit(sv, dicts, j)
+        sv.drain()
+        inf = sv.poll(i)
+        service.append(inf["done_ms"] - inf["submit_ms"])
+    sv.close()
+    end, seq_lat = -1e30, []
+    for a, sms in zip(arrive, service):
+        end = max(a, end) + sms
+        seq_lat.append(end - a)
+    seq_makespan = end - arrive[0]
+    rho = args.rate * (sum(service) / n) / 1e3
+    log(f"one at a time: mean service {sum(service) / n:.1f} ms, offered load {rho:.2f}, "
+        f"p50 {percentile(seq_lat, 50):.0f} ms, p99 {percentile(seq_lat, 99):.0f} ms")
+    cpu = None
+    if not args.no_cpu_baseline:
+        firsts = {}
+        for sp in specs:
+            firsts.setdefault(sp["Q"], sp)
+        cpu = cpu_baseline_serve(list(firsts.values()))
+    achieved = alg / (makespan_ms / 1e3) / 1e9
+    line = {
+        "metric": METRIC, "value": value, "unit": "voxel-iterations/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": makespan_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "mixed (f64, f32, bf16x3)",
+        "data": "synthetic (seeded generator, no dataset)",
+        "config": {"workload": WORKLOADS["c5"], "jobs": n, "rate_jobs_per_s": args.rate,
+                   "voxels": sum(j["N"] for j in jobs), "budget_bytes": budget,
+                   "streams": stats["streams"], "horizon_ms": args.horizon,
+                   "classes": stats["classes"]},
+        "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+        "offered_load": rho, "mean_service_ms": sum(service) / n,
+        "one_at_a_time": {"p50_ms": percentile(seq_lat, 50), "p99_ms": percentile(seq_lat, 99),
+                          "voxel_iter_per_s": vox_it / (seq_makespan / 1e3)},
+        "server": {"launches": stats["launches"], "peak_bytes": stats["peak_bytes"],
+                   "wall_s": wall},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "shared fused launches, all classes (aggregate over the makespan)",
+                     "alg_bytes": alg},
+        "cpu_baseline": cpu, "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,8 +433,15 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "unfused"])
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--grid", type=int, nargs=3, default=None,
+                    help="solve the workload's recipe on another grid (nx ny nz)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--jobs", type=int, default=None, help="served stream: number of jobs")
+    ap.add_argument("--rate", type=float, default=20.0, help="served stream: arrivals per s")
+    ap.add_argument("--streams", type=int, default=4, help="served stream: HIP streams")
+    ap.add_argument("--horizon", type=float, default=4.0, help="served stream: ms per pump")
+    ap.add_argument("--budget-gb", type=float, default=96.0, help="served stream: state budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -264,8 +457,10 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         return bench_batch(args)
+    if args.workload == "c5":
+        return bench_serve(args)
     log("generating workload", args.workload)
-    prob = synth.generate(args.workload, iters=args.iters)
+    prob = synth.generate(args.workload, iters=args.iters, grid=args.grid)
     prec = args.precision or prob.precision
     iters = prob.iters
     dt = torch.float64 if prec == "fp64" else torch.float32
@@ -328,7 +523,9 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE_NAME[prec], "data": "synthetic (seeded generator, no dataset)",
-        "config": {"workload": WORKLOADS[args.workload], "grid": list(prob.grid), "P": prob.P,
+        "config": {"workload": WORKLOADS[args.workload] if args.grid is None else
+                   f"{args.workload} recipe on a {'x'.join(map(str, prob.grid))} grid",
+                   "grid": list(prob.grid), "P": prob.P,
                    "Q": prob.Q, "rank": r, "iters": iters, "lambda": prob.lam,
                    "beta": prob.beta, "precision": prec, "kernel": kern_name},
         "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),

@@ -52,7 +52,17 @@ __device__ __forceinline__ int64_t chunk_index(int q, int64_t n, int64_t N) {
 }
 
 // ------------------------------------------------------------- projection
-template <int MODE, int RB>
+// t_n = U_r^T m_n (float64 accumulation in increasing p), ah = w = a .* (s .* t),
+// y = 0, optional t and ||m_n||^2 - ||t_n||^2, and the non-finite flag.
+// A block takes 64 voxels and 4 rank groups of 8 ranks (32 ranks per pass over
+// M; ranks above 32 take further passes). M arrives voxel-major (row n holds
+// P measurements), so tiles of 64 voxels x 32 measurements are read as
+// 128-byte row segments and stored transposed in LDS, where a wave reads one
+// measurement of its 64 voxels without bank conflicts; the matching rows of
+// U_r are broadcast from LDS.
+constexpr int PJ_V = 64, PJ_P = 32, PJ_G = 4, PJ_R = 8;
+
+template <int MODE>
 __global__ void __launch_bounds__(256)
 k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
           const double *__restrict__ Ur, const double *__restrict__ sig,
@@ -61,48 +71,71 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
           typename StateT<MODE>::T *__restrict__ ah, typename StateT<MODE>::T *__restrict__ w,
           typename StateT<MODE>::T *__restrict__ y, int *__restrict__ bad) {
     using T = typename StateT<MODE>::T;
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    const T *mrow = M + n * P;
-    double msq = 0.0;
+    constexpr int RW = PJ_G * PJ_R;                     // ranks per pass
+    __shared__ double Ms[PJ_P][PJ_V + 1];
+    __shared__ double Us[PJ_P][RW];
+    __shared__ double red[PJ_G][PJ_V];
+    const int tid = threadIdx.x, v = tid & (PJ_V - 1), g = tid / PJ_V;
+    const int64_t n0 = (int64_t)blockIdx.x * PJ_V, n = n0 + v;
+    const bool valid = n < N;
+    double msq = 0.0, tsq = 0.0;
     bool finite = true;
-    for (int p = 0; p < P; ++p) {
-        const double v = (double)mrow[p];
-        finite &= __builtin_isfinite(v);
-        msq += v * v;
-    }
-    if (!finite) atomicOr(bad, 1);
-    double tsq = 0.0;
-    for (int i0 = 0; i0 < r; i0 += RB) {
-        double acc[RB];
+    for (int i0 = 0; i0 < r; i0 += RW) {
+        double acc[PJ_R];
 #pragma unroll
-        for (int j = 0; j < RB; ++j) acc[j] = 0.0;
-        for (int p = 0; p < P; ++p) {
-            const double v = (double)mrow[p];
-            const double *urow = Ur + (size_t)p * r + i0;
+        for (int j = 0; j < PJ_R; ++j) acc[j] = 0.0;
+        for (int p0 = 0; p0 < P; p0 += PJ_P) {
+            __syncthreads();                                // the previous tile is consumed
 #pragma unroll
-            for (int j = 0; j < RB; ++j)
-                if (i0 + j < r) acc[j] += urow[j] * v;
+            for (int k = 0; k < PJ_V * PJ_P / 256; ++k) {
+                const int e = tid + 256 * k, row = e / PJ_P, col = e % PJ_P;
+                const int64_t nn = n0 + row;
+                const int pp = p0 + col;
+                Ms[col][row] = (nn < N && pp < P) ? (double)M[nn * P + pp] : 0.0;
+            }
+            for (int e = tid; e < PJ_P * RW; e += 256) {
+                const int pp = p0 + e / RW, ii = i0 + e % RW;
+                Us[e / RW][e % RW] = (pp < P && ii < r) ? Ur[(size_t)pp * r + ii] : 0.0;
+            }
+            __syncthreads();
+            const int pend = min(PJ_P, P - p0);
+            if (i0 == 0 && g == 0)
+                for (int p = 0; p < pend; ++p) {
+                    const double x = Ms[p][v];
+                    finite &= __builtin_isfinite(x);
+                    msq += x * x;
+                }
+            for (int p = 0; p < pend; ++p) {
+                const double x = Ms[p][v];
+#pragma unroll
+                for (int j = 0; j < PJ_R; ++j) acc[j] += Us[p][g * PJ_R + j] * x;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            const int i = i0 + j;
-            if (i < r) {
+        for (int j = 0; j < PJ_R; ++j) {
+            const int i = i0 + g * PJ_R + j;
+            if (valid && i < r) {
                 tsq += acc[j] * acc[j];
                 if (t) t[(size_t)i * N + n] = acc[j];
-                const T v = (T)(acoef[i] * (sig[i] * acc[j]));
-                ah[(size_t)i * N + n] = v;
-                w[(size_t)i * N + n] = v;
+                const T val = (T)(acoef[i] * (sig[i] * acc[j]));
+                ah[(size_t)i * N + n] = val;
+                w[(size_t)i * N + n] = val;
                 y[(size_t)i * N + n] = (T)0;
             }
         }
     }
-    for (int i = r; i < RP; ++i) {
-        ah[(size_t)i * N + n] = (T)0;
-        w[(size_t)i * N + n] = (T)0;
-        y[(size_t)i * N + n] = (T)0;
+    if (valid)
+        for (int i = r + g; i < RP; i += PJ_G) {
+            ah[(size_t)i * N + n] = (T)0;
+            w[(size_t)i * N + n] = (T)0;
+            y[(size_t)i * N + n] = (T)0;
+        }
+    if (!finite) atomicOr(bad, 1);
+    if (mperp2) {                                       // uniform over the block
+        red[g][v] = tsq;
+        __syncthreads();
+        if (g == 0 && valid) mperp2[n] = msq - (((red[0][v] + red[1][v]) + red[2][v]) + red[3][v]);
     }
-    if (mperp2) mperp2[n] = msq - tsq;
 }
 
 // ------------------------------------------------------------- unfused iteration
@@ -359,15 +392,13 @@ inline unsigned blocks_for(int64_t work, int per) { return (unsigned)((work + pe
 void launch_project(int mode, const void *M, int P, const double *Ur, const double *sig,
                     const double *acoef, int r, int RP, int64_t N, double *t, double *mperp2,
                     void *ah, void *w, void *y, int *bad, hipStream_t s) {
-    const dim3 grid(blocks_for(N, 256)), block(256);
+    const dim3 grid(blocks_for(N, PJ_V)), block(256);
     if (mode == MODE_FP64)
-        hipLaunchKernelGGL((k_project<MODE_FP64, 16>), grid, block, 0, s, (const double *)M, P,
-                           Ur, sig, acoef, r, RP, N, t, mperp2, (double *)ah, (double *)w,
-                           (double *)y, bad);
+        hipLaunchKernelGGL(k_project<MODE_FP64>, grid, block, 0, s, (const double *)M, P, Ur, sig,
+                           acoef, r, RP, N, t, mperp2, (double *)ah, (double *)w, (double *)y, bad);
     else
-        hipLaunchKernelGGL((k_project<MODE_FP32, 16>), grid, block, 0, s, (const float *)M, P,
-                           Ur, sig, acoef, r, RP, N, t, mperp2, (float *)ah, (float *)w,
-                           (float *)y, bad);
+        hipLaunchKernelGGL(k_project<MODE_FP32>, grid, block, 0, s, (const float *)M, P, Ur, sig,
+                           acoef, r, RP, N, t, mperp2, (float *)ah, (float *)w, (float *)y, bad);
 }
 
 void launch_update_unfused(int mode, const IterArgs &a, hipStream_t s) {

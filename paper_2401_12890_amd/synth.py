@@ -142,13 +142,20 @@ def _fields(grid, rng, nblob=3, nbump=6):
     return A
 
 
-def generate(name: str, grid=None, seed=None, iters=None, dtype_m=np.float64) -> Problem:
+def generate(name: str, grid=None, seed=None, iters=None, overrides=None, dict_seed=None,
+             single=False) -> Problem:
     """Seeded problem for recipe `name`, optionally on another grid or seed.
 
     Streams (spawned from SeedSequence(seed) in this order): dictionary
-    parameters, spectral blobs, spatial fields, noise.
+    parameters, spectral blobs, spatial fields, noise. `overrides` replaces
+    recipe entries; `dict_seed` draws the dictionary parameters from that seed
+    instead (jobs sharing one acquisition protocol share one dictionary);
+    `single` forms the data and draws the noise in float32 (m is float32 then),
+    for large served jobs; the float32 noise is a different seeded stream.
     """
     cfg = dict(CONFIGS[name])
+    if overrides:
+        cfg.update(overrides)
     if grid is not None:
         cfg["grid"] = tuple(int(v) for v in grid)
     if seed is None:
@@ -156,20 +163,27 @@ def generate(name: str, grid=None, seed=None, iters=None, dtype_m=np.float64) ->
     ss = np.random.SeedSequence(seed)
     r_dict, r_blob, r_field, r_noise = [np.random.Generator(np.random.PCG64(s))
                                         for s in ss.spawn(4)]
+    if dict_seed is not None:
+        r_dict = np.random.Generator(np.random.PCG64(np.random.SeedSequence(dict_seed).spawn(4)[0]))
     K, meta = dictionary(cfg, r_dict)
     G = _blobs(cfg, r_blob)                   # (3, Q)
     A = _fields(cfg["grid"], r_field)         # (3, N)
     KG = G @ K.T                              # (3, P): K applied to each blob
-    m = A.T @ KG                              # (N, P) noise-free data
+    if single:
+        m = A.T.astype(np.float32) @ KG.astype(np.float32)
+    else:
+        m = A.T @ KG                          # (N, P) noise-free data
     if cfg["kind"] == "dr":
         p0 = 0                                # b = 0, shortest TE
     else:
         p0 = int(np.argmax(np.abs(m).mean(axis=0)))
     sigma = float(np.abs(m[:, p0]).mean()) / cfg["snr"]
-    m += sigma * r_noise.standard_normal(m.shape)
+    if single:
+        m += np.float32(sigma) * r_noise.standard_normal(m.shape, dtype=np.float32)
+    else:
+        m += sigma * r_noise.standard_normal(m.shape)
     meta.update(sigma=sigma, p0=p0, blobs=G, fields=A, name=name, seed=seed)
-    return Problem(K=K, m=m.astype(dtype_m, copy=False), grid=cfg["grid"],
-                   lam=cfg["lam"], beta=cfg["beta"],
+    return Problem(K=K, m=m, grid=cfg["grid"], lam=cfg["lam"], beta=cfg["beta"],
                    iters=cfg["iters"] if iters is None else iters,
                    precision=cfg["precision"], meta=meta)
 
@@ -216,15 +230,58 @@ def generate_batch(nslices=None, side=None, seed=None, iters=None, max_side=None
             nx, ny = min(nx, max_side), min(ny, max_side)
         P = int(rng.choice(cfg["P"]))
         n = int(rng.choice(cfg["grid_n"]))
-        base = dict(CONFIGS["c1"] if P == 30 else CONFIGS["c2"])
-        base.update(n1=n, n2=n, snr=cfg["snr"], lam=cfg["lam"], beta=cfg["beta"],
-                    iters=cfg["iters"] if iters is None else iters, grid=(nx, ny, 1),
-                    precision="fp32")
-        CONFIGS["_slice"] = base
-        try:
-            pr = generate("_slice", seed=1000 * seed + k)
-        finally:
-            del CONFIGS["_slice"]
+        over = dict(n1=n, n2=n, snr=cfg["snr"], lam=cfg["lam"], beta=cfg["beta"],
+                    iters=cfg["iters"] if iters is None else iters, precision="fp32")
+        pr = generate("c1" if P == 30 else "c2", grid=(nx, ny, 1), seed=1000 * seed + k,
+                      overrides=over)
         pr.meta["slice"] = k
         probs.append(pr)
     return probs
+
+
+# Served stream: Poisson arrivals at `rate` jobs/s; N log-uniform on
+# [1e3, 1e6] voxels, planar (nz = 1) up to 65,536 voxels, else volumetric with
+# nz = 32; the dictionary class Q in {100, 400, 1024, 1600} uniform, each
+# taking P, precision and iteration count from its recipe. Jobs of one class
+# share one dictionary (one acquisition protocol).
+SERVE_C5 = dict(rate=20.0, njobs=60, N=(1e3, 1e6), planar_max=65536, nz=32, seed=5,
+                classes={100: ("c1", {}), 400: ("c2", dict(n1=20, n2=20)),
+                         1024: ("c3", {}), 1600: ("c2", {})})
+
+
+def _box(N, planar_max, nz):
+    if N <= planar_max:
+        nx = max(1, int(round(np.sqrt(N))))
+        return (nx, max(1, int(round(N / nx))), 1)
+    nx = max(1, int(round(np.sqrt(N / nz))))
+    return (nx, max(1, int(round(N / (nz * nx)))), nz)
+
+
+def serving_stream(njobs=None, rate=None, seed=None, N=None):
+    """Seeded job specs of the served stream (no data): a list of dicts with
+    the arrival time t (s), Q, the recipe name and overrides, the grid and
+    the data seed. Times, sizes and classes come from one stream in job order."""
+    cfg = dict(SERVE_C5)
+    njobs = cfg["njobs"] if njobs is None else njobs
+    rate = cfg["rate"] if rate is None else rate
+    seed = cfg["seed"] if seed is None else seed
+    lo, hi = cfg["N"] if N is None else N
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed).spawn(1)[0]))
+    gaps = rng.exponential(1.0 / rate, njobs)
+    t = np.cumsum(gaps) - gaps[0]
+    Qs = sorted(cfg["classes"])
+    specs = []
+    for k in range(njobs):
+        n = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        Q = int(Qs[rng.integers(len(Qs))])
+        name, over = cfg["classes"][Q]
+        specs.append(dict(t=float(t[k]), Q=Q, recipe=name, overrides=dict(over),
+                          grid=_box(n, cfg["planar_max"], cfg["nz"]), seed=1000 * seed + k))
+    return specs
+
+
+def serving_problem(spec, single=True) -> Problem:
+    """The Problem of one served job (dictionary from its recipe's own seed)."""
+    name = spec["recipe"]
+    return generate(name, grid=spec["grid"], seed=spec["seed"], overrides=spec["overrides"],
+                    dict_seed=CONFIGS[name]["seed"], single=single)
