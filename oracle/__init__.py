@@ -8,8 +8,13 @@ library never does, and this package imports nothing from the library: the
 two share no code. Inputs for both come from the seeded generator module,
 which holds none of the method's arithmetic.
 """
-from .algorithm2 import (dtd_apply, dtd_norm, f_step, ladmm, objective, rank_rule,
-                    reg_value, thin_svd, xi_rule, z_step, d_step)
+from .algorithm2 import (beta_heuristic, centre_patch, d_step, dtd_apply, dtd_apply_graph,
+                         dtd_norm, dtd_norm_graph, f_step, graph_edges, ladmm, objective,
+                         objective_masked, patch_data, rank_rule, reg_value, thin_svd, xi_rule,
+                         z_step)
+from .admm_previous import admm_previous, z_solve_dct
 
-__all__ = ["dtd_apply", "dtd_norm", "f_step", "ladmm", "objective", "rank_rule",
-           "reg_value", "thin_svd", "xi_rule", "z_step", "d_step"]
+__all__ = ["beta_heuristic", "centre_patch", "d_step", "dtd_apply", "dtd_apply_graph",
+           "dtd_norm", "dtd_norm_graph", "f_step", "graph_edges", "ladmm", "objective",
+           "objective_masked", "patch_data", "rank_rule", "reg_value", "thin_svd", "xi_rule",
+           "z_step", "admm_previous", "z_solve_dct"]

@@ -116,6 +116,57 @@ def xi_rule(lam: float, grid) -> float:
     return XI_FACTOR * lam * dtd_norm(grid) + EPS_XI
 
 
+# --------------------------------------------------------------- masked voxel sets
+# Sec. II-C (maskless footnote): only voxels inside the object are estimated,
+# with no smoothness across the object boundary. The regulariser of Eq. (l2)
+# then runs over the face-neighbour pairs whose two voxels are both inside,
+# i.e. over the graph induced by the mask; outside voxels stay 0.
+def graph_edges(grid, mask):
+    """Face-neighbour pairs (a, b), a < b, of inside voxels, as indices into
+    the list of inside voxels (in increasing voxel order)."""
+    nx, ny, nz = grid
+    inside = np.asarray(mask, dtype=bool).reshape(-1)
+    comp = -np.ones(inside.size, dtype=np.int64)
+    comp[inside] = np.arange(int(inside.sum()))
+    edges = []
+    for n in np.flatnonzero(inside):
+        x, y, z = n % nx, (n // nx) % ny, n // (nx * ny)
+        for dx, dy, dz, lim, c in ((1, 0, 0, nx, x), (0, 1, 0, ny, y), (0, 0, 1, nz, z)):
+            if c + 1 < lim:
+                m = n + dx + nx * (dy + ny * dz)
+                if inside[m]:
+                    edges.append((comp[n], comp[m]))
+    return np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+
+
+def dtd_apply_graph(z: np.ndarray, edges: np.ndarray) -> np.ndarray:
+    """D^T D z on an edge list: each pair (a, b) adds 2 (z_a - z_b) to a and
+    2 (z_b - z_a) to b (each unordered pair is two ordered pairs of Eq. l2)."""
+    out = np.zeros_like(z)
+    if len(edges):
+        a, b = edges[:, 0], edges[:, 1]
+        diff = z[a] - z[b]
+        np.add.at(out, a, 2.0 * diff)
+        np.add.at(out, b, -2.0 * diff)
+    return out
+
+
+def dtd_norm_graph(edges: np.ndarray, n: int, dense_limit: int = 2048) -> float:
+    """||D^T D||_2 on an edge list: dense eigvalsh up to dense_limit vertices,
+    else ARPACK (scipy eigsh) on the sparse matrix."""
+    if n <= dense_limit:
+        A = dtd_apply_graph(np.eye(n), edges)
+        return float(np.linalg.eigvalsh(0.5 * (A + A.T))[-1])
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import eigsh
+    a, b = edges[:, 0], edges[:, 1]
+    deg = np.bincount(np.concatenate([a, b]), minlength=n).astype(np.float64)
+    L = sp.coo_matrix((np.concatenate([deg, -np.ones(2 * len(a))]),
+                       (np.concatenate([np.arange(n), a, b]),
+                        np.concatenate([np.arange(n), b, a]))), shape=(n, n)).tocsr()
+    return float(2.0 * eigsh(L, k=1, which="LA", return_eigenvectors=False)[0])
+
+
 # --------------------------------------------------------------- objective
 def objective(K_r: np.ndarray, m: np.ndarray, z: np.ndarray, grid, lam: float) -> float:
     """Cost of Eq. (spat) with R of Eq. (l2): 1/2 ||m - (I (x) K_r) z||^2 + lambda R(z)."""
@@ -140,12 +191,21 @@ def d_step(d, z_new, f, beta):
 
 
 def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
-          track_every=0, f_star=None):
+          track_every=0, f_star=None, mask=None, stop_tol=0.0, check_every=0):
     """Run Algorithm 2 for a fixed number of iterations.
 
     Returns a dict with z, f, d (N, Q), the rank r, xi and, when
     track_every > 0, a history of (k, objective(z^k), DFCS(z^k)) where DFCS
-    follows Eq. (DFCS) against f_star when one is given."""
+    follows Eq. (DFCS) against f_star when one is given.
+
+    mask (N booleans, optional): estimate the inside voxels only, on the graph
+    of inside face neighbours (see graph_edges); outside voxels stay 0 and
+    their data is ignored. stop_tol > 0 with check_every > 0: stop after
+    iteration k+1 when k+1 is a multiple of check_every and
+    ||z^{k+1} - z^k|| <= stop_tol ||z^{k+1}|| (the relative change of the
+    iterate; "iters" returned is the number run)."""
+    if mask is not None:
+        return _ladmm_masked(K, m, grid, lam, beta, iters, rank, xi, mask, stop_tol, check_every)
     K = np.asarray(K, dtype=np.float64)
     m = np.asarray(m, dtype=np.float64)
     nx, ny, nz = grid
@@ -167,6 +227,7 @@ def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
     f = np.zeros((N, Q))
     K_r = (U_r * s_r) @ V_r.T
     hist = []
+    run = iters
     for k in range(iters):
         if track_every and k % track_every == 0:
             hist.append(_track(k, K_r, m, z, grid, lam, f_star))
@@ -174,10 +235,116 @@ def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
         f = f_step(c, V_r, s_w, beta)
         z_new = z_step(z, f, d, lam, xi, beta, grid)
         d = d_step(d, z_new, f, beta)
+        stop = _converged(z, z_new, k, stop_tol, check_every)
         z = z_new
+        if stop:
+            run = k + 1
+            break
     if track_every:
-        hist.append(_track(iters, K_r, m, z, grid, lam, f_star))
-    return dict(z=z, f=f, d=d, rank=r, xi=float(xi), sigma=s, hist=hist, K_r=K_r)
+        hist.append(_track(run, K_r, m, z, grid, lam, f_star))
+    return dict(z=z, f=f, d=d, rank=r, xi=float(xi), sigma=s, hist=hist, K_r=K_r, iters=run)
+
+
+def _converged(z, z_new, k, stop_tol, check_every):
+    """Residual stopping rule: relative change of the iterate at a check."""
+    if not (stop_tol > 0 and check_every > 0) or (k + 1) % check_every:
+        return False
+    return float(np.linalg.norm(z_new - z)) <= stop_tol * float(np.linalg.norm(z_new))
+
+
+def _ladmm_masked(K, m, grid, lam, beta, iters, rank, xi, mask, stop_tol, check_every):
+    """Algorithm 2 on the inside voxels only (graph regulariser), scattered
+    back to the full grid with zeros outside."""
+    K = np.asarray(K, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz = grid
+    N = nx * ny * nz
+    P, Q = K.shape
+    inside = np.asarray(mask, dtype=bool).reshape(-1)
+    if inside.size != N or m.shape != (N, P):
+        raise ValueError("mask must have N entries and m must be (N, P)")
+    idx = np.flatnonzero(inside)
+    edges = graph_edges(grid, inside)
+    n_in = idx.size
+    U, s, V = thin_svd(K)
+    r = rank_rule(s, rank)
+    U_r, s_r, V_r = U[:, :r], s[:r], V[:, :r]
+    if xi is None:
+        xi = XI_FACTOR * lam * dtd_norm_graph(edges, n_in) + EPS_XI
+    s_w = s_r * s_r / (beta * beta + beta * s_r * s_r)
+    g = ((m[idx] @ U_r) * s_r) @ V_r.T
+    z = np.zeros((n_in, Q))
+    d = np.zeros((n_in, Q))
+    f = np.zeros((n_in, Q))
+    run = iters
+    for k in range(iters):
+        c = g + beta * z - d
+        f = f_step(c, V_r, s_w, beta)
+        z_new = np.maximum(0.0, (xi * z - lam * dtd_apply_graph(z, edges) + beta * f + d) /
+                           (xi + beta))
+        d = d_step(d, z_new, f, beta)
+        stop = _converged(z, z_new, k, stop_tol, check_every)
+        z = z_new
+        if stop:
+            run = k + 1
+            break
+    out = {}
+    for name, a in (("z", z), ("f", f), ("d", d)):
+        full = np.zeros((N, Q))
+        full[idx] = a
+        out[name] = full
+    K_r = (U_r * s_r) @ V_r.T
+    out.update(rank=r, xi=float(xi), sigma=s, hist=[], K_r=K_r, iters=run, edges=edges, inside=idx)
+    return out
+
+
+def objective_masked(K_r, m, z, grid, lam, mask) -> float:
+    """Eq. (spat) over the inside voxels with the graph regulariser."""
+    inside = np.asarray(mask, dtype=bool).reshape(-1)
+    idx = np.flatnonzero(inside)
+    edges = graph_edges(grid, inside)
+    zi = z[idx]
+    res = m[idx] - zi @ K_r.T
+    return 0.5 * float(np.sum(res * res)) + lam * 0.5 * float(np.sum(zi * dtd_apply_graph(zi, edges)))
+
+
+# --------------------------------------------------------------- penalty heuristic
+def centre_patch(grid, size=3):
+    """The size^d sub-box at the centre of the grid (d = axes longer than 1),
+    clipped to the grid: (origin, patch grid)."""
+    org, dims = [], []
+    for n in grid:
+        w = min(size, n)
+        org.append((n - w) // 2)
+        dims.append(w)
+    return tuple(org), tuple(dims)
+
+
+def patch_data(m, grid, origin, pgrid):
+    """Rows of m (voxel-major) of the sub-box origin + pgrid, in the patch's voxel order."""
+    nx, ny, _ = grid
+    rows = []
+    for zz in range(pgrid[2]):
+        for yy in range(pgrid[1]):
+            for xx in range(pgrid[0]):
+                rows.append((origin[0] + xx) + nx * ((origin[1] + yy) + ny * (origin[2] + zz)))
+    return m[np.asarray(rows)]
+
+
+def beta_heuristic(K, m, grid, lam, iters, betas, rank=0, size=3):
+    """Penalty selection of Sec. III-F: solve the centre patch (3 x 3, or
+    3 x 3 x 3 in 3-D) for `iters` iterations at every candidate beta and keep
+    the beta whose iterate has the lowest objective of Eq. (spat) on the patch
+    (the fastest progress within the iteration budget). Returns
+    (best beta, objectives)."""
+    origin, pgrid = centre_patch(grid, size)
+    mp = patch_data(np.asarray(m, dtype=np.float64), grid, origin, pgrid)
+    J = []
+    for b in betas:
+        out = ladmm(K, mp, pgrid, lam, float(b), iters, rank=rank)
+        J.append(objective(out["K_r"], mp, out["z"], pgrid, lam))
+    J = np.asarray(J)
+    return float(betas[int(np.argmin(J))]), J
 
 
 def _track(k, K_r, m, z, grid, lam, f_star):

@@ -48,6 +48,24 @@ def explicit_D(grid):
     return sp.csr_matrix((vals, (rows, cols)), shape=(k, N))
 
 
+def explicit_D_masked(grid, mask):
+    """Sparse D over the inside voxels only (columns: inside voxels in increasing
+    voxel order), one row per ordered pair of inside face neighbours."""
+    inside = np.asarray(mask, dtype=bool).reshape(-1)
+    idx = np.flatnonzero(inside)
+    col = {int(n): c for c, n in enumerate(idx)}
+    rows, cols, vals = [], [], []
+    k = 0
+    for n in idx:
+        for m in neighbours(int(n), grid):
+            if inside[m]:
+                rows += [k, k]
+                cols += [col[int(n)], col[m]]
+                vals += [1.0, -1.0]
+                k += 1
+    return sp.csr_matrix((vals, (rows, cols)), shape=(k, len(idx)))
+
+
 def R_loops(f, grid):
     """R(f) by the double sum of Eq. (l2), with plain loops."""
     N = f.shape[0]
@@ -113,10 +131,12 @@ def J_explicit(K_r, m, z, grid, lam):
     return 0.5 * float(np.sum(res * res)) + lam * 0.5 * float(np.sum(Dz * Dz))
 
 
-def fista(K_r, m, grid, lam, iters=20000, tol=1e-14):
+def fista(K_r, m, grid, lam, iters=20000, tol=1e-14, D=None):
     """Projected gradient with Nesterov momentum and adaptive restart on the
-    same convex problem, using the explicit sparse D (independent of LADMM)."""
-    D = explicit_D(grid)
+    same convex problem, using the explicit sparse D (independent of LADMM);
+    D may be given (e.g. a masked one over a subset of voxels, with m's rows)."""
+    if D is None:
+        D = explicit_D(grid)
     DtD = (D.T @ D).tocsr()
     Lip = np.linalg.norm(K_r, 2) ** 2 + lam * np.linalg.norm(DtD.toarray(), 2)
     step = 1.0 / Lip
