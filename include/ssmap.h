@@ -87,6 +87,11 @@ typedef struct {
     int flags;              /* SSMAP_KEEP_AUX                                            */
     int kernel;             /* ssmap_kernel                                              */
     int reserved;
+    double stop_tol;        /* 0: run all iters. > 0 (needs check_every > 0, no
+                               SSMAP_KEEP_AUX): residual stopping rule, stop after
+                               iteration k when k is a multiple of check_every and
+                               ||z^k - z^{k-1}|| <= stop_tol ||z^k|| (the paper prints
+                               no rule; stats.iters reports the count run)           */
 } ssmap_steps;
 
 #define SSMAP_MAX_HIST 512
@@ -147,6 +152,29 @@ ssmap_status ssmap_solve_device(ssmap_ctx *ctx, const void *dM, double lambda,
 /* f^iters and d^iters of the last solve run with SSMAP_KEEP_AUX.
  *   f_out, d_out : N*Q float64 voxel-major host buffers; either may be NULL. */
 ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out);
+
+/* Masked voxel set (Sec. II-C, maskless footnote): estimate only the voxels
+ * inside the object, with no smoothness across its boundary. mask: N bytes
+ * (voxel order as M's rows), nonzero = inside; copied. From then on every
+ * solve on ctx keeps outside voxels at 0 (their rows of F are 0 and their rows
+ * of M are not read), the regulariser of Eq. (l2) runs over face-neighbour
+ * pairs with both voxels inside, and ||D^T D|| of that graph (float64
+ * Lanczos) enters the xi_p rule. Bricks with no inside voxel are not
+ * launched. mask = NULL restores the whole box. */
+ssmap_status ssmap_set_mask(ssmap_ctx *ctx, const uint8_t *mask);
+
+/* Penalty selection heuristic (Sec. III-F): solve the centre patch of the
+ * grid (3 voxels per axis longer than 1, fewer on shorter axes; the box
+ * without any mask) for `iters` iterations at each of the n_betas candidate
+ * penalties betas[i] > 0, with lambda and the other fields of steps as given
+ * (beta, check_every, flags and stop_tol are overridden), and return through
+ * *beta_out the candidate whose iterate has the lowest objective of
+ * Eq. (spat) on the patch (float64, the first on ties). J_out (n_betas
+ * entries, may be NULL) receives the objectives. M: the full N*P float64
+ * data on the host. */
+ssmap_status ssmap_tune_beta(ssmap_ctx *ctx, const double *M, double lambda,
+                             const ssmap_steps *steps, int iters, const double *betas,
+                             int n_betas, double *J_out, double *beta_out);
 
 /* Statistics of the last solve (see ssmap_stats). */
 ssmap_status ssmap_get_stats(const ssmap_ctx *ctx, ssmap_stats *out);

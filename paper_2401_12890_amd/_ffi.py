@@ -29,7 +29,7 @@ MAX_HIST = 512
 
 EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_get_aux",
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
-           "ssmap_destroy", "ssmap_version",
+           "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_tune_beta",
            "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
            "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
@@ -42,7 +42,8 @@ MAX_CLASSES = 16
 class Steps(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("xi_p", ctypes.c_double), ("rank", ctypes.c_int),
                 ("precision", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("flags", ctypes.c_int), ("kernel", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("kernel", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("stop_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -130,6 +131,11 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_last_error.restype = ctypes.c_char_p
     lib.ssmap_destroy.argtypes = [vp]
     lib.ssmap_destroy.restype = None
+    lib.ssmap_set_mask.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    lib.ssmap_set_mask.restype = ip
+    lib.ssmap_tune_beta.argtypes = [vp, dp, ctypes.c_double, ctypes.POINTER(Steps), ip, dp, ip,
+                                    dp, dp]
+    lib.ssmap_tune_beta.restype = ip
     lib.ssmap_version.argtypes = []
     lib.ssmap_version.restype = ctypes.c_char_p
     pp = ctypes.POINTER(ctypes.c_void_p)
@@ -177,12 +183,13 @@ def _dptr(a: np.ndarray):
 
 
 def make_steps(beta, xi_p=0.0, rank=0, precision="fp64", check_every=0, keep_aux=False,
-               kernel="auto", autotune=False) -> Steps:
+               kernel="auto", autotune=False, stop_tol=0.0) -> Steps:
     flags = (SSMAP_KEEP_AUX if keep_aux else 0) | (SSMAP_AUTOTUNE if autotune else 0)
     return Steps(beta=float(beta), xi_p=float(xi_p), rank=int(rank),
                  precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                  check_every=int(check_every), flags=flags,
-                 kernel=KERNELS[kernel] if isinstance(kernel, str) else int(kernel), reserved=0)
+                 kernel=KERNELS[kernel] if isinstance(kernel, str) else int(kernel), reserved=0,
+                 stop_tol=float(stop_tol))
 
 
 # ------------------------------------------------------------------ C names
@@ -255,6 +262,26 @@ def ssmap_destroy(ctx: int | None) -> None:
     load().ssmap_destroy(ctx)
 
 
+def ssmap_set_mask(ctx: int, mask) -> None:
+    """mask: N booleans (voxel order of M's rows), or None for the whole box."""
+    if mask is None:
+        _check(ctx, load().ssmap_set_mask(ctx, None))
+        return
+    mk = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+    _check(ctx, load().ssmap_set_mask(ctx, mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+
+def ssmap_tune_beta(ctx: int, M: np.ndarray, lam: float, steps: Steps, iters: int, betas):
+    """Returns (best beta, objectives per candidate)."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    J = np.empty(b.size)
+    best = ctypes.c_double()
+    _check(ctx, load().ssmap_tune_beta(ctx, _dptr(M), float(lam), ctypes.byref(steps), int(iters),
+                                       _dptr(b), int(b.size), _dptr(J), ctypes.byref(best)))
+    return best.value, J
+
+
 def ssmap_version() -> str:
     return load().ssmap_version().decode()
 
@@ -298,6 +325,13 @@ class Mapper:
 
     def singular_values(self) -> np.ndarray:
         return ssmap_get_singular_values(self.ctx)
+
+    def set_mask(self, mask) -> None:
+        ssmap_set_mask(self.ctx, mask)
+
+    def tune_beta(self, M, lam, iters, betas, **kw):
+        """Patch heuristic for beta; returns (best beta, objectives)."""
+        return ssmap_tune_beta(self.ctx, M, lam, make_steps(1.0, **kw), iters, betas)
 
     def close(self):
         if self.ctx:

@@ -47,6 +47,8 @@ struct IterArgs {
     void *fout;           // optional: f^{k+1}
     void *dout;           // optional: d^{k+1}
     int phase;            // shared launches: entry 2j + ((round + phase) & 1) is job j's
+    const uint8_t *code;  // masked grids: per-voxel code (bit 7 inside, bits 0..2 inside
+                          // face neighbours); NULL: the whole box
 };
 
 // Unfused reference kernels (any rank).
@@ -75,7 +77,9 @@ bool fused_supported(int mode, int RP, int64_t N);
 bool launch_fused(const FusedLaunch &L, hipStream_t s);   // false: no such shape
 FusedShape default_shape(int mode, const Grid &g);
 std::vector<FusedShape> candidate_shapes(int mode, bool planar);
-void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out);
+// Bricks of a grid in launch order; with `code` only bricks holding an inside voxel.
+void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out,
+                  const std::vector<uint8_t> *code = nullptr);
 // Per-chunk V operand blocks of the fused kernel (IterArgs::Vu points to them).
 void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
                     std::vector<double> &Vop);
@@ -91,16 +95,18 @@ void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t co
 
 // Data projection t = U_r^T m, ah = a .* (sigma .* t), w = ah, y = 0,
 // mperp2 = ||m||^2 - ||t||^2; sets *bad != 0 if m holds a NaN/Inf.
+// Outside voxels of a masked grid (code != NULL) get zeros and their data is not read.
 void launch_project(int mode, const void *M, int P, const double *Ur, const double *sig,
                     const double *acoef, int r, int RP, int64_t N, double *t,
-                    double *mperp2, void *ah, void *w, void *y, int *bad, hipStream_t s);
+                    double *mperp2, void *ah, void *w, void *y, int *bad,
+                    const uint8_t *code, hipStream_t s);
 
 // Monitoring: per-block float64 partial sums of the objective terms, then a
 // fixed-order final reduction into out[ST_COUNT].
 void launch_monitor(int mode, const void *z, const void *zprev, const double *V64,
                     const double *sig, const double *t, const double *mperp2, int r,
-                    int RP, int nchunk, Grid g, double *partial, int nblocks_cap,
-                    double *out, hipStream_t s);
+                    int RP, int nchunk, Grid g, const uint8_t *code, double *partial,
+                    int nblocks_cap, double *out, hipStream_t s);
 int monitor_blocks(int64_t N);
 
 // Chunked state -> voxel-major output (element type of the mode's I/O, or
@@ -130,6 +136,14 @@ struct HostConsts {
 void host_consts(int mode, const std::vector<double> &U, const std::vector<double> &s,
                  const std::vector<double> &V, int kmin, int P, int Q, int Qp, int r, int RP,
                  double beta, bool fused, HostConsts &out);
+
+// ---- masked voxel sets (mask.cpp)
+// Code bytes of a mask (N bytes, nonzero = inside) and the inside count.
+void mask_codes(const Grid &g, const uint8_t *mask, std::vector<uint8_t> &code, int64_t &inside);
+// ||D^T D||_2 of the graph of inside face neighbours (Lanczos, float64).
+double masked_dtd_norm(const Grid &g, const std::vector<uint8_t> &code);
+bool brick_has_inside(const Grid &g, const std::vector<uint8_t> &code, int64_t x0, int64_t y0,
+                      int64_t z0, int tx, int ty, int tz);
 
 // Fill a device array of `count` elements of `elem_bytes` (4 or 8) with zero.
 void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s);

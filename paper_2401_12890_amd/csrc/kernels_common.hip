@@ -69,7 +69,8 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
           const double *__restrict__ acoef, int r, int RP, int64_t N,
           double *__restrict__ t, double *__restrict__ mperp2,
           typename StateT<MODE>::T *__restrict__ ah, typename StateT<MODE>::T *__restrict__ w,
-          typename StateT<MODE>::T *__restrict__ y, int *__restrict__ bad) {
+          typename StateT<MODE>::T *__restrict__ y, int *__restrict__ bad,
+          const uint8_t *__restrict__ code) {
     using T = typename StateT<MODE>::T;
     constexpr int RW = PJ_G * PJ_R;                     // ranks per pass
     __shared__ double Ms[PJ_P][PJ_V + 1];
@@ -77,7 +78,8 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
     __shared__ double red[PJ_G][PJ_V];
     const int tid = threadIdx.x, v = tid & (PJ_V - 1), g = tid / PJ_V;
     const int64_t n0 = (int64_t)blockIdx.x * PJ_V, n = n0 + v;
-    const bool valid = n < N;
+    // outside voxels of a mask are not estimated: zeros, data not read
+    auto inside = [&](int64_t k) { return k < N && (!code || (code[k] & 0x80u) != 0); };
     double msq = 0.0, tsq = 0.0;
     bool finite = true;
     for (int i0 = 0; i0 < r; i0 += RW) {
@@ -91,7 +93,7 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
                 const int e = tid + 256 * k, row = e / PJ_P, col = e % PJ_P;
                 const int64_t nn = n0 + row;
                 const int pp = p0 + col;
-                Ms[col][row] = (nn < N && pp < P) ? (double)M[nn * P + pp] : 0.0;
+                Ms[col][row] = (inside(nn) && pp < P) ? (double)M[nn * P + pp] : 0.0;
             }
             for (int e = tid; e < PJ_P * RW; e += 256) {
                 const int pp = p0 + e / RW, ii = i0 + e % RW;
@@ -114,7 +116,7 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
 #pragma unroll
         for (int j = 0; j < PJ_R; ++j) {
             const int i = i0 + g * PJ_R + j;
-            if (valid && i < r) {
+            if (n < N && i < r) {        // outside voxels accumulated zeros
                 tsq += acc[j] * acc[j];
                 if (t) t[(size_t)i * N + n] = acc[j];
                 const T val = (T)(acoef[i] * (sig[i] * acc[j]));
@@ -124,7 +126,7 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
             }
         }
     }
-    if (valid)
+    if (n < N)
         for (int i = r + g; i < RP; i += PJ_G) {
             ah[(size_t)i * N + n] = (T)0;
             w[(size_t)i * N + n] = (T)0;
@@ -134,7 +136,7 @@ k_project(const typename StateT<MODE>::T *__restrict__ M, int P,
     if (mperp2) {                                       // uniform over the block
         red[g][v] = tsq;
         __syncthreads();
-        if (g == 0 && valid) mperp2[n] = msq - (((red[0][v] + red[1][v]) + red[2][v]) + red[3][v]);
+        if (g == 0 && n < N) mperp2[n] = msq - (((red[0][v] + red[1][v]) + red[2][v]) + red[3][v]);
     }
 }
 
@@ -162,15 +164,31 @@ k_update(IterArgs a) {
     const int64_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int64_t x = n % nx, yy = (n / nx) % ny, zz = n / (nx * ny);
     T lap = 0;
-    if (x > 0) lap += zc - z[e - QC];
-    if (x < nx - 1) lap += zc - z[e + QC];
-    if (yy > 0) lap += zc - z[e - nx * QC];
-    if (yy < ny - 1) lap += zc - z[e + nx * QC];
-    if (zz > 0) lap += zc - z[e - nx * ny * QC];
-    if (zz < nz - 1) lap += zc - z[e + nx * ny * QC];
+    bool inside = true;
+    if (a.code) {
+        // masked grid: outside voxels hold z = 0, so summing every box
+        // neighbour and taking the inside-neighbour count is exact
+        const unsigned cb = a.code[n];
+        inside = (cb & 0x80u) != 0;
+        T nsum = 0;
+        if (x > 0) nsum += z[e - QC];
+        if (x < nx - 1) nsum += z[e + QC];
+        if (yy > 0) nsum += z[e - nx * QC];
+        if (yy < ny - 1) nsum += z[e + nx * QC];
+        if (zz > 0) nsum += z[e - nx * ny * QC];
+        if (zz < nz - 1) nsum += z[e + nx * ny * QC];
+        lap = (T)(cb & 7u) * zc - nsum;
+    } else {
+        if (x > 0) lap += zc - z[e - QC];
+        if (x < nx - 1) lap += zc - z[e + QC];
+        if (yy > 0) lap += zc - z[e - nx * QC];
+        if (yy < ny - 1) lap += zc - z[e + nx * QC];
+        if (zz > 0) lap += zc - z[e - nx * ny * QC];
+        if (zz < nz - 1) lap += zc - z[e + nx * ny * QC];
+    }
     const T tau = (T)a.tau, lam2 = (T)a.lam2, beta = (T)a.beta;
     T zn = zc - tau * (lam2 * lap - beta * u);
-    zn = zn > (T)0 ? zn : (T)0;
+    zn = (zn > (T)0 && inside) ? zn : (T)0;
     ((T *)a.znew)[e] = zn;
     if (a.fout) {
         const T dp = a.dprev ? ((const T *)a.dprev)[e] : (T)0;
@@ -263,10 +281,12 @@ k_monitor(const typename StateT<MODE>::T *__restrict__ z,
           const typename StateT<MODE>::T *__restrict__ zprev, const double *__restrict__ V64,
           const double *__restrict__ sig, const double *__restrict__ t,
           const double *__restrict__ mperp2, int r, int RP, int nchunk, Grid g,
-          double *__restrict__ partial) {
+          const uint8_t *__restrict__ code, double *__restrict__ partial) {
     using T = typename StateT<MODE>::T;
     const int64_t N = g.N;
     double acc[5] = {0, 0, 0, 0, 0};
+    // an edge counts when both voxels are inside (every edge without a mask)
+    auto in = [&](int64_t v) { return !code || (code[v] & 0x80u) != 0; };
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
          n += (int64_t)gridDim.x * blockDim.x) {
         // data term: ||m_perp||^2 + sum_i (t_i - sigma_i y_i)^2 with y = V_r^T z in float64
@@ -294,6 +314,10 @@ k_monitor(const typename StateT<MODE>::T *__restrict__ z,
         }
         // regulariser: each forward edge once; norms; non-finite count
         const int64_t x = n % g.nx, yy = (n / g.nx) % g.ny, zz = n / (g.nx * g.ny);
+        const bool ein = in(n);
+        const bool ex = ein && x < g.nx - 1 && in(n + 1);
+        const bool ey = ein && yy < g.ny - 1 && in(n + g.nx);
+        const bool ez = ein && zz < g.nz - 1 && in(n + g.nx * g.ny);
         double reg = 0.0, zsq = 0.0, dsq = 0.0, bad = 0.0;
         for (int c = 0; c < nchunk; ++c) {
             const int64_t base = ((int64_t)c * N + n) * QC;
@@ -305,15 +329,15 @@ k_monitor(const typename StateT<MODE>::T *__restrict__ z,
                     const double dz = zc - (double)zprev[base + qq];
                     dsq += dz * dz;
                 }
-                if (x < g.nx - 1) {
+                if (ex) {
                     const double dd = zc - (double)z[base + qq + QC];
                     reg += dd * dd;
                 }
-                if (yy < g.ny - 1) {
+                if (ey) {
                     const double dd = zc - (double)z[base + qq + g.nx * QC];
                     reg += dd * dd;
                 }
-                if (zz < g.nz - 1) {
+                if (ez) {
                     const double dd = zc - (double)z[base + qq + g.nx * g.ny * QC];
                     reg += dd * dd;
                 }
@@ -391,14 +415,14 @@ inline unsigned blocks_for(int64_t work, int per) { return (unsigned)((work + pe
 // ------------------------------------------------------------- launchers
 void launch_project(int mode, const void *M, int P, const double *Ur, const double *sig,
                     const double *acoef, int r, int RP, int64_t N, double *t, double *mperp2,
-                    void *ah, void *w, void *y, int *bad, hipStream_t s) {
+                    void *ah, void *w, void *y, int *bad, const uint8_t *code, hipStream_t s) {
     const dim3 grid(blocks_for(N, PJ_V)), block(256);
     if (mode == MODE_FP64)
         hipLaunchKernelGGL(k_project<MODE_FP64>, grid, block, 0, s, (const double *)M, P, Ur, sig,
-                           acoef, r, RP, N, t, mperp2, (double *)ah, (double *)w, (double *)y, bad);
+                           acoef, r, RP, N, t, mperp2, (double *)ah, (double *)w, (double *)y, bad, code);
     else
         hipLaunchKernelGGL(k_project<MODE_FP32>, grid, block, 0, s, (const float *)M, P, Ur, sig,
-                           acoef, r, RP, N, t, mperp2, (float *)ah, (float *)w, (float *)y, bad);
+                           acoef, r, RP, N, t, mperp2, (float *)ah, (float *)w, (float *)y, bad, code);
 }
 
 void launch_update_unfused(int mode, const IterArgs &a, hipStream_t s) {
@@ -447,16 +471,16 @@ int monitor_blocks(int64_t N) {
 
 void launch_monitor(int mode, const void *z, const void *zprev, const double *V64,
                     const double *sig, const double *t, const double *mperp2, int r, int RP,
-                    int nchunk, Grid g, double *partial, int nblocks_cap, double *out,
-                    hipStream_t s) {
+                    int nchunk, Grid g, const uint8_t *code, double *partial, int nblocks_cap,
+                    double *out, hipStream_t s) {
     int nb = monitor_blocks(g.N);
     if (nb > nblocks_cap) nb = nblocks_cap;
     if (mode == MODE_FP64)
         hipLaunchKernelGGL(k_monitor<MODE_FP64>, dim3(nb), dim3(256), 0, s, (const double *)z,
-                           (const double *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, partial);
+                           (const double *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, code, partial);
     else
         hipLaunchKernelGGL(k_monitor<MODE_FP32>, dim3(nb), dim3(256), 0, s, (const float *)z,
-                           (const float *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, partial);
+                           (const float *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, code, partial);
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
 }
 

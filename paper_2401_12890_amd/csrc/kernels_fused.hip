@@ -236,6 +236,7 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     bool valid[BPW];
     int slot0[BPW];
     T deg[BPW];
+    bool inside[BPW];                    // false: outside a mask (z stays 0)
     unsigned soff[BPW];                  // byte offset of this lane's quad in a chunk
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
@@ -246,6 +247,12 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
         nvox[b] = valid[b] ? gx + nx * (gy + ny * gz) : 0;
         slot0[b] = (j + 1) + B::SX * ((by + 1) + B::SY * (bz + 1));
         deg[b] = (T)((gx > 0) + (gx + 1 < nx) + (gy > 0) + (gy + 1 < ny) + (gz > 0) + (gz + 1 < nz));
+        inside[b] = true;
+        if (a.code) {                    // masked grid: outside voxels hold z = 0, so the
+            const unsigned cb = a.code[nvox[b]];   // box neighbour sum stays exact
+            deg[b] = (T)(cb & 7u);
+            inside[b] = (cb & 0x80u) != 0;
+        }
         soff[b] = valid[b] ? (unsigned)((nvox[b] * QC + 4 * i4) * sizeof(T)) : OOB;
     }
 
@@ -355,7 +362,7 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             // projected z-update (Eq. z2 with f substituted)
             V4 zn = zc - tau * (lam2 * lap - beta * u);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) zn[i] = zn[i] > (T)0 ? zn[i] : (T)0;
+            for (int i = 0; i < 4; ++i) zn[i] = (zn[i] > (T)0 && inside[b]) ? zn[i] : (T)0;
             IO::store(zn, zo, soff[b]);
             if constexpr (BF) {
                 // K = the 16 nodes of the chunk in their natural lane order
@@ -520,6 +527,7 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
     int64_t nvox[BPW];
     bool valid[BPW];
     float deg[BPW];
+    bool inside[BPW];                    // false: outside a mask (z stays 0)
     unsigned soff[BPW];
     int sa[BPW][7];                      // byte offsets inside a z buffer
 #pragma unroll
@@ -530,6 +538,12 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
         valid[b] = gx < nx && gy < ny && gz < nz;
         nvox[b] = valid[b] ? gx + nx * (gy + ny * gz) : 0;
         deg[b] = (float)((gx > 0) + (gx + 1 < nx) + (gy > 0) + (gy + 1 < ny) + (gz > 0) + (gz + 1 < nz));
+        inside[b] = true;
+        if (a.code) {
+            const unsigned cb = a.code[nvox[b]];
+            deg[b] = (float)(cb & 7u);
+            inside[b] = (cb & 0x80u) != 0;
+        }
         soff[b] = valid[b] ? (unsigned)((nvox[b] * QC + 4 * i4) * sizeof(float)) : OOB;
         const int s0 = (j + 1) + BX::SX * ((by + 1) + BX::SY * (bz + 1));
         const int nb[7] = {s0, s0 - 1, s0 + 1, s0 - BX::SX, s0 + BX::SX, s0 - BX::SX * BX::SY,
@@ -626,7 +640,7 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
             const V4 lap = deg[b] * zc - nsum;
             V4 zn = zc - tau * (lam2 * lap - beta * u);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) zn[i] = zn[i] > 0.0f ? zn[i] : 0.0f;
+            for (int i = 0; i < 4; ++i) zn[i] = (zn[i] > 0.0f && inside[b]) ? zn[i] : 0.0f;
             zkeep[b] = zn;
             if constexpr (BF) {
                 v4s zh, zl;
@@ -749,12 +763,16 @@ std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
     return {{4, 4}, {8, 4}};
 }
 
-void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out) {
+void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out,
+                  const std::vector<uint8_t> *code) {
     const int tx = (int)((g.nx + 15) / 16), ty = (int)((g.ny + sh.ty - 1) / sh.ty),
               tz = (int)((g.nz + sh.tz - 1) / sh.tz);
     for (int k = 0; k < tz; ++k)
         for (int jy = 0; jy < ty; ++jy)
-            for (int i = 0; i < tx; ++i) out.push_back(TileRef{job, i, jy, k});
+            for (int i = 0; i < tx; ++i)
+                if (!code || brick_has_inside(g, *code, (int64_t)i * TX, (int64_t)jy * sh.ty,
+                                              (int64_t)k * sh.tz, TX, sh.ty, sh.tz))
+                    out.push_back(TileRef{job, i, jy, k});
 }
 
 bool launch_fused(const FusedLaunch &L, hipStream_t s) {

@@ -482,7 +482,7 @@ bool admit_one(ssmap_server *sv) {
     // a1: projection and z^0 = 0, w^0 = a.h, y^0 = 0
     launch_zero(j.bad, 1, 4, s);
     launch_project(j.mode, j.dM, d.P, cs.Ur, cs.sig, cs.acoef, j.r, j.RP, N, nullptr, nullptr, ah,
-                   w, y, j.bad, s);
+                   w, y, j.bad, nullptr, s);
     launch_zero(j.z[0], (size_t)d.Qp * N, (int)esz, s);
     launch_zero(j.z[1], (size_t)d.Qp * N, (int)esz, s);
     HIPS(sv, hipGetLastError());
@@ -749,8 +749,8 @@ ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t gr
         if (st.rank < -1 || st.rank > d.kmin) sfail(SSMAP_EINVAL, "rank must be in [-1, min(P,Q)]");
         if (st.precision < SSMAP_FP64 || st.precision > SSMAP_BF16X3)
             sfail(SSMAP_EINVAL, "unknown precision");
-        if (st.check_every != 0 || st.flags != 0)
-            sfail(SSMAP_EINVAL, "served jobs take no monitoring and no flags");
+        if (st.check_every != 0 || st.flags != 0 || st.stop_tol != 0)
+            sfail(SSMAP_EINVAL, "served jobs take no monitoring, no flags and no stopping rule");
         if (st.kernel != SSMAP_KERNEL_AUTO && st.kernel != SSMAP_KERNEL_FUSED)
             sfail(SSMAP_EINVAL, "served jobs run the fused kernel");
         Job j;

@@ -121,6 +121,9 @@ struct ssmap_ctx {
     int aux_mode = 0;
     int aux_iters = 0;
     void *aux_f = nullptr, *aux_d = nullptr;
+    // masked voxel set (empty code: the whole box)
+    std::vector<uint8_t> code;
+    int64_t inside = 0;
     hipEvent_t ev[6] = {};
     double *host_stats = nullptr;         // pinned ST_COUNT doubles
 };
@@ -169,6 +172,13 @@ void *ensure(ssmap_ctx *c, const std::string &name, size_t bytes) {
     return p;
 }
 
+// Device copy of the mask codes (NULL without a mask).
+const uint8_t *mask_dev(ssmap_ctx *c) {
+    if (c->code.empty()) return nullptr;
+    auto it = c->bufs.find("code");
+    return it == c->bufs.end() ? nullptr : (const uint8_t *)it->second.first;
+}
+
 // Plan check before any allocation of a solve: fail early with ENOMEM.
 void plan_check(ssmap_ctx *c, const std::vector<std::pair<std::string, size_t>> &need) {
     size_t extra = 0;
@@ -209,6 +219,10 @@ void validate_steps(ssmap_ctx *c, double lambda, const ssmap_steps *st, int iter
     if (st->check_every < 0) fail(SSMAP_EINVAL, "check_every must be >= 0");
     if (st->kernel < SSMAP_KERNEL_AUTO || st->kernel > SSMAP_KERNEL_FUSED)
         fail(SSMAP_EINVAL, "unknown kernel");
+    if (!(std::isfinite(st->stop_tol) && st->stop_tol >= 0))
+        fail(SSMAP_EINVAL, "stop_tol must be finite and >= 0");
+    if (st->stop_tol > 0 && (st->check_every == 0 || (st->flags & SSMAP_KEEP_AUX)))
+        fail(SSMAP_EINVAL, "stop_tol needs check_every > 0 and no SSMAP_KEEP_AUX");
 }
 
 Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
@@ -243,6 +257,8 @@ struct Prepared {
     void *auxA = nullptr, *auxB = nullptr;
     const void *dM = nullptr;
     int iters = 0;
+    double stop_tol = 0.0;
+    int check_every = 0;
 };
 
 IterArgs args_for(const Prepared &P, int k) {
@@ -261,7 +277,7 @@ void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
     launch_zero(bad, 1, 4, s);
     launch_project(pl.mode, P.dM, c->P, (const double *)ensure(c, "Ur", (size_t)c->P * pl.r * 8),
                    P.sig, (const double *)ensure(c, "acoef", (size_t)pl.RP * 8), pl.r, pl.RP, N,
-                   P.t, P.mperp2, (void *)P.a.ah, P.a.w, P.a.y, bad, s);
+                   P.t, P.mperp2, (void *)P.a.ah, P.a.w, P.a.y, bad, mask_dev(c), s);
     launch_zero(P.z[0], (size_t)c->Qp * N, (int)esz, s);
     launch_zero(P.z[1], (size_t)c->Qp * N, (int)esz, s);
     if (P.aux) {
@@ -282,6 +298,8 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     const int Pm = c->P, Q = c->Q, Qp = c->Qp, r = pl.r, RP = pl.RP;
     const size_t esz = pl.mode == MODE_FP64 ? 8 : 4;
     P.monitor = st->check_every > 0;
+    P.check_every = st->check_every;
+    P.stop_tol = st->stop_tol;
     P.aux = (st->flags & SSMAP_KEEP_AUX) != 0;
     const size_t zbytes = (size_t)Qp * N * esz;
     const size_t rbytes = (size_t)RP * N * esz;
@@ -366,6 +384,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     a.tau = pl.tau;
     a.lam2 = 2.0 * pl.lam;
     a.beta = pl.beta;
+    a.code = mask_dev(c);
 
     ssmap_stats &S = c->stats;
     const double setup = S.setup_ms;
@@ -401,7 +420,7 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
     L.RP = P.pl.RP;
     L.shape = default_shape(P.pl.mode, c->g);
     std::vector<TileRef> tiles;
-    append_tiles(c->g, 0, L.shape, tiles);
+    append_tiles(c->g, 0, L.shape, tiles, c->code.empty() ? nullptr : &c->code);
     IterArgs two[2] = {args_for(P, 0), args_for(P, 1)};
     IterArgs *dj = (IterArgs *)ensure(c, "jobs", sizeof(two));
     TileRef *dt = (TileRef *)ensure(c, "tiles", tiles.size() * sizeof(TileRef));
@@ -414,10 +433,13 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
     return L;
 }
 
-void monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
+// Monitoring after iteration k (z^{k+1} against z^k). Returns true when the
+// residual stopping rule fires: k + 1 is a multiple of check_every and
+// ||z^{k+1} - z^k|| <= stop_tol ||z^{k+1}||.
+bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     const Plan &pl = P.pl;
     launch_monitor(pl.mode, P.z[(k + 1) & 1], P.z[k & 1], P.V64, P.sig, P.t, P.mperp2, pl.r, pl.RP,
-                   c->nchunk, c->g, P.partial, 2048, P.stat, s);
+                   c->nchunk, c->g, mask_dev(c), P.partial, 2048, P.stat, s);
     HIPC(c, hipGetLastError());
     HIPC(c, hipMemcpyAsync(c->host_stats, P.stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipStreamSynchronize(s));
@@ -432,6 +454,8 @@ void monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     }
     if (h[ST_NONFINITE] != 0.0 || !std::isfinite(h[ST_DATA]))
         fail(SSMAP_ENONFINITE, "non-finite iterate at iteration " + std::to_string(k + 1));
+    return P.stop_tol > 0 && (k + 1) % P.check_every == 0 &&
+           std::sqrt(h[ST_DZ]) <= P.stop_tol * std::sqrt(h[ST_ZNORM]);
 }
 
 // One iteration of one job outside a shared launch (unfused kernels, or the
@@ -490,7 +514,11 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
     HIPC(c, hipEventRecord(c->ev[2], s));
     for (int k = 0; k < iters; ++k) {
         step_job(c, P, &L, k, s);
-        if (P.monitor && ((k + 1) % st->check_every == 0 || k + 1 == iters)) monitor_step(c, P, k, s);
+        if (P.monitor && ((k + 1) % st->check_every == 0 || k + 1 == iters) &&
+            monitor_step(c, P, k, s) && k + 1 < iters) {
+            P.iters = k + 1;             // residual stopping rule
+            break;
+        }
     }
     HIPC(c, hipGetLastError());
     HIPC(c, hipEventRecord(c->ev[3], s));
@@ -572,7 +600,8 @@ void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector
         const int j = C.jobs[k];
         args[2 * k] = args_for(Ps[j], 0);                    // even iterations
         args[2 * k + 1] = args_for(Ps[j], 1);                // odd iterations
-        append_tiles(b->jobs[j]->g, (int)k, shape, tiles);
+        append_tiles(b->jobs[j]->g, (int)k, shape, tiles,
+                     b->jobs[j]->code.empty() ? nullptr : &b->jobs[j]->code);
     }
     ssmap_ctx *A = &b->arena;
     const std::string tag = std::to_string(ci);
@@ -837,8 +866,9 @@ ssmap_status ssmap_solve(ssmap_ctx *ctx, const double *M, double lambda, const s
         HIPC(ctx, hipSetDevice(ctx->device));
         const int64_t N = ctx->g.N;
         const size_t nm = (size_t)N * ctx->P, nf = (size_t)N * ctx->Q;
-        for (size_t i = 0; i < nm; ++i)
-            if (!std::isfinite(M[i])) fail(SSMAP_ENONFINITE, "M holds a NaN or Inf");
+        for (size_t i = 0; i < nm; ++i)    // rows outside a mask are not read
+            if (!std::isfinite(M[i]) && (ctx->code.empty() || (ctx->code[i / ctx->P] & 0x80)))
+                fail(SSMAP_ENONFINITE, "M holds a NaN or Inf");
         const bool f64 = steps->precision == SSMAP_FP64;
         const size_t esz = f64 ? 8 : 4;
         plan_check(ctx, {{"io_M", nm * esz}, {"io_F", nf * esz}});
@@ -862,6 +892,93 @@ ssmap_status ssmap_solve(ssmap_ctx *ctx, const double *M, double lambda, const s
             for (size_t i = 0; i < nf; ++i) F_out[i] = tmp[i];
         }
     });
+}
+
+ssmap_status ssmap_set_mask(ssmap_ctx *ctx, const uint8_t *mask) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        HIPC(ctx, hipSetDevice(ctx->device));
+        if (!mask) {
+            ctx->code.clear();
+            ctx->inside = ctx->g.N;
+            ctx->dtd_norm = dtd_norm_closed(ctx->g);
+            return;
+        }
+        std::vector<uint8_t> code;
+        int64_t inside = 0;
+        mask_codes(ctx->g, mask, code, inside);
+        void *d = ensure(ctx, "code", code.size());
+        HIPC(ctx, hipMemcpy(d, code.data(), code.size(), hipMemcpyHostToDevice));
+        ctx->dtd_norm = masked_dtd_norm(ctx->g, code);
+        ctx->code.swap(code);
+        ctx->inside = inside;
+    });
+}
+
+ssmap_status ssmap_tune_beta(ssmap_ctx *ctx, const double *M, double lambda,
+                             const ssmap_steps *steps, int iters, const double *betas,
+                             int n_betas, double *J_out, double *beta_out) {
+    if (!ctx) return SSMAP_EINVAL;
+    ssmap_ctx *pc = nullptr;
+    const ssmap_status st = guarded(ctx, [&] {
+        if (!M || !steps || !betas || !beta_out) fail(SSMAP_EINVAL, "NULL argument");
+        if (n_betas < 1 || iters < 1) fail(SSMAP_EINVAL, "need n_betas >= 1 and iters >= 1");
+        for (int i = 0; i < n_betas; ++i)
+            if (!(std::isfinite(betas[i]) && betas[i] > 0)) fail(SSMAP_EINVAL, "candidate beta <= 0");
+        ssmap_steps ps = *steps;
+        ps.beta = betas[0];
+        ps.check_every = iters;          // one float64 objective after the last iteration
+        ps.flags = 0;
+        ps.stop_tol = 0.0;
+        validate_steps(ctx, lambda, &ps, iters);
+        HIPC(ctx, hipSetDevice(ctx->device));
+        // the centre patch: 3 voxels per axis (fewer on shorter axes)
+        const int64_t dims[3] = {ctx->g.nx, ctx->g.ny, ctx->g.nz};
+        int64_t org[3], pd[3];
+        for (int a = 0; a < 3; ++a) {
+            pd[a] = std::min<int64_t>(3, dims[a]);
+            org[a] = (dims[a] - pd[a]) / 2;
+        }
+        const int64_t Np = pd[0] * pd[1] * pd[2];
+        std::vector<double> Mp((size_t)Np * ctx->P);
+        for (int64_t z = 0; z < pd[2]; ++z)
+            for (int64_t y = 0; y < pd[1]; ++y)
+                for (int64_t x = 0; x < pd[0]; ++x) {
+                    const int64_t src = (org[0] + x) + dims[0] * ((org[1] + y) + dims[1] * (org[2] + z));
+                    const int64_t dst = x + pd[0] * (y + pd[1] * z);
+                    std::memcpy(&Mp[(size_t)dst * ctx->P], &M[(size_t)src * ctx->P],
+                                (size_t)ctx->P * sizeof(double));
+                }
+        // a context for the patch sharing the dictionary's factors (no new SVD)
+        pc = new ssmap_ctx();
+        pc->P = ctx->P;
+        pc->Q = ctx->Q;
+        pc->kmin = ctx->kmin;
+        pc->Qp = ctx->Qp;
+        pc->nchunk = ctx->nchunk;
+        pc->g = Grid{pd[0], pd[1], pd[2], Np};
+        pc->device = ctx->device;
+        pc->U = ctx->U;
+        pc->s = ctx->s;
+        pc->V = ctx->V;
+        pc->dtd_norm = dtd_norm_closed(pc->g);
+        for (auto &e : pc->ev) HIPC(ctx, hipEventCreate(&e));
+        HIPC(ctx, hipHostMalloc((void **)&pc->host_stats, ST_COUNT * sizeof(double)));
+        std::vector<double> F((size_t)Np * ctx->Q);
+        int best = 0;
+        std::vector<double> J(n_betas);
+        for (int i = 0; i < n_betas; ++i) {
+            ps.beta = betas[i];
+            if (ssmap_solve(pc, Mp.data(), lambda, &ps, iters, F.data()) != SSMAP_OK)
+                fail(pc->poisoned ? SSMAP_EDEVICE : SSMAP_EINVAL, "patch solve failed: " + pc->err);
+            J[i] = pc->stats.hist_objective[pc->stats.n_hist - 1];
+            if (J[i] < J[best]) best = i;
+        }
+        if (J_out) std::copy(J.begin(), J.end(), J_out);
+        *beta_out = betas[best];
+    });
+    free_ctx(pc);
+    return st;
 }
 
 ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out) {

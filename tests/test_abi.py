@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     import ctypes
-    # ssmap_steps: 2 doubles + 6 ints; ssmap_stats ends with 3 double arrays
-    assert ctypes.sizeof(_ffi.Steps) == 16 + 6 * 4
+    # ssmap_steps: 2 doubles + 6 ints + 1 double; ssmap_stats ends with 3 double arrays
+    assert ctypes.sizeof(_ffi.Steps) == 16 + 6 * 4 + 8
     assert _ffi.Stats.hist_znorm.offset + 8 * _ffi.MAX_HIST == ctypes.sizeof(_ffi.Stats)
 
 
