@@ -81,8 +81,14 @@ std::vector<FusedShape> candidate_shapes(int mode, bool planar);
 void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out,
                   const std::vector<uint8_t> *code = nullptr);
 // Per-chunk V operand blocks of the fused kernel (IterArgs::Vu points to them).
-void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
+// `tail`: the kernel takes y of ranks 16..19 on the vector ALU (fused_tail()).
+void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows, bool tail,
                     std::vector<double> &Vop);
+// Whether the fused kernel for (mode, RP, r) computes ranks 16..19 of y on the
+// vector ALU: float32 with 17 <= r <= 20 (the u K-step bucket of 5).
+inline bool fused_tail(int mode, int RP, int r) {
+    return mode == MODE_FP32 && RP == 32 && r > 16 && r <= 20;
+}
 void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vop);
 
 // f and d around a fused iteration (see kernels_common.hip):

@@ -137,14 +137,45 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, unsigned b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, RSRC_W3);
 }
 
+// Neighbour along x inside a 16-lane row by DPP: lane j takes lane j - 1
+// (SHR) or j + 1 (SHL) of its row; the lane at the row's edge keeps `edge`.
+template <bool SHR>
+__device__ __forceinline__ unsigned dpp_x(unsigned edge, unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)edge, (int)v, SHR ? 0x111 : 0x101, 0xF, 0xF,
+                                                 false);
+}
+template <bool SHR>
+__device__ __forceinline__ v4f dpp_x(v4f edge, v4f v) {
+    v4f o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        o[k] = __uint_as_float(dpp_x<SHR>(__float_as_uint(edge[k]), __float_as_uint(v[k])));
+    return o;
+}
+template <bool SHR>
+__device__ __forceinline__ v4d dpp_x(v4d edge, v4d v) {
+    v4d o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t e = __builtin_bit_cast(uint64_t, edge[k]), x = __builtin_bit_cast(uint64_t, v[k]);
+        const uint64_t lo = dpp_x<SHR>((unsigned)e, (unsigned)x);
+        const uint64_t hi = dpp_x<SHR>((unsigned)(e >> 32), (unsigned)(x >> 32));
+        o[k] = __builtin_bit_cast(double, lo | (hi << 32));
+    }
+    return o;
+}
+
 // Four state values (16 B for float, 32 B for double) through a buffer resource.
+// Stores of z^{k+1} are non-temporal (CPol NT): nothing reads them again in this
+// launch (measured 4 % faster); loads stay cached, the halo re-reads hit L2.
+constexpr int NT_STORE = 2;
 template <typename T, typename V4> struct Buf;
 template <> struct Buf<float, v4f> {
     static __device__ __forceinline__ v4f load(__amdgpu_buffer_rsrc_t r, unsigned off) {
         return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
     }
     static __device__ __forceinline__ void store(v4f v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, off, 0, NT_STORE);
     }
 };
 template <> struct Buf<double, v4d> {
@@ -157,16 +188,25 @@ template <> struct Buf<double, v4d> {
     }
     static __device__ __forceinline__ void store(v4d v, __amdgpu_buffer_rsrc_t r, unsigned off) {
         const v8u w = __builtin_bit_cast(v8u, v);
-        __builtin_amdgcn_raw_buffer_store_b128(v4u{w[0], w[1], w[2], w[3]}, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v4u{w[0], w[1], w[2], w[3]}, r, off, 0, NT_STORE);
         __builtin_amdgcn_raw_buffer_store_b128(v4u{w[4], w[5], w[6], w[7]}, r,
-                                               off == OOB ? OOB : off + 16, 0, 0);
+                                               off == OOB ? OOB : off + 16, 0, NT_STORE);
     }
 };
 
 // KSU: K-steps of the u contraction actually needed (ceil(r / 4)); RB: 16-row
 // blocks of r in the y contraction. bf16x3 uses one 32-wide K-step (KSU unused).
+// Small volumetric bricks (16 x 4 x 4: two rows per wave) of the float32 and
+// bf16x3 register-staged kernel are built for four waves per SIMD, i.e. two
+// workgroups per CU (measured faster there); the others keep the registers
+// they need (measured: capping planar bricks at 128 registers spills).
+constexpr bool fused_small(int mode, int ty, int tz) {
+    return mode != MODE_FP64 && tz > 1 && ty * tz <= 16;
+}
+constexpr int fused_occupancy(int mode, int ty, int tz) { return fused_small(mode, ty, tz) ? 4 : 1; }
+
 template <int MODE, int RB, int KSU, int TY, int TZ>
-__global__ void __launch_bounds__(NT, 1)
+__global__ void __launch_bounds__(NT, fused_occupancy(MODE, TY, TZ))
 k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles,
         int round) {
     using F = FT<MODE>;
@@ -181,6 +221,10 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     constexpr int NL = (4 * B::NSLOT + NT - 1) / NT;   // staged quads per thread
     constexpr int VB = VopSize<MODE, RB>::bytes;
     constexpr int KS = 4 * RB;           // stride of the u part of the V block
+    // ranks 17..20: y of ranks 16..19 on the vector ALU (16 FMAs per row and
+    // chunk) instead of a second, mostly padded 16-rank MFMA block
+    constexpr bool TAIL = MODE == MODE_FP32 && RB == 2 && KSU == 5;
+    constexpr int RBM = TAIL ? 1 : RB;   // 16-rank blocks on the matrix cores
     static_assert(NB % NW == 0, "brick rows must split over the waves");
     static_assert(VB % 16 == 0 && VB / 16 <= NT, "V operand block must stage in one pass");
     static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
@@ -261,9 +305,12 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     const T *wsrc = (const T *)a.w;
     T wop[BPW][BF ? 1 : KSU];
     v8bf whi[BF ? BPW : 1], wlo[BF ? BPW : 1];
-    V4 yacc[BPW][RB];
+    V4 yacc[BPW][RBM];
+    T ytail[TAIL ? BPW : 1][4];          // partial y of ranks 16..19 over this lane's nodes
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) ytail[TAIL ? b : 0][t] = (T)0;
         if constexpr (BF) {
             v4u h = v4u{0, 0, 0, 0}, l = v4u{0, 0, 0, 0};
 #pragma unroll
@@ -282,7 +329,7 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             for (int s = 0; s < KSU; ++s) wop[b][s] = wsrc[(size_t)(4 * s + i4) * N + nvox[b]];
         }
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) yacc[b][rb] = V4{0, 0, 0, 0};
+        for (int rb = 0; rb < RBM; ++rb) yacc[b][rb] = V4{0, 0, 0, 0};
     }
 
     // ---- prefetch registers: z quads of the next chunk and its V operand block
@@ -315,7 +362,8 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
 
         // V operands of this chunk (one value per lane, see the host layout)
         T vu[BF ? 1 : KSU];
-        T vy[BF ? 1 : RB][4];
+        T vy[BF ? 1 : RBM][4];
+        T vt[TAIL ? 4 : 1][4];           // V[node 4 (l/16) + i][16 + t] for the tail ranks
         v8bf vuh, vul;
         v4s vyh[RB], vyl[RB];
         if constexpr (BF) {
@@ -333,11 +381,27 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
 #pragma unroll
             for (int s = 0; s < KSU; ++s) vu[s] = VT[s * 64 + lane];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RBM; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) vy[rb][i] = VT[(KS + rb * 4 + i) * 64 + lane];
+            if constexpr (TAIL) {
+                const T *VTt = VT + (KS + 4) * 64 + i4 * 16;   // tail table, see the host layout
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) vt[i][t] = VTt[i * 4 + t];
+            }
         }
 
+        // when the rows of a wave stack along z, this lane's z^k of every row
+        // is read once and also serves as the z neighbours of the adjacent rows
+        const V4 *L = lds + i4 * B::NSP;
+        constexpr bool ZREG = TY == NW;      // row b + 1 of a wave is one step along z
+        V4 zcs[ZREG ? BPW : 1];
+        if constexpr (ZREG) {
+#pragma unroll
+            for (int b = 0; b < BPW; ++b) zcs[b] = L[slot0[b]];
+        }
 #pragma unroll
         for (int b = 0; b < BPW; ++b) {
             // u = V_r w^k for 16 nodes x 16 voxels
@@ -351,13 +415,27 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
 #pragma unroll
                 for (int s = 0; s < KSU; ++s) u = F::mfma(vu[s], wop[b][s], u);
             }
-            // D^T D z^k on the four planes of this lane, from LDS: neighbours outside
-            // the grid were staged as zeros, so deg * z - sum(neighbours) is exact
-            const V4 *L = lds + i4 * B::NSP;
+            // D^T D z^k on the four planes of this lane: neighbours outside the grid
+            // were staged as zeros, so deg * z - sum(neighbours) is exact
             const int sl = slot0[b];
-            const V4 zc = L[sl];
-            const V4 nsum = (L[sl - 1] + L[sl + 1]) + (L[sl - B::SX] + L[sl + B::SX]) +
-                            (L[sl - B::SX * B::SY] + L[sl + B::SX * B::SY]);
+            constexpr int SZ = B::SX * B::SY;
+            V4 zc, nsum;
+            if constexpr (ZREG) {
+                // x: the adjacent lanes of the row (DPP), the halo slot only at the
+                // row ends; y from LDS; z from this lane's other rows when adjacent
+                zc = zcs[ZREG ? b : 0];
+                V4 hm = V4{0, 0, 0, 0}, hp = V4{0, 0, 0, 0};
+                if (j == 0) hm = L[sl - 1];
+                if (j == 15) hp = L[sl + 1];
+                const V4 xm = dpp_x<true>(hm, zc), xp = dpp_x<false>(hp, zc);
+                const V4 zm = b > 0 ? zcs[b > 0 ? b - 1 : 0] : L[sl - SZ];
+                const V4 zp = b + 1 < BPW ? zcs[b + 1 < BPW ? b + 1 : 0] : L[sl + SZ];
+                nsum = (xm + xp) + (L[sl - B::SX] + L[sl + B::SX]) + (zm + zp);
+            } else {
+                zc = L[sl];
+                nsum = (L[sl - 1] + L[sl + 1]) + (L[sl - B::SX] + L[sl + B::SX]) +
+                       (L[sl - SZ] + L[sl + SZ]);
+            }
             const V4 lap = deg[b] * zc - nsum;
             // projected z-update (Eq. z2 with f substituted)
             V4 zn = zc - tau * (lam2 * lap - beta * u);
@@ -377,13 +455,32 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             } else {
                 // y^{k+1} += V_r^T z^{k+1}: K-row l/16 of step i is node 4*(l/16)+i
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
+                for (int rb = 0; rb < RBM; ++rb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
                         yacc[b][rb] = F::mfma(vy[rb][i], zn[i], yacc[b][rb]);
+                if constexpr (TAIL) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) ytail[b][t] += vt[i][t] * zn[i];
+                }
             }
         }
         __syncthreads();
+    }
+
+    // ---- tail ranks: sum the four node groups (lanes j, j+16, j+32, j+48)
+    if constexpr (TAIL) {
+#pragma unroll
+        for (int b = 0; b < BPW; ++b)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                T v = ytail[b][t];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                ytail[b][t] = v;
+            }
     }
 
     // ---- r-vector recursion; lane holds y^{k+1}[r][voxel j] for the four
@@ -401,8 +498,19 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             for (int i = 0; i < 4; ++i) {
                 // f64 16x16x4 returns rows l/16 + 4 i; the others rows 4 (l/16) + i
                 const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
+                if (r >= a.r) continue;          // padded ranks stay 0 (never stored)
                 const size_t o = (size_t)r * N + nvox[b];
-                const T yn = yacc[b][rb][i];
+                T yn;
+                if constexpr (TAIL) {
+                    if (rb == 0) {
+                        yn = yacc[b][0][i];
+                    } else {                     // r in 16..19 here (a.r <= 20)
+                        const int t = r - 16;
+                        yn = t == 0 ? ytail[b][0] : t == 1 ? ytail[b][1] : t == 2 ? ytail[b][2] : ytail[b][3];
+                    }
+                } else {
+                    yn = yacc[b][rb][i];
+                }
                 const T wn = ah[o] - bc[r] * ((T)2 * yn - yold[o] - wsrc[o]);
                 const unsigned ob = valid[b] ? (unsigned)(o * sizeof(T)) : OOB;
                 if constexpr (sizeof(T) == 8) {
@@ -703,9 +811,10 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
 
 template <int MODE, int RB, int KSU, int TY, int TZ>
 void launch_t(const FusedLaunch &L, hipStream_t s) {
-    // float64 and float32 stage through registers (measured faster for float32),
-    // bf16x3 through direct LDS loads
-    if constexpr (MODE == MODE_BF16X3)
+    // bf16x3 stages the small volumetric brick through registers (four waves
+    // per SIMD) and the others through direct LDS loads; float32 and float64
+    // always through registers
+    if constexpr (MODE == MODE_BF16X3 && !fused_small(MODE, TY, TZ))
         hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s,
                            L.jobs, L.tiles, L.ntiles, L.round);
     else
@@ -751,6 +860,7 @@ bool fused_supported(int mode, int RP, int64_t N) {
 
 FusedShape default_shape(int mode, const Grid &g) {
     if (mode == MODE_FP64) return g.nz == 1 ? FusedShape{16, 1} : FusedShape{4, 4};
+    if (mode == MODE_BF16X3) return g.nz == 1 ? FusedShape{16, 1} : FusedShape{4, 4};
     return g.nz == 1 ? FusedShape{16, 1} : FusedShape{8, 4};
 }
 
@@ -844,7 +954,7 @@ void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vec
 // one rows l/16 + 4 i; row() maps an MFMA output row of u to the chunk node
 // that lane must hold (node 4 (l/16) + i): identity for f32, m -> 4 (m % 4)
 // + m / 4 for f64.
-void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows,
+void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows, bool tail,
                     std::vector<double> &Vop) {
     const int nchunk = Qp / QC, RB = RP / 16, KS = 4 * RB;
     const size_t per = (size_t)(KS + 4 * RB) * 64;
@@ -857,11 +967,16 @@ void fused_operands(const std::vector<double> &Vh, int Qp, int RP, bool f64_rows
             const int row = f64_rows ? 4 * (m % 4) + m / 4 : m;
             for (int s = 0; s < KS; ++s)
                 U[s * 64 + l] = Vh[(size_t)(16 * c + row) * RP + 4 * s + l / 16];
-            for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < (tail ? 1 : RB); ++rb)
                 for (int i = 0; i < 4; ++i)
                     Y[(rb * 4 + i) * 64 + l] =
                         Vh[(size_t)(16 * c + 4 * (l / 16) + i) * RP + 16 * rb + l % 16];
         }
+        if (tail)   // [g][i][t] = V[node 4 g + i][rank 16 + t], g = lane / 16
+            for (int g = 0; g < 4; ++g)
+                for (int i = 0; i < 4; ++i)
+                    for (int t = 0; t < 4; ++t)
+                        Y[4 * 64 + (g * 4 + i) * 4 + t] = Vh[(size_t)(16 * c + 4 * g + i) * RP + 16 + t];
     }
 }
 

@@ -83,7 +83,7 @@ void host_consts(int mode, const std::vector<double> &U, const std::vector<doubl
         as_bytes(v16, out.Vop);
     } else {
         std::vector<double> v64;
-        fused_operands(out.Vh, Qp, RP, mode == MODE_FP64, v64);
+        fused_operands(out.Vh, Qp, RP, mode == MODE_FP64, fused_tail(mode, RP, r), v64);
         if (mode == MODE_FP64) as_bytes(v64, out.Vop);
         else as_bytes(std::vector<float>(v64.begin(), v64.end()), out.Vop);
     }
