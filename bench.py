@@ -400,6 +400,17 @@ def bench_serve(args):
             firsts.setdefault(sp["Q"], sp)
         cpu = cpu_baseline_serve(list(firsts.values()))
     achieved = alg / (makespan_ms / 1e3) / 1e9
+    by_class = {}
+    for j, l_cb, l_seq in zip(jobs, lat, seq_lat):
+        c = by_class.setdefault(f"Q={j['Q']} {j['prec']}", dict(jobs=0, cb=[], seq=[], voxels=0))
+        c["jobs"] += 1
+        c["voxels"] += j["N"]
+        c["cb"].append(l_cb)
+        c["seq"].append(l_seq)
+    classes = {k: dict(jobs=v["jobs"], voxels=v["voxels"], p50_ms=percentile(v["cb"], 50),
+                       max_ms=max(v["cb"]), one_at_a_time_p50_ms=percentile(v["seq"], 50),
+                       one_at_a_time_max_ms=max(v["seq"]))
+               for k, v in sorted(by_class.items())}
     line = {
         "metric": METRIC, "value": value, "unit": "voxel-iterations/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": makespan_ms, "higher_is_better": True,
@@ -415,6 +426,7 @@ def bench_serve(args):
                           "voxel_iter_per_s": vox_it / (seq_makespan / 1e3)},
         "server": {"launches": stats["launches"], "peak_bytes": stats["peak_bytes"],
                    "wall_s": wall},
+        "latency_by_class": classes,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "shared fused launches, all classes (aggregate over the makespan)",

@@ -263,7 +263,8 @@ void ssmap_batch_destroy(ssmap_batch *b);
  * admission to retirement. Admission is first in, first out under a device-
  * memory budget reserved at creation; a job that does not fit waits, and so
  * do the jobs behind it. Running jobs of one class (precision, padded rank,
- * u K-step bucket, brick shape) advance together, one iteration per shared
+ * u K-step bucket, brick shape, and size band: below 64 MB, below 1 GB or
+ * above of state moved per iteration) advance together, one iteration per shared
  * fused launch; a job joins its class at an iteration boundary and leaves
  * after its last iteration while the others keep running (continuous
  * batching). Classes are spread over up to four HIP streams and progress

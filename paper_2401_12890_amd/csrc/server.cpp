@@ -13,7 +13,8 @@
 //   * Staging- a pinned host ring that feeds every host-to-device upload, so
 //              enqueueing never blocks on pageable copies.
 //   * Class  - running jobs sharing a fused kernel (precision, padded rank,
-//              u K-step bucket, brick shape), with its own round counter, a
+//              u K-step bucket, brick shape) and a size band (bytes moved per
+//              iteration), with its own round counter, a
 //              device descriptor/brick table rebuilt when membership changes,
 //              and a lane. Each job's descriptor pair is picked by
 //              (round + phase) & 1, the phase being its admission round.
@@ -164,6 +165,7 @@ struct Job {
 
 struct Class {
     int mode = 0, RP = 0, rkey = 0;       // rkey: largest rank of the K-step bucket
+    int band = 0;                         // size band of the member jobs
     FusedShape shape{16, 1};
     int lane = 0;
     int64_t round = 0;
@@ -363,21 +365,38 @@ Consts &get_consts(ssmap_server *sv, Dict &d, const Job &j, int li) {
     return d.consts.emplace(key, c).first->second;
 }
 
+// Size band of a job by the bytes one iteration moves: a job shares launches
+// only with jobs of its band, so a small job's iteration is not as long as a
+// large job's (< 64 MB, < 1 GB, larger).
+int size_band(const ssmap_server *sv, const Job &j) {
+    const double bytes = (double)j.g.N * (2.0 * sv->dicts[j.dict].Qp + 5.0 * j.RP) *
+                         (j.mode == MODE_FP64 ? 8.0 : 4.0);
+    return bytes < 64e6 ? 0 : bytes < 1e9 ? 1 : 2;
+}
+
 int find_class(ssmap_server *sv, const Job &j) {
     const FusedShape sh = default_shape(j.mode, j.g);
     const int rk = j.mode == MODE_BF16X3 ? j.RP : bucket_rank(j.r);
+    const int band = size_band(sv, j);
+    int in_band = 0;
     for (size_t c = 0; c < sv->classes.size(); ++c) {
         const Class &C = sv->classes[c];
         if (C.mode == j.mode && C.RP == j.RP && C.rkey == rk && C.shape.ty == sh.ty &&
-            C.shape.tz == sh.tz)
+            C.shape.tz == sh.tz && C.band == band)
             return (int)c;
+        in_band += C.band == band;
     }
     Class C;
     C.mode = j.mode;
     C.RP = j.RP;
     C.rkey = rk;
     C.shape = sh;
-    C.lane = (int)(sv->classes.size() % sv->nlanes);
+    C.band = band;
+    // small and middle bands get a stream each, the large band the rest, so
+    // short launches never queue behind long ones in one stream
+    const int L = sv->nlanes;
+    if (band < 2) C.lane = std::min(band, L - 1);
+    else C.lane = L > 2 ? 2 + in_band % (L - 2) : L - 1;
     sv->classes.push_back(C);
     sv->stats.classes = (int)sv->classes.size();
     return (int)sv->classes.size() - 1;
