@@ -33,11 +33,16 @@ WORKLOADS = {
     "c1": "2-D diffusion-relaxation 32x32, P=30, Q=100 (10x10), fp64, 500 iters",
     "c4": "64 uneven 2-D slices (sides 48..256), P in {30,60}, Q in {100,400,1600}, one batch, "
           "200 iters",
+    "c3x": "3-D T1-T2 fingerprinting-like 96x96x32, P=1000, Q=1024 (32x32) at the exact rank "
+           "r=min(P,Q)=1000 (unapproximated K), bf16x3 GEMM path, 300 iters",
     "c5": "served stream: Poisson arrivals, N log-uniform 1e3..1e6 (2-D up to 65,536, else "
           "nz=32), Q in {100 fp64 500 it, 400 fp32 300 it, 1024 bf16x3 300 it, "
           "1600 fp32 300 it}",
 }
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 state)"}
+# workloads that run a recipe at another rank: name -> (recipe, rank)
+RECIPE = {"c3x": ("c3", -1)}
+MFMA_PEAK_TFS = {"bf16x3": 2500.0, "fp32": 157.3}    # dense MI355X matrix peaks
 
 
 def log(*a):
@@ -117,13 +122,15 @@ def measured_traffic(workload):
     return kib * 1024.0
 
 
-def cpu_baseline(name, seconds_hint=20.0):
+def cpu_baseline(name, seconds_hint=20.0, rank=0):
     """The FP64 oracle, untuned, on a bounded sample of the same workload."""
     import numpy as np
 
     import oracle
     from paper_2401_12890_amd import synth
     grid = {"c2": (64, 64, 8), "c3": (48, 48, 8), "c1": (32, 32, 1)}[name]
+    if rank == -1:
+        grid = (24, 24, 8)
     prob = synth.generate(name, grid=grid)
     try:
         from threadpoolctl import threadpool_info
@@ -131,19 +138,20 @@ def cpu_baseline(name, seconds_hint=20.0):
     except Exception:
         cores = os.cpu_count() or 1
     t0 = time.perf_counter()
-    oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, 1)
+    oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, 1, rank=rank)
     t1 = time.perf_counter()
     one = t1 - t0
     n_it = 6
     t0 = time.perf_counter()
-    oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, 1 + n_it)
+    oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, 1 + n_it, rank=rank)
     t1 = time.perf_counter()
     per_iter = max((t1 - t0) - one, 1e-9) / n_it
     N = prob.N
     return {"value": N / per_iter, "unit": "voxel-iterations/s", "cores": int(cores),
             "kind": "oracle",
             "sample": f"{name} generator on a {grid[0]}x{grid[1]}x{grid[2]} grid ({N} voxels, "
-                      f"Q={prob.Q}), {n_it} float64 iterations after one, NumPy "
+                      f"Q={prob.Q}{', exact rank' if rank == -1 else ''}), {n_it} float64 "
+                      f"iterations after one, NumPy "
                       f"{np.__version__}, {platform.processor() or platform.machine()}"}
 
 
@@ -472,7 +480,8 @@ def main():
     if args.workload == "c5":
         return bench_serve(args)
     log("generating workload", args.workload)
-    prob = synth.generate(args.workload, iters=args.iters, grid=args.grid)
+    recipe, rank = RECIPE.get(args.workload, (args.workload, 0))
+    prob = synth.generate(recipe, iters=args.iters, grid=args.grid)
     prec = args.precision or prob.precision
     iters = prob.iters
     dt = torch.float64 if prec == "fp64" else torch.float32
@@ -482,12 +491,12 @@ def main():
     mp = _ffi.Mapper(prob.K, prob.grid)
     setup_ms = mp.stats()["setup_ms"]
     stream = torch.cuda.current_stream()
-    kw = dict(precision=prec, kernel=args.kernel)
+    kw = dict(precision=prec, kernel=args.kernel, rank=rank)
     log("warmup", args.warmup)
     for _ in range(args.warmup):
         mp.solve_torch(M, prob.lam, prob.beta, iters, F=F, stream=stream, **kw)
     torch.cuda.synchronize()
-    lat, loop_ms = [], []
+    lat, loop_ms, gemm = [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -496,7 +505,9 @@ def main():
         ts = time.perf_counter()
         mp.solve_torch(M, prob.lam, prob.beta, iters, F=F, stream=stream, **kw)
         lat.append((time.perf_counter() - ts) * 1e3)
-        loop_ms.append(mp.stats()["iterate_ms"])
+        sk = mp.stats()
+        loop_ms.append(sk["iterate_ms"])
+        gemm.append((sk["gemm_ms"], sk["gemm_flops"]))
         log(f"step {k}: {lat[-1]:.2f} ms (loop {loop_ms[-1]:.2f} ms)")
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -512,15 +523,33 @@ def main():
     per_launch_ms = (sum(loop_ms) / len(loop_ms)) / iters
     alg = alg_bytes_per_voxel_iter(prob.Q, r, wbytes) * prob.N
     achieved = alg / (per_launch_ms / 1e3) / 1e9
-    kern_name = "ssmap_iter_fused" if st["kernel"] == 2 else "k_update+k_projw (unfused)"
-    traffic = measured_traffic(args.workload) if args.kernel in ("auto", "fused") else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kern_name, "avg_launch_ms": round(per_launch_ms, 5),
-                "alg_bytes_per_launch": alg}
+    kern_name = {1: "k_update+k_projw (unfused)", 2: "k_fused", 3: "k_gemm_tn (GEMM path)"}[st["kernel"]]
+    if st["kernel"] == 3:
+        # dominant kernel: the GEMM (two launches per iteration, equal flops), timed by the
+        # library's HIP events around each launch. Algorithmic flops: the two contractions
+        # at the unpadded rank, 2 x 2 r Q per voxel, times 3 bf16 products for bf16x3.
+        g_ms = sum(x[0] for x in gemm) / len(gemm)
+        n_launch = 2 * iters
+        split = 3 if prec == "bf16x3" else 1
+        alg_flops = 2.0 * r * prob.Q * prob.N * split          # per launch
+        per_gemm_ms = g_ms / n_launch
+        achieved_t = alg_flops / (per_gemm_ms / 1e3) / 1e12
+        peak = MFMA_PEAK_TFS[prec]
+        roofline = {"bound": "mfma", "achieved": round(achieved_t, 1), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved_t / peak, 4), "traffic": None,
+                    "kernel": kern_name, "avg_launch_ms": round(per_gemm_ms, 5),
+                    "alg_flops_per_launch": alg_flops,
+                    "issued_flops_per_launch": sum(x[1] for x in gemm) / len(gemm) / n_launch,
+                    "gemm_share_of_loop": round(g_ms / (sum(loop_ms) / len(loop_ms)), 4)}
+    else:
+        traffic = measured_traffic(args.workload) if args.kernel in ("auto", "fused") else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": kern_name, "avg_launch_ms": round(per_launch_ms, 5),
+                    "alg_bytes_per_launch": alg}
 
     parity = None
-    if not args.no_parity:
+    if not args.no_parity and rank == 0:
         log("sampled parity vs stored oracle values")
         parity = sampled_parity(mp, prob, prec, args.kernel)
     mp.close()
@@ -528,7 +557,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(args.workload)
+        cpu = cpu_baseline(recipe, rank=rank)
 
     out = {
         "metric": METRIC, "value": value, "unit": "voxel-iterations/s", "n_gpus": 1,

@@ -66,9 +66,16 @@ typedef enum {
 
 /* Kernel family for the iteration (both compute the same iterates). */
 typedef enum {
-    SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows, else unfused */
+    SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows (r <= 32); else
+                               the GEMM path for float32 / bf16x3 without monitoring
+                               or aux output; else unfused                        */
     SSMAP_KERNEL_UNFUSED = 1,
-    SSMAP_KERNEL_FUSED = 2
+    SSMAP_KERNEL_FUSED = 2,
+    SSMAP_KERNEL_GEMM = 3   /* any rank, float32 / bf16x3: the two contractions as
+                               MFMA-tiled GEMMs over all voxels (compute bound at
+                               high rank), the stencil / z-update and r-vector
+                               recursion as elementwise passes; check_every = 0,
+                               no SSMAP_KEEP_AUX                                   */
 } ssmap_kernel;
 
 enum {
@@ -113,6 +120,8 @@ typedef struct {
     double iterate_ms;      /* the iteration loop, monitoring included             */
     double output_ms;       /* z^K to the voxel-major output                        */
     double device_bytes;    /* device memory held by the context                   */
+    double gemm_ms;         /* GEMM path: time in the two products (events)        */
+    double gemm_flops;      /* GEMM path: flops of the two products as issued      */
     int hist_iter[SSMAP_MAX_HIST];
     double hist_objective[SSMAP_MAX_HIST];  /* 1/2||m - K_r z||^2 + lambda R(z)    */
     double hist_dual[SSMAP_MAX_HIST];       /* beta ||z^k - z^{k-1}||               */

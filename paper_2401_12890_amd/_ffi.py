@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "SSMAP_OK", -1: "SSMAP_EINVAL", -2: "SSMAP_ENOMEM", -3: "SSMA
                 -4: "SSMAP_ENONFINITE", -5: "SSMAP_ENODEV"}
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-KERNELS = {"auto": 0, "unfused": 1, "fused": 2}
+KERNELS = {"auto": 0, "unfused": 1, "fused": 2, "gemm": 3}
 SSMAP_KEEP_AUX = 1
 MAX_HIST = 512
 
@@ -53,6 +53,7 @@ class Stats(ctypes.Structure):
                 ("sigma_max", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("project_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
                 ("output_ms", ctypes.c_double), ("device_bytes", ctypes.c_double),
+                ("gemm_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
                 ("hist_iter", ctypes.c_int * MAX_HIST),
                 ("hist_objective", ctypes.c_double * MAX_HIST),
                 ("hist_dual", ctypes.c_double * MAX_HIST),
@@ -241,7 +242,7 @@ def ssmap_get_stats(ctx: int) -> dict:
                 iters=s.iters, xi_p=s.xi_p, tau=s.tau, dtd_norm=s.dtd_norm,
                 sigma_max=s.sigma_max, setup_ms=s.setup_ms, project_ms=s.project_ms,
                 iterate_ms=s.iterate_ms, output_ms=s.output_ms, device_bytes=s.device_bytes,
-                hist_iter=list(s.hist_iter[:n]), hist_objective=list(s.hist_objective[:n]),
+                gemm_ms=s.gemm_ms, gemm_flops=s.gemm_flops, hist_iter=list(s.hist_iter[:n]), hist_objective=list(s.hist_objective[:n]),
                 hist_dual=list(s.hist_dual[:n]), hist_znorm=list(s.hist_znorm[:n]))
 
 

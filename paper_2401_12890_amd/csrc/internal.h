@@ -151,6 +151,21 @@ double masked_dtd_norm(const Grid &g, const std::vector<uint8_t> &code);
 bool brick_has_inside(const Grid &g, const std::vector<uint8_t> &code, int64_t x0, int64_t y0,
                       int64_t z0, int tx, int ty, int tz);
 
+// ---- exact-rank GEMM path (kernels_gemm.hip); voxel-major padded layouts
+// C[n][m] = sum_k A[m][k] B[n][k]; A: M x K, B: N x K, C: N x M (row-major),
+// float32 or bf16 operands (bf16 = true), float32 result. M a multiple of
+// 128, K of 16 (float32) or 64 (bf16); false when the shape is not supported.
+bool launch_gemm_tn(bool bf16, const void *A, const void *B, float *C, int M, int K, int64_t N,
+                    hipStream_t s);
+void launch_gemm_update(const float *z, const float *u, float *zn, uint16_t *zs, Grid g, int Qg,
+                        double tau, double lam2, double beta, const uint8_t *code, hipStream_t s);
+void launch_gemm_w(const float *ah, const float *ynew, const float *yold, float *w, uint16_t *ws,
+                   const float *bcoef, int64_t N, int Rg, hipStream_t s);
+void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, int64_t N, int Rg,
+                            hipStream_t s);
+void launch_gemm_output(const float *z, void *F, bool to_double, int64_t N, int Q, int Qg,
+                        hipStream_t s);
+
 // Fill a device array of `count` elements of `elem_bytes` (4 or 8) with zero.
 void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s);
 

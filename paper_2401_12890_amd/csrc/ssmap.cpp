@@ -126,6 +126,7 @@ struct ssmap_ctx {
     int64_t inside = 0;
     hipEvent_t ev[6] = {};
     double *host_stats = nullptr;         // pinned ST_COUNT doubles
+    std::vector<hipEvent_t> gemm_ev;      // GEMM path: 4 timing events per iteration
 };
 
 namespace {
@@ -172,6 +173,17 @@ void *ensure(ssmap_ctx *c, const std::string &name, size_t bytes) {
     return p;
 }
 
+// The four timing events of GEMM-path iteration k (created on first use).
+hipEvent_t *gemm_events(ssmap_ctx *c, int k) {
+    const size_t need = 4 * (size_t)(k + 1);
+    while (c->gemm_ev.size() < need) {
+        hipEvent_t e = nullptr;
+        HIPC(c, hipEventCreate(&e));
+        c->gemm_ev.push_back(e);
+    }
+    return &c->gemm_ev[4 * (size_t)k];
+}
+
 // Device copy of the mask codes (NULL without a mask).
 const uint8_t *mask_dev(ssmap_ctx *c) {
     if (c->code.empty()) return nullptr;
@@ -199,6 +211,8 @@ struct Plan {
     int mode, r, RP;
     double xi, tau, beta, lam;
     bool fused;
+    bool gemm;         // exact-rank path: contractions as GEMMs (ranks above 32)
+    int Qg, Rg;        // its padded node and rank counts (multiples of 128)
 };
 
 double elapsed_ms(hipEvent_t a, hipEvent_t b) {
@@ -217,7 +231,7 @@ void validate_steps(ssmap_ctx *c, double lambda, const ssmap_steps *st, int iter
     if (st->precision < SSMAP_FP64 || st->precision > SSMAP_BF16X3)
         fail(SSMAP_EINVAL, "unknown precision");
     if (st->check_every < 0) fail(SSMAP_EINVAL, "check_every must be >= 0");
-    if (st->kernel < SSMAP_KERNEL_AUTO || st->kernel > SSMAP_KERNEL_FUSED)
+    if (st->kernel < SSMAP_KERNEL_AUTO || st->kernel > SSMAP_KERNEL_GEMM)
         fail(SSMAP_EINVAL, "unknown kernel");
     if (!(std::isfinite(st->stop_tol) && st->stop_tol >= 0))
         fail(SSMAP_EINVAL, "stop_tol must be finite and >= 0");
@@ -238,6 +252,14 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
     if (st->kernel == SSMAP_KERNEL_FUSED && !can_fuse)
         fail(SSMAP_EINVAL, "no fused kernel for this precision and rank");
     p.fused = st->kernel == SSMAP_KERNEL_FUSED || (st->kernel == SSMAP_KERNEL_AUTO && can_fuse);
+    // GEMM path: float32 / bf16x3 without monitoring or aux output; AUTO takes
+    // it where no fused kernel exists
+    const bool gemm_ok = p.mode != MODE_FP64 && st->check_every == 0 && !(st->flags & SSMAP_KEEP_AUX);
+    if (st->kernel == SSMAP_KERNEL_GEMM && !gemm_ok)
+        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without monitoring or aux output");
+    p.gemm = st->kernel == SSMAP_KERNEL_GEMM || (st->kernel == SSMAP_KERNEL_AUTO && !can_fuse && gemm_ok);
+    p.Qg = (c->Q + 127) / 128 * 128;
+    p.Rg = (p.r + 127) / 128 * 128;
     return p;
 }
 
@@ -259,6 +281,11 @@ struct Prepared {
     int iters = 0;
     double stop_tol = 0.0;
     int check_every = 0;
+    // GEMM path (voxel-major, padded): z, y ping-pong; u; w, a.h; bf16 splits; constants
+    float *gz[2] = {nullptr, nullptr}, *gy[2] = {nullptr, nullptr}, *gu = nullptr, *gw = nullptr,
+          *gah = nullptr, *gb = nullptr;
+    uint16_t *gzs = nullptr, *gws = nullptr;
+    const void *gAu = nullptr, *gAy = nullptr;
 };
 
 IterArgs args_for(const Prepared &P, int k) {
@@ -287,10 +314,17 @@ void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
     HIPC(c, hipGetLastError());
 }
 
+Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s);
+
 Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *st, int iters,
                  hipStream_t s) {
     Prepared P;
     P.pl = make_plan(c, lambda, st);
+    if (P.pl.gemm) {
+        P.dM = dM;
+        P.iters = iters;
+        return prepare_gemm(c, P, s);
+    }
     const Plan &pl = P.pl;
     P.dM = dM;
     P.iters = iters;
@@ -411,6 +445,178 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     return P;
 }
 
+// ---- exact-rank GEMM path: constants, projection and state in its layouts
+Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
+    const Plan &pl = P.pl;
+    const int64_t N = c->g.N;
+    const int Pm = c->P, Q = c->Q, Qp = c->Qp, r = pl.r, RP = pl.RP, Qg = pl.Qg, Rg = pl.Rg;
+    const bool bf = pl.mode == MODE_BF16X3;
+    const int Ku = bf ? 3 * Rg : Rg, Ky = bf ? 3 * Qg : Qg;
+    const size_t esA = bf ? 2 : 4;
+    const size_t zb = (size_t)N * Qg * 4, rb = (size_t)N * Rg * 4;
+    std::vector<std::pair<std::string, size_t>> need = {
+        {"gz0", zb}, {"gz1", zb}, {"gu", zb}, {"gy0", rb}, {"gy1", rb}, {"gw", rb}, {"gah", rb},
+        {"gb", (size_t)Rg * 4}, {"gAu", (size_t)Qg * Ku * esA}, {"gAy", (size_t)Rg * Ky * esA},
+        {"Ur", (size_t)Pm * r * 8}, {"sig", (size_t)RP * 8}, {"acoef", (size_t)RP * 8}, {"bad", 256}};
+    if (bf) {
+        need.push_back({"gzs", (size_t)N * 3 * Qg * 2});
+        need.push_back({"gws", (size_t)N * 3 * Rg * 2});
+    }
+    plan_check(c, need);
+    for (int k = 0; k < 2; ++k) {
+        P.gz[k] = (float *)ensure(c, k ? "gz1" : "gz0", zb);
+        P.gy[k] = (float *)ensure(c, k ? "gy1" : "gy0", rb);
+    }
+    P.gu = (float *)ensure(c, "gu", zb);
+    P.gw = (float *)ensure(c, "gw", rb);
+    P.gah = (float *)ensure(c, "gah", rb);
+    P.gb = (float *)ensure(c, "gb", (size_t)Rg * 4);
+    if (bf) {
+        P.gzs = (uint16_t *)ensure(c, "gzs", (size_t)N * 3 * Qg * 2);
+        P.gws = (uint16_t *)ensure(c, "gws", (size_t)N * 3 * Rg * 2);
+    }
+    void *Au = ensure(c, "gAu", (size_t)Qg * Ku * esA), *Ay = ensure(c, "gAy", (size_t)Rg * Ky * esA);
+    double *Ur = (double *)ensure(c, "Ur", (size_t)Pm * r * 8);
+    P.sig = (double *)ensure(c, "sig", (size_t)RP * 8);
+    double *acoef = (double *)ensure(c, "acoef", (size_t)RP * 8);
+
+    // constants: A of u (Qg x Ku, row-major) and A of y (Rg x Ky); bf16x3 concatenates
+    // hi | hi | lo along K against the operands' hi | lo | hi
+    HostConsts hc;
+    host_consts(pl.mode, c->U, c->s, c->V, c->kmin, Pm, Q, Qp, r, RP, pl.beta, false, hc);
+    auto Vf = [&](int q, int i) -> float {
+        return (q < Q && i < r) ? (float)hc.Vh[(size_t)q * RP + i] : 0.0f;
+    };
+    std::vector<float> bg(Rg, 0.0f);
+    for (int i = 0; i < r; ++i) bg[i] = (float)(c->s[i] * c->s[i] / (pl.beta + c->s[i] * c->s[i]));
+    if (bf) {
+        auto bits = [](float x) {
+            uint32_t u;
+            std::memcpy(&u, &x, 4);
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            return (uint16_t)(u >> 16);
+        };
+        auto val = [](uint16_t b) {
+            const uint32_t u = (uint32_t)b << 16;
+            float x;
+            std::memcpy(&x, &u, 4);
+            return x;
+        };
+        std::vector<uint16_t> au((size_t)Qg * Ku), ay((size_t)Rg * Ky);
+        for (int q = 0; q < Qg; ++q)
+            for (int i = 0; i < Rg; ++i) {
+                const float f = Vf(q, i);
+                const uint16_t h = bits(f), l = bits(f - val(h));
+                au[(size_t)q * Ku + i] = h;
+                au[(size_t)q * Ku + Rg + i] = h;
+                au[(size_t)q * Ku + 2 * Rg + i] = l;
+                ay[(size_t)i * Ky + q] = h;
+                ay[(size_t)i * Ky + Qg + q] = h;
+                ay[(size_t)i * Ky + 2 * Qg + q] = l;
+            }
+        HIPC(c, hipMemcpyAsync(Au, au.data(), au.size() * 2, hipMemcpyHostToDevice, s));
+        HIPC(c, hipMemcpyAsync(Ay, ay.data(), ay.size() * 2, hipMemcpyHostToDevice, s));
+        HIPC(c, hipStreamSynchronize(s));
+    } else {
+        std::vector<float> au((size_t)Qg * Ku), ay((size_t)Rg * Ky);
+        for (int q = 0; q < Qg; ++q)
+            for (int i = 0; i < Rg; ++i) {
+                au[(size_t)q * Ku + i] = Vf(q, i);
+                ay[(size_t)i * Ky + q] = Vf(q, i);
+            }
+        HIPC(c, hipMemcpyAsync(Au, au.data(), au.size() * 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipMemcpyAsync(Ay, ay.data(), ay.size() * 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipStreamSynchronize(s));
+    }
+    P.gAu = Au;
+    P.gAy = Ay;
+    HIPC(c, hipMemcpyAsync(P.gb, bg.data(), Rg * 4, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(Ur, hc.Ur.data(), hc.Ur.size() * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(P.sig, hc.sig.data(), RP * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(acoef, hc.a.data(), RP * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipStreamSynchronize(s));     // host staging vectors are locals
+
+    ssmap_stats &S = c->stats;
+    const double setup = S.setup_ms;
+    std::memset(&S, 0, sizeof(S));
+    S.setup_ms = setup;
+    S.rank = r;
+    S.rank_padded = Rg;
+    S.precision = pl.mode;
+    S.kernel = SSMAP_KERNEL_GEMM;
+    S.xi_p = pl.xi;
+    S.tau = pl.tau;
+    S.dtd_norm = c->dtd_norm;
+    S.sigma_max = c->s.empty() ? 0.0 : c->s[0];
+    c->aux_valid = false;
+
+    // a1: projection into rank-major temporaries (gy0: a.h and w^0, gy1: y^0), then the
+    // voxel-major a.h, w^0 (and its split); z^0 = 0, y^0 = 0
+    HIPC(c, hipEventRecord(c->ev[0], s));
+    int *bad = (int *)ensure(c, "bad", 256);
+    launch_zero(bad, 1, 4, s);
+    launch_project(pl.mode, P.dM, Pm, Ur, P.sig, acoef, r, RP, N, nullptr, nullptr, P.gy[0], P.gy[0],
+                   P.gy[1], bad, mask_dev(c), s);
+    launch_gemm_from_ranks(P.gy[0], RP, P.gah, nullptr, N, Rg, s);
+    launch_gemm_from_ranks(P.gy[0], RP, P.gw, P.gws, N, Rg, s);
+    for (int k = 0; k < 2; ++k) {
+        launch_zero(P.gz[k], (size_t)N * Qg, 4, s);
+        launch_zero(P.gy[k], (size_t)N * Rg, 4, s);
+    }
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipEventRecord(c->ev[1], s));
+    int badh = 0;
+    HIPC(c, hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (badh) fail(SSMAP_ENONFINITE, "M holds a NaN or Inf");
+    return P;
+}
+
+// One GEMM-path iteration k: u = V_r w^k; z-update; y^{k+1} = V_r^T z^{k+1}; w^{k+1}.
+// The two products are bracketed by timing events (stats.gemm_ms).
+void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
+    const Plan &pl = P.pl;
+    const bool bf = pl.mode == MODE_BF16X3;
+    const int64_t N = c->g.N;
+    const int Qg = pl.Qg, Rg = pl.Rg;
+    const float *z = P.gz[k & 1];
+    float *zn = P.gz[(k + 1) & 1];
+    const float *yo = P.gy[k & 1];
+    float *yn = P.gy[(k + 1) & 1];
+    hipEvent_t *ev = gemm_events(c, k);
+    HIPC(c, hipEventRecord(ev[0], s));
+    if (!launch_gemm_tn(bf, P.gAu, bf ? (const void *)P.gws : (const void *)P.gw, P.gu, Qg,
+                        bf ? 3 * Rg : Rg, N, s))
+        fail(SSMAP_EINVAL, "GEMM shape not supported");
+    HIPC(c, hipEventRecord(ev[1], s));
+    launch_gemm_update(z, P.gu, zn, P.gzs, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta, mask_dev(c), s);
+    HIPC(c, hipEventRecord(ev[2], s));
+    if (!launch_gemm_tn(bf, P.gAy, bf ? (const void *)P.gzs : (const void *)zn, yn, Rg,
+                        bf ? 3 * Qg : Qg, N, s))
+        fail(SSMAP_EINVAL, "GEMM shape not supported");
+    HIPC(c, hipEventRecord(ev[3], s));
+    launch_gemm_w(P.gah, yn, yo, P.gw, P.gws, P.gb, N, Rg, s);
+}
+
+void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
+    const int iters = P.iters;
+    launch_gemm_output(P.gz[iters & 1], dF, false, c->g.N, c->Q, P.pl.Qg, s);
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipEventRecord(c->ev[4], s));
+    HIPC(c, hipStreamSynchronize(s));
+    ssmap_stats &S = c->stats;
+    S.iters = iters;
+    S.device_bytes = (double)c->held;
+    double ms = 0.0;
+    for (int k = 0; k < iters; ++k) {
+        hipEvent_t *ev = gemm_events(c, k);
+        ms += elapsed_ms(ev[0], ev[1]) + elapsed_ms(ev[2], ev[3]);
+    }
+    S.gemm_ms = ms;
+    const bool bf = P.pl.mode == MODE_BF16X3;
+    S.gemm_flops = 2.0 * 2.0 * (double)P.pl.Qg * P.pl.Rg * (bf ? 3.0 : 1.0) * (double)c->g.N * iters;
+}
+
 // Device copies of a one-job launch plan: two IterArgs (even / odd
 // iterations) and the brick table for the default shape.
 FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
@@ -460,8 +666,14 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
 
 // One iteration of one job outside a shared launch (unfused kernels, or the
 // fused single-job launch with the aux passes around it).
+void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s);
+
 void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipStream_t s) {
     const Plan &pl = P.pl;
+    if (pl.gemm) {
+        step_gemm(c, P, k, s);
+        return;
+    }
     IterArgs a = args_for(P, k);
     const int iters = P.iters;
     if (P.aux && k == iters - 2) a.dout = P.auxA;                    // d^{K-1}
@@ -487,7 +699,13 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
     }
 }
 
+void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s);
+
 void finish(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
+    if (P.pl.gemm) {
+        finish_gemm(c, P, dF, s);
+        return;
+    }
     const int iters = P.iters;
     launch_output(P.pl.mode, P.z[iters & 1], dF, c->Q, c->g.N, false, s);
     HIPC(c, hipGetLastError());
@@ -560,6 +778,7 @@ void free_ctx(ssmap_ctx *c) {
     c->bufs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->gemm_ev) (void)hipEventDestroy(e);
     if (c->host_stats) (void)hipHostFree(c->host_stats);
     delete c;
 }
