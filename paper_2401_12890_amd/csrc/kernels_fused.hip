@@ -229,8 +229,12 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     static_assert(VB % 16 == 0 && VB / 16 <= NT, "V operand block must stage in one pass");
     static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
 
-    __shared__ V4 lds[4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
-    __shared__ uint4 ldsv[NT];           // V operands of the chunk (entries >= VB/16 unused)
+    // The float32 16 x 8 x 4 brick (one workgroup per CU either way) double-buffers
+    // its LDS: chunk c + 1 is stored while chunk c is read, one barrier per chunk.
+    constexpr bool DBL = MODE == MODE_FP32 && TY == 8 && TZ == 4;
+    constexpr int NBUF = DBL ? 2 : 1;
+    __shared__ V4 lds[NBUF][4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
+    __shared__ uint4 ldsv[NBUF][NT];           // V operands of the chunk (entries >= VB/16 unused)
 
     int tile = blockIdx.x;
     if ((ntiles & 7) == 0) {             // keep neighbouring bricks on one XCD (shared L2)
@@ -344,17 +348,35 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
 #pragma unroll
         for (int l = 0; l < NL; ++l) R[l] = IO::load(zr, voff[l]);
     };
+    auto stage = [&](int buf) {          // registers -> LDS (out-of-grid slots hold zeros)
+#pragma unroll
+        for (int l = 0; l < NL; ++l) lds[buf][loff[l]] = R[l];
+        ldsv[buf][tid] = Rv;
+    };
     fetch(0);
+    if constexpr (DBL) {
+        stage(0);
+        fetch(a.nchunk > 1 ? 1 : 0);
+        __syncthreads();
+    }
 
     for (int c = 0; c < a.nchunk; ++c) {
-        // ---- chunk c: registers -> LDS (out-of-grid slots hold zeros)
-#pragma unroll
-        for (int l = 0; l < NL; ++l) lds[loff[l]] = R[l];
-        ldsv[tid] = Rv;
-        __syncthreads();
-        // ---- loads of chunk c+1 stay in flight during the arithmetic of chunk c
-        //      (the last pass re-reads its own chunk: one loop path, exact wait counts)
-        fetch(c + 1 < a.nchunk ? c + 1 : c);
+        int cb = 0;                      // LDS buffer holding chunk c
+        if constexpr (DBL) {
+            // ---- chunk c + 1 into the other buffer (free since the last barrier), then
+            //      the loads of chunk c + 2 (past the end: the last chunk again, for one
+            //      loop path with exact wait counts)
+            cb = c & 1;
+            if (c + 1 < a.nchunk) stage(cb ^ 1);
+            fetch(c + 2 < a.nchunk ? c + 2 : a.nchunk - 1);
+        } else {
+            // ---- chunk c: registers -> LDS
+            stage(0);
+            __syncthreads();
+            // ---- loads of chunk c+1 stay in flight during the arithmetic of chunk c
+            //      (the last pass re-reads its own chunk: one loop path, exact wait counts)
+            fetch(c + 1 < a.nchunk ? c + 1 : c);
+        }
         // keep the loads ahead of the arithmetic (float64 has no registers to spare)
         if constexpr (MODE != MODE_FP64) __builtin_amdgcn_sched_barrier(0);
 
@@ -367,17 +389,17 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
         v8bf vuh, vul;
         v4s vyh[RB], vyl[RB];
         if constexpr (BF) {
-            const v4u *U8 = (const v4u *)ldsv;                      // [hi/lo][lane] x 8 bf16
+            const v4u *U8 = (const v4u *)ldsv[cb];                      // [hi/lo][lane] x 8 bf16
             vuh = __builtin_bit_cast(v8bf, U8[lane]);
             vul = __builtin_bit_cast(v8bf, U8[64 + lane]);
-            const v2u *Y4 = (const v2u *)((const char *)ldsv + 2048); // [rb][hi/lo][lane] x 4 bf16
+            const v2u *Y4 = (const v2u *)((const char *)ldsv[cb] + 2048); // [rb][hi/lo][lane] x 4 bf16
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 vyh[rb] = __builtin_bit_cast(v4s, Y4[(rb * 2 + 0) * 64 + lane]);
                 vyl[rb] = __builtin_bit_cast(v4s, Y4[(rb * 2 + 1) * 64 + lane]);
             }
         } else {
-            const T *VT = (const T *)ldsv;
+            const T *VT = (const T *)ldsv[cb];
 #pragma unroll
             for (int s = 0; s < KSU; ++s) vu[s] = VT[s * 64 + lane];
 #pragma unroll
@@ -395,7 +417,7 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
 
         // when the rows of a wave stack along z, this lane's z^k of every row
         // is read once and also serves as the z neighbours of the adjacent rows
-        const V4 *L = lds + i4 * B::NSP;
+        const V4 *L = lds[cb] + i4 * B::NSP;
         constexpr bool ZREG = TY == NW;      // row b + 1 of a wave is one step along z
         V4 zcs[ZREG ? BPW : 1];
         if constexpr (ZREG) {
