@@ -152,15 +152,20 @@ bool brick_has_inside(const Grid &g, const std::vector<uint8_t> &code, int64_t x
                       int64_t z0, int tx, int ty, int tz);
 
 // ---- exact-rank GEMM path (kernels_gemm.hip); voxel-major padded layouts
-// C[n][m] = sum_k A[m][k] B[n][k]; A: M x K, B: N x K, C: N x M (row-major),
-// float32 or bf16 operands (bf16 = true), float32 result. M a multiple of
-// 128, K of 16 (float32) or 64 (bf16); false when the shape is not supported.
-bool launch_gemm_tn(bool bf16, const void *A, const void *B, float *C, int M, int K, int64_t N,
-                    hipStream_t s);
-void launch_gemm_update(const float *z, const float *u, float *zn, uint16_t *zs, Grid g, int Qg,
-                        double tau, double lam2, double beta, const uint8_t *code, hipStream_t s);
-void launch_gemm_w(const float *ah, const float *ynew, const float *yold, float *w, uint16_t *ws,
-                   const float *bcoef, int64_t N, int Rg, hipStream_t s);
+// Products C[n][m] = sum_k A[m][k] B[n][k] (A: M x K, row-major, float32 or
+// bf16 operands, float32 accumulation), M a multiple of 128, K of 16 (float32)
+// or 3 x 64 (bf16); false when the shape is not supported. float32: B is N x K.
+// bf16 (split precision): B holds 2K/3 values per row (hi | lo) and column k
+// reads column k mod 2K/3, so the third K segment is the hi half again. C is not
+// stored: the u product (M = Qg) applies the z-update to it (z -> zn, and
+// zn's hi/lo bf16 split into zs when zs is not null), the y product (M = Rg) the
+// r-vector recursion with s = y + w (s in place; w^{k+1} into w, or its split
+// into ws when ws is not null).
+bool launch_gemm_u(bool bf16, const void *A, const void *B, int K, const float *z, float *zn,
+                   uint16_t *zs, Grid g, int Qg, double tau, double lam2, double beta,
+                   const uint8_t *code, hipStream_t s);
+bool launch_gemm_y(bool bf16, const void *A, const void *B, int K, int64_t N, int Rg, const float *ah,
+                   float *sv, float *w, uint16_t *ws, const float *bcoef, hipStream_t s);
 void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, int64_t N, int Rg,
                             hipStream_t s);
 void launch_gemm_output(const float *z, void *F, bool to_double, int64_t N, int Q, int Qg,

@@ -1,17 +1,25 @@
 // Exact-rank iteration (r above the fused kernels' 32): the two contractions
 // of the reduced form (u = V_r w, y = V_r^T z; Eq. DictVecSVD) are dense
-// matrix products over all voxels, run as MFMA-tiled GEMMs, with the stencil /
-// projected z-update (Eq. z2) and the r-vector recursion as separate
-// elementwise passes.
+// matrix products over all voxels, run as MFMA-tiled GEMMs whose epilogues
+// apply the elementwise steps to the tile in registers: the product u feeds
+// the stencil / projected z-update (Eq. z2) and the product y the r-vector
+// recursion, so neither u nor y is written to memory.
 //
-// Layouts (voxel-major, padded): z, u: N x Qg; w, y, a.h: N x Rg (Qg, Rg
-// multiples of 128, padding 0). bf16x3 keeps the hi/lo/hi bf16 split of each
-// voxel's w (3 Rg values) and z (3 Qg values) so that one bf16 product over a
-// tripled K gives hi*hi + lo*hi + hi*lo with float32 accumulation.
+// Layouts (voxel-major, padded): z: N x Qg; w, s, a.h: N x Rg (Qg, Rg
+// multiples of 128, padding 0). bf16x3 keeps the hi/lo bf16 split of each
+// voxel's w (2 Rg values) and z (2 Qg values); the product runs over a tripled
+// K whose third segment reads the hi half again (the constant operand is
+// hi | hi | lo), so one bf16 product gives hi*hi + hi*lo + lo*hi with float32
+// accumulation.
 //
-// GEMM: C[n][m] = sum_k A[m][k] B[n][k] (A: M x K row-major, B: N x K
-// row-major, C: N x M row-major), M and K multiples of the tiles, N ragged.
-// All operands have k contiguous, so a lane's MFMA fragment is one 16-byte read.
+// The r-vector recursion w^{k+1} = a.h - b.(2 y^{k+1} - y^k - w^k) is carried
+// with s^k = y^k + w^k in place of the pair (y^k, w^k): w^{k+1} = a.h -
+// b.(2 y^{k+1} - s^k), s^{k+1} = y^{k+1} + w^{k+1}, s^0 = w^0 (y^0 = 0).
+//
+// GEMM: C[n][m] = sum_k A[m][k] B[n][k] (A: M x K row-major; B: N rows of KB
+// values, column k of B read at k mod KB), M, K and KB multiples of the tiles,
+// N ragged. All operands have k contiguous, so a lane's MFMA fragment is one
+// 16-byte read.
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
@@ -39,13 +47,143 @@ template <> struct GK<uint16_t> {
     static constexpr int LD = KT + 8;          // rows 144 B apart
 };
 
+__device__ __forceinline__ uint16_t bf16_rne_bits(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// hi/lo bf16 split of a float row segment: dst[2 L] = (hi[0..L), lo[0..L))
+__device__ __forceinline__ void split2(float v, uint16_t *dst, int k, int L) {
+    const uint16_t h = bf16_rne_bits(v);
+    const uint16_t l = bf16_rne_bits(v - __uint_as_float((unsigned)h << 16));
+    dst[k] = h;
+    dst[L + k] = l;
+}
+
+// The same split of 4 consecutive values (k a multiple of 4): two 8-byte stores.
+__device__ __forceinline__ void split2x4(const v4f &v, uint16_t *dst, int k, int L) {
+    unsigned h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = bf16_rne_bits(v[i]);
+        l[i] = bf16_rne_bits(v[i] - __uint_as_float(h[i] << 16));
+    }
+    const uint2 hh{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+    const uint2 ll{l[0] | (l[1] << 16), l[2] | (l[3] << 16)};
+    *(uint2 *)(dst + k) = hh;
+    *(uint2 *)(dst + L + k) = ll;
+}
+
+// Epilogue of u = V_r w: z^{k+1} = max(0, z - tau (2 lambda (deg z - sum of
+// neighbours) - beta u)) for the voxel's 4 nodes q..q+3; outside a mask z stays 0.
+struct EpiZ {
+    const float *z;
+    float *zn;
+    uint16_t *zs;            // bf16 split of z^{k+1} (bf16x3) or null
+    Grid g;
+    int Qg;
+    float tau, lam2, beta;
+    const uint8_t *code;     // mask codes or null
+};
+
+// Per-voxel part of the z-update, shared by the voxel's nodes: the rows of z
+// at the voxel and its six face neighbours (a missing neighbour points at the
+// voxel's own row and is weighted 0, so every load is unconditional and valid).
+struct ColZ {
+    const float *c, *nb[6];
+    float wt[6];
+    float deg;
+    bool inside;
+    int64_t n;
+};
+
+__device__ __forceinline__ ColZ column(const EpiZ &e, int64_t n) {
+    const Grid &g = e.g;
+    const int64_t x = n % g.nx, t = n / g.nx, y = t % g.ny, zz = t / g.ny;
+    const int64_t step[3] = {(int64_t)e.Qg, g.nx * (int64_t)e.Qg, g.nx * g.ny * (int64_t)e.Qg};
+    const bool lo[3] = {x > 0, y > 0, zz > 0};
+    const bool hi[3] = {x + 1 < g.nx, y + 1 < g.ny, zz + 1 < g.nz};
+    ColZ c;
+    c.n = n;
+    c.c = e.z + n * (int64_t)e.Qg;
+    int deg = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c.nb[2 * d] = lo[d] ? c.c - step[d] : c.c;
+        c.nb[2 * d + 1] = hi[d] ? c.c + step[d] : c.c;
+        c.wt[2 * d] = lo[d] ? 1.0f : 0.0f;
+        c.wt[2 * d + 1] = hi[d] ? 1.0f : 0.0f;
+        deg += (int)lo[d] + (int)hi[d];
+    }
+    c.inside = true;
+    if (e.code) {
+        const unsigned cb = e.code[n];
+        c.inside = (cb & 0x80u) != 0;
+        deg = (int)(cb & 7u);
+    }
+    c.deg = (float)deg;
+    return c;
+}
+
+__device__ __forceinline__ void epilogue(const EpiZ &e, const ColZ &c, int q, const v4f &u) {
+    v4f nb[6];
+    const v4f zc = *(const v4f *)(c.c + q);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nb[k] = *(const v4f *)(c.nb[k] + q);
+    v4f nsum = v4f{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nsum += c.wt[k] * nb[k];
+    v4f r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float lap = c.deg * zc[i] - nsum[i];
+        const float v = zc[i] - e.tau * (e.lam2 * lap - e.beta * u[i]);
+        r[i] = (v > 0.0f && c.inside) ? v : 0.0f;
+    }
+    *(v4f *)(e.zn + c.n * (int64_t)e.Qg + q) = r;
+    if (e.zs) split2x4(r, e.zs + c.n * 2 * (int64_t)e.Qg, q, e.Qg);
+}
+
+// Epilogue of y = V_r^T z: w^{k+1} = a.h - b.(2 y^{k+1} - s^k), s^{k+1} =
+// y^{k+1} + w^{k+1} for the voxel's ranks i..i+3 (s updated in place); w^{k+1}
+// goes out as float32 (w) or as its bf16 split (ws).
+struct EpiW {
+    const float *ah;
+    float *s;
+    float *w;                // float32 operand of the next u product, or null
+    uint16_t *ws;            // its bf16 split (bf16x3), or null
+    const float *bcoef;
+    int Rg;
+};
+
+struct ColW {
+    int64_t o;               // first element of the voxel's row
+};
+
+__device__ __forceinline__ ColW column(const EpiW &e, int64_t n) { return ColW{n * (int64_t)e.Rg}; }
+
+__device__ __forceinline__ void epilogue(const EpiW &e, const ColW &c, int i, const v4f &y) {
+    const int64_t o = c.o + i;
+    const v4f a = *(const v4f *)(e.ah + o), sk = *(const v4f *)(e.s + o);
+    const v4f b = *(const v4f *)(e.bcoef + i);
+    v4f w, s1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        w[t] = a[t] - b[t] * (2.0f * y[t] - sk[t]);
+        s1[t] = y[t] + w[t];
+    }
+    *(v4f *)(e.s + o) = s1;
+    if (e.ws) split2x4(w, e.ws + 2 * c.o, i, e.Rg);
+    else *(v4f *)(e.w + o) = w;
+}
+
 // Workgroup tile (2 TM x 16) x (2 TN x 16): each wave owns TM x TN MFMA tiles of
 // 16 x 16. Larger wave tiles read fewer LDS bytes per product (the bf16 kernel
 // needs 8 x 4 to stay within the LDS bandwidth at the matrix-core rate).
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, typename E>
 __global__ void __launch_bounds__(GNT, 2)
-k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, float *__restrict__ C, int M, int K,
-          int64_t N) {
+k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, int M, int K, int KB, int64_t N, E epi) {
     using G = GK<T>;
     constexpr int KT = G::KT, LD = G::LD;
     constexpr int BM = 32 * TM, BN = 32 * TN;         // workgroup tile
@@ -59,12 +197,20 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, float *__restrict__ 
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * 16 * TM, wn = (wave >> 1) * 16 * TN;
-    const int m0 = blockIdx.y * BM;
-    const int64_t n0 = (int64_t)blockIdx.x * BN;
+    // M blocks fastest: the M / BM tiles that share one block of B rows run at
+    // the same time (after the first, their B reads hit the caches), and the
+    // grid sweeps the voxels in order, so the z rows one plane away that the
+    // stencil epilogue reads are recent enough to be cached. Ordering the
+    // tiles per XCD instead measured no better.
+    const unsigned t = blockIdx.x;
+    const int MB = M / BM;
+    const int m0 = (int)(t % MB) * BM;
+    const int64_t n0 = (int64_t)(t / MB) * BN;
 
     // staging: thread -> (row, vector) of the BM x KT and BN x KT tiles (rows of B beyond N load 0)
     v4u ra[NVA], rb[NVB];
     auto fetch = [&](int k0) {
+        const int kb = k0 % KB;           // a K tile never straddles a multiple of KB
 #pragma unroll
         for (int v = 0; v < NVA; ++v) {
             const int e = tid + GNT * v, row = e / VPR, vec = e % VPR;
@@ -74,7 +220,7 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, float *__restrict__ 
         for (int v = 0; v < NVB; ++v) {
             const int e = tid + GNT * v, row = e / VPR, vec = e % VPR;
             const int64_t n = n0 + row;
-            rb[v] = n < N ? *(const v4u *)(B + (size_t)n * K + k0 + vec * EPV) : v4u{0, 0, 0, 0};
+            rb[v] = n < N ? *(const v4u *)(B + (size_t)n * KB + kb + vec * EPV) : v4u{0, 0, 0, 0};
         }
     };
     auto put = [&](T *dst, const v4u &v) {
@@ -145,89 +291,15 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, float *__restrict__ 
             }
         }
     }
-    // D layout: lane holds rows (m) 4 (l / 16) + i of column (n) l % 16: 16 contiguous bytes of C
+    // D layout: lane holds rows (m) 4 (l / 16) + i of column (n) l % 16
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int64_t n = n0 + wn + 16 * j + r16;
         if (n >= N) continue;
+        const auto col = column(epi, n);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-            *(v4f *)(C + (size_t)n * M + m0 + wm + 16 * i + 4 * g4) = acc[i][j];
+        for (int i = 0; i < TM; ++i) epilogue(epi, col, m0 + wm + 16 * i + 4 * g4, acc[i][j]);
     }
-}
-
-__device__ __forceinline__ uint16_t bf16_rne_bits(float x) {
-    unsigned u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-// hi/lo/hi bf16 split of a float row segment: dst[3 L] = (hi[0..L), lo[0..L), hi[0..L))
-__device__ __forceinline__ void split3(float v, uint16_t *dst, int k, int L) {
-    const uint16_t h = bf16_rne_bits(v);
-    const uint16_t l = bf16_rne_bits(v - __uint_as_float((unsigned)h << 16));
-    dst[k] = h;
-    dst[L + k] = l;
-    dst[2 * L + k] = h;
-}
-
-// z^{k+1} = max(0, z - tau (2 lambda (deg z - sum of neighbours) - beta u)) per (voxel, node);
-// outside a mask z stays 0. One thread per (voxel, 4 nodes).
-__global__ void __launch_bounds__(256)
-k_gemm_update(const float *__restrict__ z, const float *__restrict__ u, float *__restrict__ zn,
-              uint16_t *__restrict__ zs, Grid g, int Qg, float tau, float lam2, float beta,
-              const uint8_t *__restrict__ code) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int q4 = Qg / 4;
-    if (idx >= g.N * q4) return;
-    const int64_t n = idx / q4;
-    const int q = (int)(idx % q4) * 4;
-    const int64_t x = n % g.nx, y = (n / g.nx) % g.ny, zz = n / (g.nx * g.ny);
-    const size_t o = (size_t)n * Qg + q;
-    const v4f zc = *(const v4f *)(z + o);
-    v4f nsum = v4f{0, 0, 0, 0};
-    int deg = 0;
-    const int64_t sy = g.nx, sz = g.nx * g.ny;
-    if (x > 0) { nsum += *(const v4f *)(z + o - Qg); ++deg; }
-    if (x + 1 < g.nx) { nsum += *(const v4f *)(z + o + Qg); ++deg; }
-    if (y > 0) { nsum += *(const v4f *)(z + o - sy * Qg); ++deg; }
-    if (y + 1 < g.ny) { nsum += *(const v4f *)(z + o + sy * Qg); ++deg; }
-    if (zz > 0) { nsum += *(const v4f *)(z + o - sz * Qg); ++deg; }
-    if (zz + 1 < g.nz) { nsum += *(const v4f *)(z + o + sz * Qg); ++deg; }
-    bool inside = true;
-    if (code) {
-        const unsigned cb = code[n];
-        inside = (cb & 0x80u) != 0;
-        deg = (int)(cb & 7u);
-    }
-    const v4f uu = *(const v4f *)(u + o);
-    v4f r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float lap = (float)deg * zc[i] - nsum[i];
-        const float v = zc[i] - tau * (lam2 * lap - beta * uu[i]);
-        r[i] = (v > 0.0f && inside) ? v : 0.0f;
-    }
-    *(v4f *)(zn + o) = r;
-    if (zs) {
-        uint16_t *d = zs + (size_t)n * 3 * Qg;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) split3(r[i], d, q + i, Qg);
-    }
-}
-
-// w^{k+1} = a.h - b.(2 y^{k+1} - y^k - w^k) per (voxel, rank), and its bf16 split.
-__global__ void __launch_bounds__(256)
-k_gemm_w(const float *__restrict__ ah, const float *__restrict__ ynew, const float *__restrict__ yold,
-         float *__restrict__ w, uint16_t *__restrict__ ws, const float *__restrict__ bcoef,
-         int64_t N, int Rg) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= N * Rg) return;
-    const int64_t n = idx / Rg;
-    const int i = (int)(idx % Rg);
-    const float v = ah[idx] - bcoef[i] * (2.0f * ynew[idx] - yold[idx] - w[idx]);
-    w[idx] = v;
-    if (ws) split3(v, ws + (size_t)n * 3 * Rg, i, Rg);
 }
 
 // [i][n] (rank-major, RP rows) -> [n][i] (voxel-major, Rg columns), zero padded;
@@ -241,7 +313,7 @@ k_gemm_from_ranks(const float *__restrict__ src, int RP, float *__restrict__ dst
     const int i = (int)(idx % Rg);
     const float v = i < RP ? src[(size_t)i * N + n] : 0.0f;
     dst[idx] = v;
-    if (ds) split3(v, ds + (size_t)n * 3 * Rg, i, Rg);
+    if (ds) split2(v, ds + (size_t)n * 2 * Rg, i, Rg);
 }
 
 // z (N x Qg) -> F (N x Q), float32 or float64 output.
@@ -259,34 +331,44 @@ inline unsigned nblocks(int64_t work, int per) { return (unsigned)((work + per -
 
 }  // namespace
 
-bool launch_gemm_tn(bool bf16, const void *A, const void *B, float *C, int M, int K, int64_t N,
-                    hipStream_t s) {
-    if (M % 128 || K % (bf16 ? GK<uint16_t>::KT : GK<float>::KT) || N <= 0) return false;
+namespace {
+
+// M x K by N x K product with epilogue e; false for shapes the tiles do not cover.
+template <typename E>
+bool gemm_tn(bool bf16, const void *A, const void *B, int M, int K, int KB, int64_t N, const E &e,
+             hipStream_t s) {
+    const int KT = bf16 ? GK<uint16_t>::KT : GK<float>::KT;
+    if (M % 128 || K % KT || KB % KT || KB <= 0 || KB > K || N <= 0) return false;
+    if ((N + 127) / 128 * (M / 128) > 0x7fffffff) return false;   // one-dimensional grid
     const dim3 block(GNT);
+    const unsigned nb = nblocks(N, 128);
     if (bf16 && M % 256 == 0) {
         // 256 x 128 workgroup tiles, 128 x 64 per wave
-        hipLaunchKernelGGL((k_gemm_tn<uint16_t, 8, 4>), dim3(nblocks(N, 128), (unsigned)(M / 256)), block,
-                           0, s, (const uint16_t *)A, (const uint16_t *)B, C, M, K, N);
+        hipLaunchKernelGGL((k_gemm_tn<uint16_t, 8, 4, E>), dim3(nb * (unsigned)(M / 256)), block, 0, s,
+                           (const uint16_t *)A, (const uint16_t *)B, M, K, KB, N, e);
     } else if (bf16) {
-        hipLaunchKernelGGL((k_gemm_tn<uint16_t, 4, 4>), dim3(nblocks(N, 128), (unsigned)(M / 128)), block,
-                           0, s, (const uint16_t *)A, (const uint16_t *)B, C, M, K, N);
+        hipLaunchKernelGGL((k_gemm_tn<uint16_t, 4, 4, E>), dim3(nb * (unsigned)(M / 128)), block, 0, s,
+                           (const uint16_t *)A, (const uint16_t *)B, M, K, KB, N, e);
     } else {
-        hipLaunchKernelGGL((k_gemm_tn<float, 4, 4>), dim3(nblocks(N, 128), (unsigned)(M / 128)), block, 0,
-                           s, (const float *)A, (const float *)B, C, M, K, N);
+        hipLaunchKernelGGL((k_gemm_tn<float, 4, 4, E>), dim3(nb * (unsigned)(M / 128)), block, 0, s,
+                           (const float *)A, (const float *)B, M, K, KB, N, e);
     }
     return true;
 }
 
-void launch_gemm_update(const float *z, const float *u, float *zn, uint16_t *zs, Grid g, int Qg,
-                        double tau, double lam2, double beta, const uint8_t *code, hipStream_t s) {
-    hipLaunchKernelGGL(k_gemm_update, dim3(nblocks(g.N * (Qg / 4), 256)), dim3(256), 0, s, z, u, zn, zs,
-                       g, Qg, (float)tau, (float)lam2, (float)beta, code);
+}  // namespace
+
+bool launch_gemm_u(bool bf16, const void *A, const void *B, int K, const float *z, float *zn,
+                   uint16_t *zs, Grid g, int Qg, double tau, double lam2, double beta,
+                   const uint8_t *code, hipStream_t s) {
+    const EpiZ e{z, zn, zs, g, Qg, (float)tau, (float)lam2, (float)beta, code};
+    return gemm_tn(bf16, A, B, Qg, K, bf16 ? K / 3 * 2 : K, g.N, e, s);
 }
 
-void launch_gemm_w(const float *ah, const float *ynew, const float *yold, float *w, uint16_t *ws,
-                   const float *bcoef, int64_t N, int Rg, hipStream_t s) {
-    hipLaunchKernelGGL(k_gemm_w, dim3(nblocks(N * Rg, 256)), dim3(256), 0, s, ah, ynew, yold, w, ws,
-                       bcoef, N, Rg);
+bool launch_gemm_y(bool bf16, const void *A, const void *B, int K, int64_t N, int Rg, const float *ah,
+                   float *sv, float *w, uint16_t *ws, const float *bcoef, hipStream_t s) {
+    const EpiW e{ah, sv, w, ws, bcoef, Rg};
+    return gemm_tn(bf16, A, B, Rg, K, bf16 ? K / 3 * 2 : K, N, e, s);
 }
 
 void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, int64_t N, int Rg,

@@ -126,7 +126,7 @@ struct ssmap_ctx {
     int64_t inside = 0;
     hipEvent_t ev[6] = {};
     double *host_stats = nullptr;         // pinned ST_COUNT doubles
-    std::vector<hipEvent_t> gemm_ev;      // GEMM path: 4 timing events per iteration
+    std::vector<hipEvent_t> gemm_ev;      // GEMM path: 3 timing events per iteration
 };
 
 namespace {
@@ -173,15 +173,15 @@ void *ensure(ssmap_ctx *c, const std::string &name, size_t bytes) {
     return p;
 }
 
-// The four timing events of GEMM-path iteration k (created on first use).
+// The three timing events of GEMM-path iteration k (created on first use).
 hipEvent_t *gemm_events(ssmap_ctx *c, int k) {
-    const size_t need = 4 * (size_t)(k + 1);
+    const size_t need = 3 * (size_t)(k + 1);
     while (c->gemm_ev.size() < need) {
         hipEvent_t e = nullptr;
         HIPC(c, hipEventCreate(&e));
         c->gemm_ev.push_back(e);
     }
-    return &c->gemm_ev[4 * (size_t)k];
+    return &c->gemm_ev[3 * (size_t)k];
 }
 
 // Device copy of the mask codes (NULL without a mask).
@@ -281,9 +281,9 @@ struct Prepared {
     int iters = 0;
     double stop_tol = 0.0;
     int check_every = 0;
-    // GEMM path (voxel-major, padded): z, y ping-pong; u; w, a.h; bf16 splits; constants
-    float *gz[2] = {nullptr, nullptr}, *gy[2] = {nullptr, nullptr}, *gu = nullptr, *gw = nullptr,
-          *gah = nullptr, *gb = nullptr;
+    // GEMM path (voxel-major, padded): z ping-pong; s = y + w; w (float32 operand);
+    // a.h; bf16 splits; constants
+    float *gz[2] = {nullptr, nullptr}, *gs = nullptr, *gw = nullptr, *gah = nullptr, *gb = nullptr;
     uint16_t *gzs = nullptr, *gws = nullptr;
     const void *gAu = nullptr, *gAy = nullptr;
 };
@@ -453,27 +453,29 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     const bool bf = pl.mode == MODE_BF16X3;
     const int Ku = bf ? 3 * Rg : Rg, Ky = bf ? 3 * Qg : Qg;
     const size_t esA = bf ? 2 : 4;
-    const size_t zb = (size_t)N * Qg * 4, rb = (size_t)N * Rg * 4;
+    const size_t zb = (size_t)N * Qg * 4, rb = (size_t)N * Rg * 4, tb = (size_t)N * RP * 4;
     std::vector<std::pair<std::string, size_t>> need = {
-        {"gz0", zb}, {"gz1", zb}, {"gu", zb}, {"gy0", rb}, {"gy1", rb}, {"gw", rb}, {"gah", rb},
+        {"gz0", zb}, {"gz1", zb}, {"gs", rb}, {"gah", rb}, {"gt0", tb}, {"gt1", tb},
         {"gb", (size_t)Rg * 4}, {"gAu", (size_t)Qg * Ku * esA}, {"gAy", (size_t)Rg * Ky * esA},
         {"Ur", (size_t)Pm * r * 8}, {"sig", (size_t)RP * 8}, {"acoef", (size_t)RP * 8}, {"bad", 256}};
     if (bf) {
-        need.push_back({"gzs", (size_t)N * 3 * Qg * 2});
-        need.push_back({"gws", (size_t)N * 3 * Rg * 2});
+        need.push_back({"gzs", (size_t)N * 2 * Qg * 2});
+        need.push_back({"gws", (size_t)N * 2 * Rg * 2});
+    } else {
+        need.push_back({"gw", rb});
     }
     plan_check(c, need);
-    for (int k = 0; k < 2; ++k) {
-        P.gz[k] = (float *)ensure(c, k ? "gz1" : "gz0", zb);
-        P.gy[k] = (float *)ensure(c, k ? "gy1" : "gy0", rb);
-    }
-    P.gu = (float *)ensure(c, "gu", zb);
-    P.gw = (float *)ensure(c, "gw", rb);
+    for (int k = 0; k < 2; ++k) P.gz[k] = (float *)ensure(c, k ? "gz1" : "gz0", zb);
+    P.gs = (float *)ensure(c, "gs", rb);
     P.gah = (float *)ensure(c, "gah", rb);
+    // rank-major projection temporaries: a.h (= w^0) and y^0
+    float *gt0 = (float *)ensure(c, "gt0", tb), *gt1 = (float *)ensure(c, "gt1", tb);
     P.gb = (float *)ensure(c, "gb", (size_t)Rg * 4);
     if (bf) {
-        P.gzs = (uint16_t *)ensure(c, "gzs", (size_t)N * 3 * Qg * 2);
-        P.gws = (uint16_t *)ensure(c, "gws", (size_t)N * 3 * Rg * 2);
+        P.gzs = (uint16_t *)ensure(c, "gzs", (size_t)N * 2 * Qg * 2);
+        P.gws = (uint16_t *)ensure(c, "gws", (size_t)N * 2 * Rg * 2);
+    } else {
+        P.gw = (float *)ensure(c, "gw", rb);
     }
     void *Au = ensure(c, "gAu", (size_t)Qg * Ku * esA), *Ay = ensure(c, "gAy", (size_t)Rg * Ky * esA);
     double *Ur = (double *)ensure(c, "Ur", (size_t)Pm * r * 8);
@@ -550,19 +552,17 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     S.sigma_max = c->s.empty() ? 0.0 : c->s[0];
     c->aux_valid = false;
 
-    // a1: projection into rank-major temporaries (gy0: a.h and w^0, gy1: y^0), then the
-    // voxel-major a.h, w^0 (and its split); z^0 = 0, y^0 = 0
+    // a1: projection into rank-major temporaries (a.h = w^0, y^0 = 0), then the
+    // voxel-major a.h, s^0 = y^0 + w^0 = w^0 and w^0 (float32 or its split); z^0 = 0
     HIPC(c, hipEventRecord(c->ev[0], s));
     int *bad = (int *)ensure(c, "bad", 256);
     launch_zero(bad, 1, 4, s);
-    launch_project(pl.mode, P.dM, Pm, Ur, P.sig, acoef, r, RP, N, nullptr, nullptr, P.gy[0], P.gy[0],
-                   P.gy[1], bad, mask_dev(c), s);
-    launch_gemm_from_ranks(P.gy[0], RP, P.gah, nullptr, N, Rg, s);
-    launch_gemm_from_ranks(P.gy[0], RP, P.gw, P.gws, N, Rg, s);
-    for (int k = 0; k < 2; ++k) {
-        launch_zero(P.gz[k], (size_t)N * Qg, 4, s);
-        launch_zero(P.gy[k], (size_t)N * Rg, 4, s);
-    }
+    launch_project(pl.mode, P.dM, Pm, Ur, P.sig, acoef, r, RP, N, nullptr, nullptr, gt0, gt0, gt1,
+                   bad, mask_dev(c), s);
+    launch_gemm_from_ranks(gt0, RP, P.gah, nullptr, N, Rg, s);
+    launch_gemm_from_ranks(gt0, RP, P.gs, P.gws, N, Rg, s);
+    if (!bf) launch_gemm_from_ranks(gt0, RP, P.gw, nullptr, N, Rg, s);
+    for (int k = 0; k < 2; ++k) launch_zero(P.gz[k], (size_t)N * Qg, 4, s);
     HIPC(c, hipGetLastError());
     HIPC(c, hipEventRecord(c->ev[1], s));
     int badh = 0;
@@ -572,8 +572,9 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     return P;
 }
 
-// One GEMM-path iteration k: u = V_r w^k; z-update; y^{k+1} = V_r^T z^{k+1}; w^{k+1}.
-// The two products are bracketed by timing events (stats.gemm_ms).
+// One GEMM-path iteration k: u = V_r w^k with the z-update as its epilogue, then
+// y^{k+1} = V_r^T z^{k+1} with the r-vector recursion as its epilogue. Both
+// launches are bracketed by timing events (stats.gemm_ms).
 void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     const Plan &pl = P.pl;
     const bool bf = pl.mode == MODE_BF16X3;
@@ -581,21 +582,16 @@ void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     const int Qg = pl.Qg, Rg = pl.Rg;
     const float *z = P.gz[k & 1];
     float *zn = P.gz[(k + 1) & 1];
-    const float *yo = P.gy[k & 1];
-    float *yn = P.gy[(k + 1) & 1];
     hipEvent_t *ev = gemm_events(c, k);
     HIPC(c, hipEventRecord(ev[0], s));
-    if (!launch_gemm_tn(bf, P.gAu, bf ? (const void *)P.gws : (const void *)P.gw, P.gu, Qg,
-                        bf ? 3 * Rg : Rg, N, s))
+    if (!launch_gemm_u(bf, P.gAu, bf ? (const void *)P.gws : (const void *)P.gw, bf ? 3 * Rg : Rg, z, zn,
+                       P.gzs, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta, mask_dev(c), s))
         fail(SSMAP_EINVAL, "GEMM shape not supported");
     HIPC(c, hipEventRecord(ev[1], s));
-    launch_gemm_update(z, P.gu, zn, P.gzs, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta, mask_dev(c), s);
-    HIPC(c, hipEventRecord(ev[2], s));
-    if (!launch_gemm_tn(bf, P.gAy, bf ? (const void *)P.gzs : (const void *)zn, yn, Rg,
-                        bf ? 3 * Qg : Qg, N, s))
+    if (!launch_gemm_y(bf, P.gAy, bf ? (const void *)P.gzs : (const void *)zn, bf ? 3 * Qg : Qg, N, Rg,
+                       P.gah, P.gs, P.gw, P.gws, P.gb, s))
         fail(SSMAP_EINVAL, "GEMM shape not supported");
-    HIPC(c, hipEventRecord(ev[3], s));
-    launch_gemm_w(P.gah, yn, yo, P.gw, P.gws, P.gb, N, Rg, s);
+    HIPC(c, hipEventRecord(ev[2], s));
 }
 
 void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
@@ -610,7 +606,7 @@ void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
     double ms = 0.0;
     for (int k = 0; k < iters; ++k) {
         hipEvent_t *ev = gemm_events(c, k);
-        ms += elapsed_ms(ev[0], ev[1]) + elapsed_ms(ev[2], ev[3]);
+        ms += elapsed_ms(ev[0], ev[2]);
     }
     S.gemm_ms = ms;
     const bool bf = P.pl.mode == MODE_BF16X3;
