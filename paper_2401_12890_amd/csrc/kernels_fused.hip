@@ -86,8 +86,10 @@ constexpr int TX = 16;
 template <int TY, int TZ> struct Brick {
     static constexpr int SX = TX + 2, SY = TY + 2, SZ = TZ + 2;
     static constexpr int NS = SX * SY * SZ;
-    // pad the per-quad plane so the four quads of one slot fall on different banks
-    static constexpr int NSP = ((NS + 11) / 16) * 16 + 4;
+    // per-quad plane padded to 2 mod 16 entries: the staging stores (the four
+    // quads of two adjacent slots per eight lanes) fall on distinct banks; this
+    // halved the measured LDS bank-conflict cycles against 4 mod 16
+    static constexpr int NSP = ((NS + 13) / 16) * 16 + 2;
     static constexpr int C = TX * TY * TZ;
     static constexpr int XF = 2 * TY * TZ;
     static constexpr int YF = 2 * TX * TZ;
@@ -350,7 +352,8 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     };
     auto stage = [&](int buf) {          // registers -> LDS (out-of-grid slots hold zeros)
 #pragma unroll
-        for (int l = 0; l < NL; ++l) lds[buf][loff[l]] = R[l];
+        for (int l = 0; l < NL; ++l)     // unused staging lanes (whole waves) store nothing
+            if (NT * (l + 1) <= 4 * B::NSLOT || tid + NT * l < 4 * B::NSLOT) lds[buf][loff[l]] = R[l];
         ldsv[buf][tid] = Rv;
     };
     fetch(0);
