@@ -74,7 +74,7 @@ typedef enum {
     SSMAP_KERNEL_GEMM = 3   /* any rank, float32 / bf16x3: the two contractions as
                                MFMA-tiled GEMMs over all voxels (compute bound at
                                high rank), the stencil / z-update and r-vector
-                               recursion as elementwise passes; check_every = 0,
+                               recursion as the GEMMs' epilogues; check_every = 0,
                                no SSMAP_KEEP_AUX                                   */
 } ssmap_kernel;
 
