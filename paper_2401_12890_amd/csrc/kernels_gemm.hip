@@ -44,7 +44,7 @@ template <> struct GK<float> {
 };
 template <> struct GK<uint16_t> {
     static constexpr int KT = 64;
-    static constexpr int LD = KT + 8;          // rows 144 B apart
+    static constexpr int LD = KT;              // rows 128 B, 16-byte units swizzled (see sw)
 };
 
 __device__ __forceinline__ uint16_t bf16_rne_bits(float x) {
@@ -223,6 +223,11 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, int M, int K, int KB
             rb[v] = n < N ? *(const v4u *)(B + (size_t)n * KB + kb + vec * EPV) : v4u{0, 0, 0, 0};
         }
     };
+    // 16-byte unit u of LDS row `row`: bf16 rows are unpadded and the unit index
+    // is XORed with row % 8, so the fragment reads (16 rows x 4 units) and the
+    // staging stores (8 units of consecutive rows) both run at the full LDS rate
+    // (measured; padded 144-byte rows cost a third more LDS cycles per read)
+    auto sw = [](int row, int u) { return sizeof(T) == 2 ? u ^ (row & 7) : u; };
     auto put = [&](T *dst, const v4u &v) {
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
@@ -235,12 +240,12 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, int M, int K, int KB
 #pragma unroll
         for (int v = 0; v < NVA; ++v) {
             const int e = tid + GNT * v;
-            put(As + (e / VPR) * LD + (e % VPR) * EPV, ra[v]);
+            put(As + (e / VPR) * LD + sw(e / VPR, e % VPR) * EPV, ra[v]);
         }
 #pragma unroll
         for (int v = 0; v < NVB; ++v) {
             const int e = tid + GNT * v;
-            put(Bs + (e / VPR) * LD + (e % VPR) * EPV, rb[v]);
+            put(Bs + (e / VPR) * LD + sw(e / VPR, e % VPR) * EPV, rb[v]);
         }
     };
 
@@ -279,10 +284,10 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, int M, int K, int KB
                 v8bf a[TM], b[TN];
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    a[i] = *(const v8bf *)(As + (wm + 16 * i + r16) * LD + ks + 8 * g4);
+                    a[i] = *(const v8bf *)(As + (wm + 16 * i + r16) * LD + sw(r16, ks / 8 + g4) * 8);
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    b[j] = *(const v8bf *)(Bs + (wn + 16 * j + r16) * LD + ks + 8 * g4);
+                    b[j] = *(const v8bf *)(Bs + (wn + 16 * j + r16) * LD + sw(r16, ks / 8 + g4) * 8);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
