@@ -390,10 +390,36 @@ k_output(const T *__restrict__ z, O *__restrict__ F, int Q, int64_t N) {
     F[idx] = (O)z[chunk_index(q, n, N)];
 }
 
+// Four consecutive nodes per lane (Q % 4 == 0): a wave moves 4 voxels x 64 nodes,
+// reading 256 contiguous bytes per chunk and writing 256 contiguous bytes per
+// voxel row; block = 16 voxels, grid.y over groups of 64 nodes.
+template <typename T, typename O>
+__global__ void __launch_bounds__(256)
+k_output4(const T *__restrict__ z, O *__restrict__ F, int Q, int64_t N) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t n = ((int64_t)blockIdx.x * 4 + wave) * 4 + (lane >> 4);
+    const int q = (int)blockIdx.y * 64 + 4 * (lane & 15);
+    if (n >= N || q >= Q) return;
+    const T *src = z + chunk_index(q, n, N);     // q % 4 == 0: four nodes of one chunk
+    O *dst = F + n * (int64_t)Q + q;
+    if constexpr (sizeof(T) == 4 && sizeof(O) == 4) {
+        *(float4 *)dst = *(const float4 *)src;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = (O)src[i];
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_zero(T *p, size_t count) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = (T)0;
+}
+
+// 16 bytes per lane (the bulk of a 16-byte aligned array)
+__global__ void __launch_bounds__(256) k_zero16(uint4 *p, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = uint4{0, 0, 0, 0};
 }
 
 __global__ void __launch_bounds__(256)
@@ -486,6 +512,20 @@ void launch_monitor(int mode, const void *z, const void *zprev, const double *V6
 
 void launch_output(int mode, const void *z, void *F, int Q, int64_t N, bool to_double,
                    hipStream_t s) {
+    const bool aligned = ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(F)) & 15) == 0;
+    if (Q % 4 == 0 && N > 0 && aligned && (N + 15) / 16 <= 0x7fffffff) {
+        const dim3 grid4((unsigned)((N + 15) / 16), (unsigned)((Q + 63) / 64)), block4(256);
+        if (mode == MODE_FP64)
+            hipLaunchKernelGGL((k_output4<double, double>), grid4, block4, 0, s, (const double *)z,
+                               (double *)F, Q, N);
+        else if (to_double)
+            hipLaunchKernelGGL((k_output4<float, double>), grid4, block4, 0, s, (const float *)z,
+                               (double *)F, Q, N);
+        else
+            hipLaunchKernelGGL((k_output4<float, float>), grid4, block4, 0, s, (const float *)z,
+                               (float *)F, Q, N);
+        return;
+    }
     const dim3 grid(blocks_for(N * Q, 256)), block(256);
     if (mode == MODE_FP64)
         hipLaunchKernelGGL((k_output<double, double>), grid, block, 0, s, (const double *)z,
@@ -500,6 +540,13 @@ void launch_output(int mode, const void *z, void *F, int Q, int64_t N, bool to_d
 
 void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s) {
     if (count == 0) return;
+    const size_t bytes = count * (size_t)elem_bytes;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && bytes >= 16 && bytes % 16 == 0) {
+        const size_t n16 = bytes / 16;
+        hipLaunchKernelGGL(k_zero16, dim3(blocks_for((int64_t)n16, 256)), dim3(256), 0, s, (uint4 *)p,
+                           n16);
+        return;
+    }
     const dim3 grid(blocks_for((int64_t)count, 256)), block(256);
     if (elem_bytes == 8) hipLaunchKernelGGL(k_zero<double>, grid, block, 0, s, (double *)p, count);
     else if (elem_bytes == 4) hipLaunchKernelGGL(k_zero<float>, grid, block, 0, s, (float *)p, count);
