@@ -126,23 +126,34 @@ __device__ __forceinline__ ColZ column(const EpiZ &e, int64_t n) {
     return c;
 }
 
-__device__ __forceinline__ void epilogue(const EpiZ &e, const ColZ &c, int q, const v4f &u) {
-    v4f nb[6];
-    const v4f zc = *(const v4f *)(c.c + q);
+// G steps of one voxel (nodes q[g] .. q[g] + 3): every load is issued before any
+// result is computed, so a lane has 7 G loads in flight instead of 7 (the
+// epilogue is bound by their latency).
+template <int G>
+__device__ __forceinline__ void epilogue_batch(const EpiZ &e, const ColZ &c, const int (&q)[G],
+                                               const v4f (&u)[G]) {
+    v4f zc[G], nb[G][6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) nb[k] = *(const v4f *)(c.nb[k] + q);
-    v4f nsum = v4f{0, 0, 0, 0};
+    for (int g = 0; g < G; ++g) {
+        zc[g] = *(const v4f *)(c.c + q[g]);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) nsum += c.wt[k] * nb[k];
-    v4f r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float lap = c.deg * zc[i] - nsum[i];
-        const float v = zc[i] - e.tau * (e.lam2 * lap - e.beta * u[i]);
-        r[i] = (v > 0.0f && c.inside) ? v : 0.0f;
+        for (int k = 0; k < 6; ++k) nb[g][k] = *(const v4f *)(c.nb[k] + q[g]);
     }
-    *(v4f *)(e.zn + c.n * (int64_t)e.Qg + q) = r;
-    if (e.zs) split2x4(r, e.zs + c.n * 2 * (int64_t)e.Qg, q, e.Qg);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        v4f nsum = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) nsum += c.wt[k] * nb[g][k];
+        v4f r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float lap = c.deg * zc[g][i] - nsum[i];
+            const float v = zc[g][i] - e.tau * (e.lam2 * lap - e.beta * u[g][i]);
+            r[i] = (v > 0.0f && c.inside) ? v : 0.0f;
+        }
+        *(v4f *)(e.zn + c.n * (int64_t)e.Qg + q[g]) = r;
+        if (e.zs) split2x4(r, e.zs + c.n * 2 * (int64_t)e.Qg, q[g], e.Qg);
+    }
 }
 
 // Epilogue of y = V_r^T z: w^{k+1} = a.h - b.(2 y^{k+1} - s^k), s^{k+1} =
@@ -163,19 +174,61 @@ struct ColW {
 
 __device__ __forceinline__ ColW column(const EpiW &e, int64_t n) { return ColW{n * (int64_t)e.Rg}; }
 
-__device__ __forceinline__ void epilogue(const EpiW &e, const ColW &c, int i, const v4f &y) {
-    const int64_t o = c.o + i;
-    const v4f a = *(const v4f *)(e.ah + o), sk = *(const v4f *)(e.s + o);
-    const v4f b = *(const v4f *)(e.bcoef + i);
-    v4f w, s1;
+template <int G>
+__device__ __forceinline__ void epilogue_batch(const EpiW &e, const ColW &c, const int (&q)[G],
+                                               const v4f (&y)[G]) {
+    v4f a[G], sk[G], b[G];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        w[t] = a[t] - b[t] * (2.0f * y[t] - sk[t]);
-        s1[t] = y[t] + w[t];
+    for (int g = 0; g < G; ++g) {
+        a[g] = *(const v4f *)(e.ah + c.o + q[g]);
+        sk[g] = *(const v4f *)(e.s + c.o + q[g]);
+        b[g] = *(const v4f *)(e.bcoef + q[g]);
     }
-    *(v4f *)(e.s + o) = s1;
-    if (e.ws) split2x4(w, e.ws + 2 * c.o, i, e.Rg);
-    else *(v4f *)(e.w + o) = w;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        v4f w, s1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            w[t] = a[g][t] - b[g][t] * (2.0f * y[g][t] - sk[g][t]);
+            s1[t] = y[g][t] + w[t];
+        }
+        *(v4f *)(e.s + c.o + q[g]) = s1;
+        if (e.ws) split2x4(w, e.ws + 2 * c.o, q[g], e.Rg);
+        else *(v4f *)(e.w + c.o + q[g]) = w;
+    }
+}
+
+// Steps per epilogue batch: GZ for the stencil (7 loaded vectors a step; the
+// caller picks it against its register budget), 8 for the r-vectors.
+template <typename E, int GZ> struct EpiBatch;
+template <int GZ> struct EpiBatch<EpiZ, GZ> { static constexpr int value = GZ; };
+template <int GZ> struct EpiBatch<EpiW, GZ> { static constexpr int value = 8; };
+
+// The epilogue of a wave's TM x TN accumulator tiles: lane holds rows (m)
+// 4 (l / 16) + i of column (n) l % 16 of each 16 x 16 tile.
+template <int TM, int TN, int GZ, typename E>
+__device__ __forceinline__ void run_epilogue(const E &epi, const v4f (&acc)[TM][TN], int m0, int64_t n0,
+                                             int64_t N, int lane) {
+    constexpr int G = EpiBatch<E, GZ>::value < TM ? EpiBatch<E, GZ>::value : TM;
+    static_assert(TM % G == 0, "epilogue batches must tile the wave's rows");
+    const int r16 = lane & 15, g4 = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + 16 * j + r16;
+        if (n >= N) continue;
+        const auto col = column(epi, n);
+#pragma unroll
+        for (int i0 = 0; i0 < TM; i0 += G) {
+            int q[G];
+            v4f v[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                q[g] = m0 + 16 * (i0 + g) + 4 * g4;
+                v[g] = acc[i0 + g][j];
+            }
+            epilogue_batch<G>(epi, col, q, v);
+        }
+    }
 }
 
 // Workgroup tile (2 TM x 16) x (2 TN x 16): each wave owns TM x TN MFMA tiles of
@@ -296,15 +349,8 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, int M, int K, int KB
             }
         }
     }
-    // D layout: lane holds rows (m) 4 (l / 16) + i of column (n) l % 16
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int64_t n = n0 + wn + 16 * j + r16;
-        if (n >= N) continue;
-        const auto col = column(epi, n);
-#pragma unroll
-        for (int i = 0; i < TM; ++i) epilogue(epi, col, m0 + wm + 16 * i + 4 * g4, acc[i][j]);
-    }
+    // float32: single stencil steps keep the kernel at four waves per SIMD
+    run_epilogue<TM, TN, sizeof(T) == 4 ? 1 : 2>(epi, acc, m0 + wm, n0 + wn, N, lane);
 }
 
 // [i][n] (rank-major, RP rows) -> [n][i] (voxel-major, Rg columns), zero padded;
