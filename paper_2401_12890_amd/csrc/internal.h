@@ -39,7 +39,6 @@ struct IterArgs {
     const void *Vlo;
     const void *bcoef;    // b_i = sigma_i^2 / (beta + sigma_i^2), RP (state type)
     const void *Vu;       // fused kernel: per-chunk V operand blocks
-    const void *Vy;       // (unused)
     int r, RP, nchunk;
     Grid g;
     double tau, lam2, beta;   // tau = 1/(xi+beta), lam2 = 2*lambda (D^T D = 2L)

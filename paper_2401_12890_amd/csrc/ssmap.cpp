@@ -410,7 +410,6 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     a.Vlo = Vlo;
     a.bcoef = bd;
     a.Vu = Vop;
-    a.Vy = nullptr;
     a.r = r;
     a.RP = RP;
     a.nchunk = c->nchunk;
