@@ -508,44 +508,104 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             }
     }
 
-    // ---- r-vector recursion; lane holds y^{k+1}[r][voxel j] for the four
-    //      ranks r of its accumulator rows
-    const T *ah = (const T *)a.ah;
-    const T *bc = (const T *)a.bcoef;
-    const unsigned rbytes = (unsigned)((size_t)a.RP * N * sizeof(T));
-    const __amdgpu_buffer_rsrc_t wr = rsrc(a.w, rbytes), yr = rsrc(a.y, rbytes);
-    const T *yold = (const T *)a.y;
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                // f64 16x16x4 returns rows l/16 + 4 i; the others rows 4 (l/16) + i
-                const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
-                if (r >= a.r) continue;          // padded ranks stay 0 (never stored)
-                const size_t o = (size_t)r * N + nvox[b];
-                T yn;
-                if constexpr (TAIL) {
-                    if (rb == 0) {
-                        yn = yacc[b][0][i];
-                    } else {                     // r in 16..19 here (a.r <= 20)
-                        const int t = r - 16;
-                        yn = t == 0 ? ytail[b][0] : t == 1 ? ytail[b][1] : t == 2 ? ytail[b][2] : ytail[b][3];
+    // ---- r-vector recursion (lane holds y^{k+1}[r][voxel j] for the four ranks r
+    //      of its accumulator rows). The double-buffered float32 brick issues a
+    //      row's loads before forming any result (measured 1 % faster there; the
+    //      other shapes measured slower with it and keep one rank at a time).
+    if constexpr (DBL) {
+        // padded ranks and voxels outside the grid get out-of-range offsets: their
+        // loads return 0 and their stores are dropped
+        const unsigned rbytes = (unsigned)((size_t)a.RP * N * sizeof(T));
+        const __amdgpu_buffer_rsrc_t wr = rsrc(a.w, rbytes), yr = rsrc(a.y, rbytes), ahr = rsrc(a.ah, rbytes),
+                                     bcr = rsrc(a.bcoef, (unsigned)(a.RP * sizeof(T)));
+        auto ld1 = [](const __amdgpu_buffer_rsrc_t &rs, unsigned off) -> T {
+            if constexpr (sizeof(T) == 8)
+                return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+            else
+                return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        };
+    #pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            T lah[RB][4], lyo[RB][4], lw[RB][4], lbc[RB][4];
+            unsigned ob[RB][4];
+    #pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    // f64 16x16x4 returns rows l/16 + 4 i; the others rows 4 (l/16) + i
+                    const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
+                    const size_t o = (size_t)r * N + nvox[b];
+                    ob[rb][i] = r < a.r && valid[b] ? (unsigned)(o * sizeof(T)) : OOB;
+                    const unsigned obc = r < a.r ? (unsigned)(r * sizeof(T)) : OOB;
+                    lah[rb][i] = ld1(ahr, ob[rb][i]);
+                    lyo[rb][i] = ld1(yr, ob[rb][i]);
+                    lw[rb][i] = ld1(wr, ob[rb][i]);
+                    lbc[rb][i] = ld1(bcr, obc);
+                }
+    #pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
+                    T yn;
+                    if constexpr (TAIL) {
+                        if (rb == 0) {
+                            yn = yacc[b][0][i];
+                        } else {                     // r in 16..19 here (a.r <= 20)
+                            const int t = r - 16;
+                            yn = t == 0 ? ytail[b][0] : t == 1 ? ytail[b][1] : t == 2 ? ytail[b][2] : ytail[b][3];
+                        }
+                    } else {
+                        yn = yacc[b][rb][i];
                     }
-                } else {
-                    yn = yacc[b][rb][i];
+                    const T wn = lah[rb][i] - lbc[rb][i] * ((T)2 * yn - lyo[rb][i] - lw[rb][i]);
+                    if constexpr (sizeof(T) == 8) {
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, wn), wr, ob[rb][i], 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, yn), yr, ob[rb][i], 0, 0);
+                    } else {
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, wn), wr, ob[rb][i], 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, yn), yr, ob[rb][i], 0, 0);
+                    }
                 }
-                const T wn = ah[o] - bc[r] * ((T)2 * yn - yold[o] - wsrc[o]);
-                const unsigned ob = valid[b] ? (unsigned)(o * sizeof(T)) : OOB;
-                if constexpr (sizeof(T) == 8) {
-                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, wn), wr, ob, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, yn), yr, ob, 0, 0);
-                } else {
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, wn), wr, ob, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, yn), yr, ob, 0, 0);
+        }
+    } else {
+        const T *ah = (const T *)a.ah;
+        const T *bc = (const T *)a.bcoef;
+        const unsigned rbytes = (unsigned)((size_t)a.RP * N * sizeof(T));
+        const __amdgpu_buffer_rsrc_t wr = rsrc(a.w, rbytes), yr = rsrc(a.y, rbytes);
+        const T *yold = (const T *)a.y;
+    #pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+    #pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    // f64 16x16x4 returns rows l/16 + 4 i; the others rows 4 (l/16) + i
+                    const int r = MODE == MODE_FP64 ? 16 * rb + i4 + 4 * i : 16 * rb + 4 * i4 + i;
+                    if (r >= a.r) continue;          // padded ranks stay 0 (never stored)
+                    const size_t o = (size_t)r * N + nvox[b];
+                    T yn;
+                    if constexpr (TAIL) {
+                        if (rb == 0) {
+                            yn = yacc[b][0][i];
+                        } else {                     // r in 16..19 here (a.r <= 20)
+                            const int t = r - 16;
+                            yn = t == 0 ? ytail[b][0] : t == 1 ? ytail[b][1] : t == 2 ? ytail[b][2] : ytail[b][3];
+                        }
+                    } else {
+                        yn = yacc[b][rb][i];
+                    }
+                    const T wn = ah[o] - bc[r] * ((T)2 * yn - yold[o] - wsrc[o]);
+                    const unsigned ob = valid[b] ? (unsigned)(o * sizeof(T)) : OOB;
+                    if constexpr (sizeof(T) == 8) {
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, wn), wr, ob, 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, yn), yr, ob, 0, 0);
+                    } else {
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, wn), wr, ob, 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, yn), yr, ob, 0, 0);
+                    }
                 }
-            }
+        }
     }
 }
 
