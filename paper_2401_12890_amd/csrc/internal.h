@@ -70,6 +70,7 @@ struct FusedLaunch {
     const TileRef *tiles;  // device array
     int ntiles;
     int round;             // iteration counter of the shared loop
+    int maxchunk;          // largest chunk count among the jobs (0: unknown)
 };
 // fused_supported(): whether (mode, padded rank, voxel count) has a fused kernel.
 bool fused_supported(int mode, int RP, int64_t N);

@@ -175,6 +175,7 @@ struct Class {
     TileRef *dtiles = nullptr;
     size_t cap_jobs = 0, cap_tiles = 0;
     int ntiles = 0;
+    int maxchunk = 0;                // largest chunk count among the members
     double model_ms = 0;                  // modelled duration of one round (alone on the GPU)
     double ratio = 1.0;                   // measured / modelled round time (running mean)
     struct Chunk {
@@ -434,6 +435,8 @@ void upload_tables(ssmap_server *sv, Class &C) {
     upload(sv, C.lane, C.djobs, args.data(), args.size() * sizeof(IterArgs));
     upload(sv, C.lane, C.dtiles, tiles.data(), tiles.size() * sizeof(TileRef));
     C.ntiles = (int)tiles.size();
+    C.maxchunk = 0;
+    for (const IterArgs &a : args) C.maxchunk = std::max(C.maxchunk, a.nchunk);
     C.model_ms = kLaunchMs + bytes / kBytesPerMs;
     C.dirty = false;
 }
@@ -580,6 +583,7 @@ void run_class(ssmap_server *sv, Class &C, double horizon_ms) {
         L.jobs = C.djobs;
         L.tiles = C.dtiles;
         L.ntiles = C.ntiles;
+        L.maxchunk = C.maxchunk;
         L.round = (int)(C.round & 0x3fffffff);   // only the parity matters
         if (!launch_fused(L, s)) sfail(SSMAP_EINVAL, "no fused kernel for this class");
         sv->stats.launches++;

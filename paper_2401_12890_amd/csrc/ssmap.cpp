@@ -631,6 +631,7 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
     L.jobs = dj;
     L.tiles = dt;
     L.ntiles = (int)tiles.size();
+    L.maxchunk = c->nchunk;
     return L;
 }
 
@@ -832,6 +833,7 @@ void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector
     L.jobs = dj;
     L.tiles = dt;
     L.ntiles = (int)tiles.size();
+    for (const IterArgs &a : args) L.maxchunk = std::max(L.maxchunk, a.nchunk);
 }
 
 // One shared launch of iteration k (jobs[2j], jobs[2j+1]: job j's even and

@@ -130,6 +130,33 @@ def test_crop_parity(torch_cuda, kernel, name, grid, prec, iters):
     assert st["hist_objective"][-1] == pytest.approx(ref["hist"][-1][1], rel=1e-4)
 
 
+# ------------------------------------------------------------ persistent brick walk
+# Short float32 volumetric bricks (Q = 36: three 16-node chunks) run a grid of
+# one workgroup per CU, so with more bricks than CUs a workgroup takes several
+# in turn and prefetches the next brick's first chunks. 320 bricks: the table
+# splits into eight contiguous XCD runs; 350: plain round robin. Ragged in
+# every axis.
+WALKS = [(60, 62, 38), (76, 54, 38)]
+
+
+@pytest.mark.parametrize("grid", WALKS)
+def test_persistent_walk_parity(torch_cuda, grid):
+    iters = 12
+    prob = synth.generate("c2", grid=grid, iters=iters, overrides=dict(n1=6, n2=6))
+    ref = oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, iters, track_every=iters)
+    say("walk", grid, "rank", ref["rank"])
+    with _ffi.Mapper(prob.K, prob.grid) as mp:
+        z = run(mp, prob, "fp32", "fused", iters, ref, keep_aux=True, check_every=iters)
+        f, d = mp.aux()
+        st = mp.stats()
+    tol = TOL["fp32"]
+    assert relerr(z, ref["z"]) <= tol, relerr(z, ref["z"])
+    assert relerr(f, ref["f"]) <= 10 * tol, relerr(f, ref["f"])
+    assert relerr(d, ref["d"]) <= 10 * tol, relerr(d, ref["d"])
+    assert z.min() >= 0.0
+    assert st["hist_objective"][-1] == pytest.approx(ref["hist"][-1][1], rel=1e-4)
+
+
 # ------------------------------------------------------------ edge cases
 EDGES = [
     ("zero iters", dict(P=6, Q=5, grid=(3, 2, 1), iters=0)),
