@@ -77,8 +77,9 @@ bool fused_supported(int mode, int RP, int64_t N);
 bool launch_fused(const FusedLaunch &L, hipStream_t s);   // false: no such shape
 FusedShape default_shape(int mode, const Grid &g);
 std::vector<FusedShape> candidate_shapes(int mode, bool planar);
-// Bricks of a grid in launch order; with `code` only bricks holding an inside voxel.
-void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out,
+// Bricks of a grid in launch order for precision `mode`; with `code` only bricks
+// holding an inside voxel.
+void append_tiles(const Grid &g, int job, int mode, FusedShape sh, std::vector<TileRef> &out,
                   const std::vector<uint8_t> *code = nullptr);
 // Per-chunk V operand blocks of the fused kernel (IterArgs::Vu points to them).
 // `tail`: the kernel takes y of ranks 16..19 on the vector ALU (fused_tail()).

@@ -26,6 +26,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
@@ -1057,16 +1058,27 @@ std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
     return {{4, 4}, {8, 4}};
 }
 
-void append_tiles(const Grid &g, int job, FusedShape sh, std::vector<TileRef> &out,
+void append_tiles(const Grid &g, int job, int mode, FusedShape sh, std::vector<TileRef> &out,
                   const std::vector<uint8_t> *code) {
     const int tx = (int)((g.nx + 15) / 16), ty = (int)((g.ny + sh.ty - 1) / sh.ty),
               tz = (int)((g.nz + sh.tz - 1) / sh.tz);
+    // Bricks that run at the same time on one XCD can share their face halos
+    // through its L2. The float32 16 x 8 x 4 brick (one workgroup per CU, 32 per
+    // XCD) lists its bricks in blocks of 4 x 8 x 1 (x fastest inside a block, the
+    // blocks in x, y, z order). At 128 x 128 x 64 (8 x 16 x 16 bricks) this measured
+    // 2.5 % faster than x-fastest rows, with 4 % fewer bytes read; blocks two bricks
+    // wide read less still but ran 8 % slower, and the 16 x 4 x 4 bricks measured
+    // 0.6-1 % slower with any blocking, so every other shape keeps the plain order.
+    const bool blocked = mode == MODE_FP32 && sh.ty == 8 && sh.tz == 4;
+    const int bx = blocked ? 4 : tx, by = blocked ? 8 : ty;
     for (int k = 0; k < tz; ++k)
-        for (int jy = 0; jy < ty; ++jy)
-            for (int i = 0; i < tx; ++i)
-                if (!code || brick_has_inside(g, *code, (int64_t)i * TX, (int64_t)jy * sh.ty,
-                                              (int64_t)k * sh.tz, TX, sh.ty, sh.tz))
-                    out.push_back(TileRef{job, i, jy, k});
+        for (int j0 = 0; j0 < ty; j0 += by)
+            for (int i0 = 0; i0 < tx; i0 += bx)
+                for (int jy = j0; jy < std::min(j0 + by, ty); ++jy)
+                    for (int i = i0; i < std::min(i0 + bx, tx); ++i)
+                        if (!code || brick_has_inside(g, *code, (int64_t)i * TX, (int64_t)jy * sh.ty,
+                                                      (int64_t)k * sh.tz, TX, sh.ty, sh.tz))
+                            out.push_back(TileRef{job, i, jy, k});
 }
 
 bool launch_fused(const FusedLaunch &L, hipStream_t s) {

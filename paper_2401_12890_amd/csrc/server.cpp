@@ -420,7 +420,7 @@ void upload_tables(ssmap_server *sv, Class &C) {
         args[2 * k] = args_at(j, 0);
         args[2 * k + 1] = args_at(j, 1);
         args[2 * k].phase = args[2 * k + 1].phase = (int)(j.r0 & 1);
-        append_tiles(j.g, (int)k, C.shape, tiles);
+        append_tiles(j.g, (int)k, C.mode, C.shape, tiles);
         const size_t esz = j.mode == MODE_FP64 ? 8 : 4;
         bytes += (double)j.g.N * (2.0 * j.a.nchunk * QC + 5.0 * j.RP) * esz;
     }

@@ -621,7 +621,7 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
     L.RP = P.pl.RP;
     L.shape = default_shape(P.pl.mode, c->g);
     std::vector<TileRef> tiles;
-    append_tiles(c->g, 0, L.shape, tiles, c->code.empty() ? nullptr : &c->code);
+    append_tiles(c->g, 0, L.mode, L.shape, tiles, c->code.empty() ? nullptr : &c->code);
     IterArgs two[2] = {args_for(P, 0), args_for(P, 1)};
     IterArgs *dj = (IterArgs *)ensure(c, "jobs", sizeof(two));
     TileRef *dt = (TileRef *)ensure(c, "tiles", tiles.size() * sizeof(TileRef));
@@ -815,7 +815,7 @@ void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector
         const int j = C.jobs[k];
         args[2 * k] = args_for(Ps[j], 0);                    // even iterations
         args[2 * k + 1] = args_for(Ps[j], 1);                // odd iterations
-        append_tiles(b->jobs[j]->g, (int)k, shape, tiles,
+        append_tiles(b->jobs[j]->g, (int)k, C.mode, shape, tiles,
                      b->jobs[j]->code.empty() ? nullptr : &b->jobs[j]->code);
     }
     ssmap_ctx *A = &b->arena;
