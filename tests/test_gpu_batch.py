@@ -53,6 +53,30 @@ def test_batch_equals_solo_and_oracle(torch_cuda, slices, prec):
         assert err <= TOL[prec], (p.grid, p.Q, err)
 
 
+def test_batch_persistent_walk_across_jobs(torch_cuda):
+    # Volumetric float32 jobs with short spectra (3 and 4 chunks of 16 nodes) in one
+    # class: 419 bricks of 16 x 8 x 4, more than the CUs, so each workgroup of the
+    # persistent grid walks several bricks and its load stream crosses from one
+    # job's bricks into the next job's. Ragged grids; Q = 36, 49, 64.
+    iters = 10
+    probs = [synth.generate("c2", grid=g, iters=iters, overrides=dict(n1=n, n2=n))
+             for g, n in (((60, 62, 38), 6), ((40, 30, 21), 7), ((33, 17, 9), 8))]
+    with _ffi.BatchMapper([p.K for p in probs], [p.grid for p in probs]) as bm:
+        F = bm.solve([p.m for p in probs], [p.lam for p in probs], [p.beta for p in probs], iters,
+                     precision="fp32")
+        st = bm.stats()
+    say("walk batch", st["classes"])
+    assert st["nclasses"] == 1 and st["solo_jobs"] == 0
+    assert st["classes"][0]["brick"] == (16, 8, 4) and st["classes"][0]["bricks"] == 419
+    for p, Fb in zip(probs, F):
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            Fs = mp.solve(p.m, p.lam, p.beta, iters, precision="fp32")
+        assert np.array_equal(Fb, Fs), p.grid
+        ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters)
+        err = np.linalg.norm(Fb - ref["z"]) / np.linalg.norm(ref["z"])
+        assert err <= TOL["fp32"], (p.grid, p.Q, err)
+
+
 def test_batch_autotune_keeps_the_bits(torch_cuda, slices):
     iters = 12
     with _ffi.BatchMapper([p.K for p in slices], [p.grid for p in slices]) as bm:
