@@ -156,22 +156,11 @@ __device__ __forceinline__ v4f dpp_x(v4f edge, v4f v) {
         o[k] = __uint_as_float(dpp_x<SHR>(__float_as_uint(edge[k]), __float_as_uint(v[k])));
     return o;
 }
-template <bool SHR>
-__device__ __forceinline__ v4d dpp_x(v4d edge, v4d v) {
-    v4d o;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t e = __builtin_bit_cast(uint64_t, edge[k]), x = __builtin_bit_cast(uint64_t, v[k]);
-        const uint64_t lo = dpp_x<SHR>((unsigned)e, (unsigned)x);
-        const uint64_t hi = dpp_x<SHR>((unsigned)(e >> 32), (unsigned)(x >> 32));
-        o[k] = __builtin_bit_cast(double, lo | (hi << 32));
-    }
-    return o;
-}
 
 // Four state values (16 B for float, 32 B for double) through a buffer resource.
 // Stores of z^{k+1} are non-temporal (CPol NT): nothing reads them again in this
-// launch (measured 4 % faster); loads stay cached, the halo re-reads hit L2.
+// launch (measured 4 % faster); loads stay cached, so a face halo that a brick
+// running at the same time on the same XCD has just loaded can hit its L2.
 constexpr int NT_STORE = 2;
 template <typename T, typename V4> struct Buf;
 template <> struct Buf<float, v4f> {
@@ -233,11 +222,13 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     static_assert(VB % 16 == 0 && VB / 16 <= NT, "V operand block must stage in one pass");
     static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
 
-    // The float32 16 x 8 x 4 brick (one workgroup per CU either way) double-buffers
-    // its LDS: chunk c + 1 is stored while chunk c is read, one barrier per chunk.
-    // It also runs persistent: a workgroup takes several bricks in turn and the
-    // loads of a brick's first chunks overlap the end of the one before it.
-    constexpr bool DBL = MODE == MODE_FP32 && TY == 8 && TZ == 4;
+    // The float32 16 x 8 x 4 and float64 16 x 8 x 1 bricks (one workgroup per CU
+    // either way) double-buffer their LDS: chunk c + 1 is stored while chunk c is
+    // read, one barrier per chunk, the loads two chunks ahead. The float32 brick
+    // also runs persistent for short spectra: a workgroup takes several bricks in
+    // turn and the loads of a brick's first chunks overlap the end of the one
+    // before it.
+    constexpr bool DBL = (MODE == MODE_FP32 && TY == 8 && TZ == 4) || (MODE == MODE_FP64 && TY == 8 && TZ == 1);
     constexpr int NBUF = DBL ? 2 : 1;
     __shared__ V4 lds[NBUF][4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
     __shared__ uint4 ldsv[NBUF][NT];           // V operands of the chunk (entries >= VB/16 unused)
@@ -491,7 +482,10 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             // when the rows of a wave stack along z, this lane's z^k of every row
             // is read once and also serves as the z neighbours of the adjacent rows
             const V4 *L = lds[cb] + i4 * B::NSP;
-            constexpr bool ZREG = TY == NW;      // row b + 1 of a wave is one step along z
+            // (float64 keeps the LDS stencil: built with x neighbours by DPP on both
+            // 32-bit halves, the compiled code shifted only the first of the four
+            // doubles and reused its neighbour sum for the other three)
+            constexpr bool ZREG = TY == NW && MODE != MODE_FP64;   // row b + 1 of a wave is one step along z
             V4 zcs[ZREG ? BPW : 1];
             if constexpr (ZREG) {
     #pragma unroll
@@ -579,8 +573,8 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
         }
 
         // ---- r-vector recursion (lane holds y^{k+1}[r][voxel j] for the four ranks r
-        //      of its accumulator rows). The double-buffered float32 brick issues a
-        //      row's loads before forming any result (measured 1 % faster there; the
+        //      of its accumulator rows). The double-buffered bricks issue a row's
+        //      loads before forming any result (measured 1 % faster for float32; the
         //      other shapes measured slower with it and keep one rank at a time).
         if constexpr (DBL) {
             // padded ranks and voxels outside the grid get out-of-range offsets: their
@@ -1011,6 +1005,7 @@ template <int MODE, int RB, int KSU>
 bool launch_shape(const FusedLaunch &L, hipStream_t s) {
     const int ty = L.shape.ty, tz = L.shape.tz;
     if constexpr (MODE == MODE_FP64) {
+        if (ty == 8 && tz == 1) return launch_t<MODE, RB, KSU, 8, 1>(L, s), true;
         if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
         if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
     } else {
@@ -1044,13 +1039,15 @@ bool fused_supported(int mode, int RP, int64_t N) {
 }
 
 FusedShape default_shape(int mode, const Grid &g) {
-    if (mode == MODE_FP64) return g.nz == 1 ? FusedShape{16, 1} : FusedShape{4, 4};
+    // float64 planar: the double-buffered 16 x 8 x 1 brick (32 x 32 with Q = 100:
+    // 31.3 -> 18.3 us per iteration against 16 x 16 x 1; 1024 x 1024: 777 -> 745 us)
+    if (mode == MODE_FP64) return g.nz == 1 ? FusedShape{8, 1} : FusedShape{4, 4};
     if (mode == MODE_BF16X3) return g.nz == 1 ? FusedShape{16, 1} : FusedShape{4, 4};
     return g.nz == 1 ? FusedShape{16, 1} : FusedShape{8, 4};
 }
 
 std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
-    if (mode == MODE_FP64) return planar ? std::vector<FusedShape>{{16, 1}} : std::vector<FusedShape>{{4, 4}};
+    if (mode == MODE_FP64) return planar ? std::vector<FusedShape>{{8, 1}, {16, 1}} : std::vector<FusedShape>{{4, 4}};
     if (planar) {
         if (mode == MODE_FP32) return {{8, 1}, {16, 1}, {32, 1}};
         return {{8, 1}, {16, 1}};
