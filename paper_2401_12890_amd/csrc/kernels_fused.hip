@@ -222,13 +222,15 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     static_assert(VB % 16 == 0 && VB / 16 <= NT, "V operand block must stage in one pass");
     static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
 
-    // The float32 16 x 8 x 4 and float64 16 x 8 x 1 bricks (one workgroup per CU
-    // either way) double-buffer their LDS: chunk c + 1 is stored while chunk c is
-    // read, one barrier per chunk, the loads two chunks ahead. The float32 brick
-    // also runs persistent for short spectra: a workgroup takes several bricks in
-    // turn and the loads of a brick's first chunks overlap the end of the one
-    // before it.
-    constexpr bool DBL = (MODE == MODE_FP32 && TY == 8 && TZ == 4) || (MODE == MODE_FP64 && TY == 8 && TZ == 1);
+    // The float32 16 x 8 x 4 and 16 x 16 x 1 and the float64 16 x 8 x 1 bricks
+    // double-buffer their LDS (one workgroup per CU): chunk c + 1 is stored while
+    // chunk c is read, one barrier per chunk, the loads two chunks ahead (float32
+    // planar: 10 % faster on the batched slices than two single-buffered
+    // workgroups per CU). The float32 volumetric brick also runs persistent for
+    // short spectra: a workgroup takes several bricks in turn and the loads of a
+    // brick's first chunks overlap the end of the one before it.
+    constexpr bool DBL = (MODE == MODE_FP32 && ((TY == 8 && TZ == 4) || (TY == 16 && TZ == 1))) ||
+                         (MODE == MODE_FP64 && TY == 8 && TZ == 1);
     constexpr int NBUF = DBL ? 2 : 1;
     __shared__ V4 lds[NBUF][4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
     __shared__ uint4 ldsv[NBUF][NT];           // V operands of the chunk (entries >= VB/16 unused)
