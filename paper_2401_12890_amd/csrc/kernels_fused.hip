@@ -226,9 +226,9 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     // double-buffer their LDS (one workgroup per CU): chunk c + 1 is stored while
     // chunk c is read, one barrier per chunk, the loads two chunks ahead (float32
     // planar: 10 % faster on the batched slices than two single-buffered
-    // workgroups per CU). The float32 volumetric brick also runs persistent for
-    // short spectra: a workgroup takes several bricks in turn and the loads of a
-    // brick's first chunks overlap the end of the one before it.
+    // workgroups per CU). For short spectra they also run persistent: a workgroup
+    // takes several bricks in turn and the loads of a brick's first chunks overlap
+    // the end of the one before it.
     constexpr bool DBL = (MODE == MODE_FP32 && ((TY == 8 && TZ == 4) || (TY == 16 && TZ == 1))) ||
                          (MODE == MODE_FP64 && TY == 8 && TZ == 1);
     constexpr int NBUF = DBL ? 2 : 1;
@@ -241,10 +241,11 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     const int j = lane & 15;
     const int i4 = lane >> 4;
 
-    // ---- bricks of this workgroup. The double-buffered brick runs a persistent
-    //      grid (about one workgroup per CU, each taking its bricks in turn); the
-    //      other shapes run one brick per workgroup. Either way the bricks of an
-    //      XCD form one contiguous run of the table (neighbours share its L2).
+    // ---- bricks of this workgroup. For short spectra the double-buffered bricks
+    //      run a persistent grid (about one workgroup per CU, each taking its
+    //      bricks in turn); otherwise every workgroup takes one brick. Either way
+    //      the bricks of an XCD form one contiguous run of the table (neighbours
+    //      share its L2).
     auto tile_of = [&](int it) -> int {  // it-th brick of this workgroup, -1 past the last
         const int b = blockIdx.x, nwg = gridDim.x;
         if ((ntiles & 7) == 0 && (nwg & 7) == 0) {
@@ -276,10 +277,11 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     }
 
     // ---- the load stream: one fetch brings the z quads and the V operand block of
-    //      one chunk into registers. The double-buffered brick streams chunk 0 ..
-    //      nchunk-1 of each of its bricks in turn (past the last brick every offset
-    //      is out of range: zeros, no memory traffic); the others re-read their last
-    //      chunk at the end (one loop path with exact wait counts).
+    //      one chunk into registers. With a double-buffered shape a workgroup
+    //      streams chunk 0 .. nchunk-1 of each of its bricks in turn (past the last
+    //      brick every offset is out of range: zeros, no memory traffic); the other
+    //      shapes re-read their last chunk at the end (one loop path with exact
+    //      wait counts).
     V4 R[NL];
     uint4 Rv;
     unsigned voff[NL];                   // byte offset of the staged quad in a chunk (OOB: zero)
@@ -962,7 +964,7 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
     }
 }
 
-// Longest brick (in 16-node chunks) that the double-buffered shape runs persistent.
+// Longest brick (in 16-node chunks) that the double-buffered shapes run persistent.
 constexpr int kPersistChunks = 32;
 
 // Compute units of the current device (the persistent grid's width), read once per device.
@@ -987,14 +989,17 @@ void launch_t(const FusedLaunch &L, hipStream_t s) {
         hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s,
                            L.jobs, L.tiles, L.ntiles, L.round);
     else {
-        // Short bricks of the double-buffered shape (one workgroup per CU) run a
+        // Short bricks of the double-buffered shapes (one workgroup per CU) run a
         // persistent grid, at most one workgroup per CU: the loads of a brick's
-        // first chunks then overlap the end of the brick before (measured 3 %
-        // faster per iteration at 9 chunks). Long bricks take one workgroup each:
-        // the hardware's dynamic dispatch balances them better than a fixed share
-        // per CU (measured 1 % slower persistent at 100 chunks, equal at 25..49).
+        // first chunks then overlap the end of the brick before. Measured per
+        // iteration: float32 128 x 128 x 64 at 9 chunks 3 % faster, equal at
+        // 25..49; float64 512 x 512 at 7 chunks 5 % faster; float32 512 x 512 at
+        // 25 chunks 4 % faster. Long bricks take one workgroup each: the
+        // hardware's dynamic dispatch balances them better than a fixed share per
+        // CU (float32 volumetric at 100 chunks: 1 % slower persistent).
         int nwg = L.ntiles;
-        if constexpr (MODE == MODE_FP32 && TY == 8 && TZ == 4) {
+        if constexpr ((MODE == MODE_FP32 && ((TY == 8 && TZ == 4) || (TY == 16 && TZ == 1))) ||
+                      (MODE == MODE_FP64 && TY == 8 && TZ == 1)) {
             const int cus = device_cus();
             if (L.maxchunk > 0 && L.maxchunk <= kPersistChunks && cus > 0 && cus < nwg) nwg = cus;
         }

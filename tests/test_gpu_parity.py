@@ -131,25 +131,27 @@ def test_crop_parity(torch_cuda, kernel, name, grid, prec, iters):
 
 
 # ------------------------------------------------------------ persistent brick walk
-# Short float32 volumetric bricks (Q = 36: three 16-node chunks) run a grid of
-# one workgroup per CU, so with more bricks than CUs a workgroup takes several
-# in turn and prefetches the next brick's first chunks. 320 bricks: the table
-# splits into eight contiguous XCD runs; 350: plain round robin. Ragged in
-# every axis.
-WALKS = [(60, 62, 38), (76, 54, 38)]
+# Short spectra on the double-buffered bricks run a grid of one workgroup per
+# CU, so with more bricks than CUs a workgroup takes several in turn and
+# prefetches the next brick's first chunks. Float32 volumetric (16 x 8 x 4,
+# Q = 36): 320 bricks, the table in eight contiguous XCD runs, and 350, plain
+# round robin. Float64 planar (16 x 8 x 1, Q = 100): 312 bricks. Float32
+# planar (16 x 16 x 1, Q = 36): 304 bricks. Ragged in every axis.
+WALKS = [("c2", (60, 62, 38), "fp32", 6), ("c2", (76, 54, 38), "fp32", 6),
+         ("c1", (200, 190, 1), "fp64", 10), ("c2", (300, 250, 1), "fp32", 6)]
 
 
-@pytest.mark.parametrize("grid", WALKS)
-def test_persistent_walk_parity(torch_cuda, grid):
+@pytest.mark.parametrize("recipe,grid,prec,n", WALKS)
+def test_persistent_walk_parity(torch_cuda, recipe, grid, prec, n):
     iters = 12
-    prob = synth.generate("c2", grid=grid, iters=iters, overrides=dict(n1=6, n2=6))
+    prob = synth.generate(recipe, grid=grid, iters=iters, overrides=dict(n1=n, n2=n))
     ref = oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, iters, track_every=iters)
-    say("walk", grid, "rank", ref["rank"])
+    say("walk", recipe, grid, prec, "rank", ref["rank"])
     with _ffi.Mapper(prob.K, prob.grid) as mp:
-        z = run(mp, prob, "fp32", "fused", iters, ref, keep_aux=True, check_every=iters)
+        z = run(mp, prob, prec, "fused", iters, ref, keep_aux=True, check_every=iters)
         f, d = mp.aux()
         st = mp.stats()
-    tol = TOL["fp32"]
+    tol = TOL[prec]
     assert relerr(z, ref["z"]) <= tol, relerr(z, ref["z"])
     assert relerr(f, ref["f"]) <= 10 * tol, relerr(f, ref["f"])
     assert relerr(d, ref["d"]) <= 10 * tol, relerr(d, ref["d"])
