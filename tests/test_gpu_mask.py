@@ -77,6 +77,33 @@ def test_masked_solve_matches_oracle(torch_cuda, name, recipe, grid, centre, rad
             assert err <= TOL[prec], (name, prec, kernel, err)
 
 
+# Masked grids with short spectra on the double-buffered bricks: the brick
+# table holds only bricks with an inside voxel (still more than the CUs), and
+# the persistent grid walks it. Float32 volumetric 16 x 8 x 4 (Q = 36) and
+# float64 planar 16 x 8 x 1 (Q = 100).
+WALK_CASES = [
+    ("c2", (70, 66, 40), (34, 32, 19), (33, 31, 19), "fp32", 6),
+    ("c1", (300, 200, 1), (150, 100, 0), (148, 98, 1), "fp64", 10),
+]
+
+
+@pytest.mark.parametrize("recipe,grid,centre,radii,prec,n", WALK_CASES)
+def test_masked_persistent_walk(torch_cuda, recipe, grid, centre, radii, prec, n):
+    iters = 10
+    p = synth.generate(recipe, grid=grid, iters=iters, overrides=dict(n1=n, n2=n))
+    mask = ellipsoid_mask(grid, centre, radii, holes=40, seed=5)
+    m = p.m.copy()
+    m[~mask] = np.nan
+    ref = oracle.ladmm(p.K, m, p.grid, p.lam, p.beta, iters, mask=mask)
+    say("masked walk", recipe, grid, prec, "inside", int(mask.sum()), "of", p.N, "rank", ref["rank"])
+    with _ffi.Mapper(p.K, p.grid) as mp:
+        mp.set_mask(mask)
+        F = mp.solve(m, p.lam, p.beta, iters, precision=prec, kernel="fused")
+    assert np.all(F[~mask] == 0.0)
+    err = relerr(F, ref["z"])
+    assert err <= TOL[prec], (recipe, grid, prec, err)
+
+
 def test_mask_norm_objective_and_reset(torch_cuda):
     p = synth.generate("c1", grid=(23, 17, 1), iters=30)
     mask = ellipsoid_mask(p.grid, (11, 8, 0), (10, 7, 1), holes=5, seed=3)

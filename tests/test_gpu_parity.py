@@ -136,9 +136,13 @@ def test_crop_parity(torch_cuda, kernel, name, grid, prec, iters):
 # prefetches the next brick's first chunks. Float32 volumetric (16 x 8 x 4,
 # Q = 36): 320 bricks, the table in eight contiguous XCD runs, and 350, plain
 # round robin. Float64 planar (16 x 8 x 1, Q = 100): 312 bricks. Float32
-# planar (16 x 16 x 1, Q = 36): 304 bricks. Ragged in every axis.
+# planar (16 x 16 x 1, Q = 36): 304 bricks. With Q = 16 each brick is a single
+# chunk, so the stream moves on to the next brick at every chunk (324, 306 and
+# 289 bricks, rank below 17). Ragged in every axis.
 WALKS = [("c2", (60, 62, 38), "fp32", 6), ("c2", (76, 54, 38), "fp32", 6),
-         ("c1", (200, 190, 1), "fp64", 10), ("c2", (300, 250, 1), "fp32", 6)]
+         ("c1", (200, 190, 1), "fp64", 10), ("c2", (300, 250, 1), "fp32", 6),
+         ("c2", (64, 72, 36), "fp32", 4), ("c1", (260, 140, 1), "fp64", 4),
+         ("c2", (270, 260, 1), "fp32", 4)]
 
 
 @pytest.mark.parametrize("recipe,grid,prec,n", WALKS)
