@@ -554,6 +554,9 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": kern_name, "avg_launch_ms": round(per_launch_ms, 5),
                     "alg_bytes_per_launch": alg}
+        if 2 * prob.N * prob.Q * wbytes < (64 << 20):
+            roofline["note"] = ("the state arrays fit in the caches: the run is latency-bound and "
+                                "the fraction of the HBM peak does not bound it")
 
     parity = None
     if not args.no_parity and rank == 0:
