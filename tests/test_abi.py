@@ -78,3 +78,32 @@ def test_server_structs_and_argument_errors():
     assert lib.ssmap_server_drain(None) == _ffi.SSMAP_EINVAL
     assert lib.ssmap_server_poll(None, 0, None) == _ffi.SSMAP_EINVAL
     assert lib.ssmap_server_get_stats(None, None) == _ffi.SSMAP_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # the binding never falls back to another implementation
+    with pytest.raises(OSError):
+        _ffi.load(str(tmp_path / "libssmap.so"))
+
+
+def test_package_imports_nothing_from_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2401_12890_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, flags=re.M), f
+                assert "import_module" not in text and "__import__" not in text, f
+
+
+def test_solve_without_a_gpu_is_an_error():
+    # with no HIP device the library reports it; nothing is computed elsewhere
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2401_12890_amd import synth
+    p = synth.generate("c1", grid=(4, 4, 1), iters=3)
+    with pytest.raises(_ffi.SsmapError) as e:
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            mp.solve(p.m, p.lam, p.beta, 3)
+    assert e.value.status == _ffi.SSMAP_ENODEV
