@@ -248,7 +248,9 @@ ssmap_status ssmap_batch_create(int njobs, const double *const *K, const int *P,
  * `hip_stream`. dM[j] / dF[j] as in ssmap_solve_device for job j; lambda and
  * steps are per job (njobs entries). steps[j].check_every must be 0 and
  * SSMAP_KEEP_AUX unset (use the single-problem entry points for those).
- * SSMAP_AUTOTUNE in any job's flags turns the shape search on. */
+ * SSMAP_AUTOTUNE in any job's flags turns the shape search on; the shapes it
+ * chooses are kept in `b` and used by its later solves of the same classes
+ * (same precision, rank bucket and member jobs) until it is destroyed. */
 ssmap_status ssmap_batch_solve_device(ssmap_batch *b, const void *const *dM, const double *lambda,
                                       const ssmap_steps *steps, int iters, void *const *dF,
                                       void *hip_stream);

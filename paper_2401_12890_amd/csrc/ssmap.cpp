@@ -797,6 +797,9 @@ struct ssmap_batch {
     bool poisoned = false;
     ssmap_batch_stats stats{};
     hipEvent_t ev[6] = {};
+    // brick shapes chosen by a tuned solve, by class (precision, padded rank,
+    // planar, member jobs): later solves of the same classes reuse them
+    std::map<std::string, FusedShape> tuned;
 };
 
 namespace {
@@ -912,7 +915,11 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
     for (size_t c = 0; c < classes.size(); ++c) {
         BatchClass &C = classes[c];
         Grid g0 = b->jobs[C.jobs[0]]->g;
-        FusedShape best = default_shape(C.mode, g0);
+        std::string key = std::to_string(C.mode) + "/" + std::to_string(C.RP) + "/" +
+                          std::to_string(C.r) + "/" + (C.planar ? "p" : "v");
+        for (int j : C.jobs) key += "," + std::to_string(j);
+        const auto kept = b->tuned.find(key);
+        FusedShape best = kept != b->tuned.end() ? kept->second : default_shape(C.mode, g0);
         const auto cands = candidate_shapes(C.mode, C.planar);
         if (tune && cands.size() > 1 && iters > 0) {
             float best_ms = 1e30f;
@@ -932,6 +939,7 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
             }
             // the search advanced these jobs' states: start them again from z^0
             for (int j : C.jobs) init_state(b->jobs[j], Ps[j], s);
+            b->tuned[key] = best;
         }
         C.shape = best;
         upload_class(b, (int)c, C, Ps, best, Ls[c], s);

@@ -84,10 +84,14 @@ def test_batch_autotune_keeps_the_bits(torch_cuda, slices):
         F0 = bm.solve(*args, precision="fp32")
         F1 = bm.solve(*args, precision="fp32", autotune=True)
         st = bm.stats()
+        # a later solve without the search keeps the shapes it chose
+        F2 = bm.solve(*args, precision="fp32")
+        st2 = bm.stats()
     assert st["autotune_ms"] > 0
     say("autotuned bricks", [c["brick"] for c in st["classes"]])
-    for a, b in zip(F0, F1):
-        assert np.array_equal(a, b)
+    assert [c["brick"] for c in st2["classes"]] == [c["brick"] for c in st["classes"]]
+    for a, b, c in zip(F0, F1, F2):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
 def test_batch_mixed_ranks_solo_jobs_and_device_entry(torch_cuda, slices):
