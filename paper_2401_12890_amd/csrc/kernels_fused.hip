@@ -1049,7 +1049,10 @@ FusedShape default_shape(int mode, const Grid &g) {
     // float64 planar: the double-buffered 16 x 8 x 1 brick (32 x 32 with Q = 100:
     // 31.3 -> 18.3 us per iteration against 16 x 16 x 1; 1024 x 1024: 777 -> 745 us)
     if (mode == MODE_FP64) return g.nz == 1 ? FusedShape{8, 1} : FusedShape{4, 4};
-    if (mode == MODE_BF16X3) return g.nz == 1 ? FusedShape{16, 1} : FusedShape{4, 4};
+    // bf16x3 planar: the 16 x 8 x 1 direct-LDS brick (two workgroups per CU) beat
+    // 16 x 16 x 1 at every size measured (128 x 128: 144 -> 106 us per iteration,
+    // 1024 x 1024: 956 -> 850 us)
+    if (mode == MODE_BF16X3) return g.nz == 1 ? FusedShape{8, 1} : FusedShape{4, 4};
     return g.nz == 1 ? FusedShape{16, 1} : FusedShape{8, 4};
 }
 
