@@ -222,15 +222,15 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     static_assert(VB % 16 == 0 && VB / 16 <= NT, "V operand block must stage in one pass");
     static_assert(BF || (KSU >= 1 && KSU <= KS), "u K-steps must fit the padded rank");
 
-    // The float32 16 x 8 x 4 and 16 x 16 x 1 and the float64 16 x 8 x 1 bricks
-    // double-buffer their LDS (one workgroup per CU): chunk c + 1 is stored while
+    // The float32 16 x 8 x 4 and 16 x 16 x 1 and the float64 16 x 8 x 1 and
+    // 16 x 4 x 2 bricks double-buffer their LDS (one workgroup per CU): chunk c + 1 is stored while
     // chunk c is read, one barrier per chunk, the loads two chunks ahead (float32
     // planar: 10 % faster on the batched slices than two single-buffered
     // workgroups per CU). For short spectra they also run persistent: a workgroup
     // takes several bricks in turn and the loads of a brick's first chunks overlap
     // the end of the one before it.
     constexpr bool DBL = (MODE == MODE_FP32 && ((TY == 8 && TZ == 4) || (TY == 16 && TZ == 1))) ||
-                         (MODE == MODE_FP64 && TY == 8 && TZ == 1);
+                         (MODE == MODE_FP64 && ((TY == 8 && TZ == 1) || (TY == 4 && TZ == 2)));
     constexpr int NBUF = DBL ? 2 : 1;
     __shared__ V4 lds[NBUF][4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
     __shared__ uint4 ldsv[NBUF][NT];           // V operands of the chunk (entries >= VB/16 unused)
@@ -999,7 +999,7 @@ void launch_t(const FusedLaunch &L, hipStream_t s) {
         // CU (float32 volumetric at 100 chunks: 1 % slower persistent).
         int nwg = L.ntiles;
         if constexpr ((MODE == MODE_FP32 && ((TY == 8 && TZ == 4) || (TY == 16 && TZ == 1))) ||
-                      (MODE == MODE_FP64 && TY == 8 && TZ == 1)) {
+                      (MODE == MODE_FP64 && ((TY == 8 && TZ == 1) || (TY == 4 && TZ == 2)))) {
             const int cus = device_cus();
             if (L.maxchunk > 0 && L.maxchunk <= kPersistChunks && cus > 0 && cus < nwg) nwg = cus;
         }
@@ -1015,6 +1015,7 @@ bool launch_shape(const FusedLaunch &L, hipStream_t s) {
         if (ty == 8 && tz == 1) return launch_t<MODE, RB, KSU, 8, 1>(L, s), true;
         if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
         if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
+        if (ty == 4 && tz == 2) return launch_t<MODE, RB, KSU, 4, 2>(L, s), true;
     } else {
         if (ty == 8 && tz == 1) return launch_t<MODE, RB, KSU, 8, 1>(L, s), true;
         if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
@@ -1047,8 +1048,16 @@ bool fused_supported(int mode, int RP, int64_t N) {
 
 FusedShape default_shape(int mode, const Grid &g) {
     // float64 planar: the double-buffered 16 x 8 x 1 brick (32 x 32 with Q = 100:
-    // 31.3 -> 18.3 us per iteration against 16 x 16 x 1; 1024 x 1024: 777 -> 745 us)
-    if (mode == MODE_FP64) return g.nz == 1 ? FusedShape{8, 1} : FusedShape{4, 4};
+    // 31.3 -> 18.3 us per iteration against 16 x 16 x 1; 1024 x 1024: 777 -> 745 us).
+    // float64 volumetric: 16 x 4 x 4, or the double-buffered 16 x 4 x 2 when the
+    // 16 x 4 x 4 bricks would not fill the CUs (32 x 32 x 32 with Q = 100: 34.0 ->
+    // 23.8 us; from 64 x 64 x 32 up 16 x 4 x 4 is 7-17 % faster)
+    if (mode == MODE_FP64) {
+        if (g.nz == 1) return FusedShape{8, 1};
+        const int64_t b44 = ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
+        const int cus = device_cus();
+        return b44 < (cus > 0 ? cus : 256) ? FusedShape{4, 2} : FusedShape{4, 4};
+    }
     // bf16x3 planar: the 16 x 8 x 1 direct-LDS brick (two workgroups per CU) beat
     // 16 x 16 x 1 at every size measured (128 x 128: 144 -> 106 us per iteration,
     // 1024 x 1024: 956 -> 850 us)
@@ -1057,7 +1066,7 @@ FusedShape default_shape(int mode, const Grid &g) {
 }
 
 std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
-    if (mode == MODE_FP64) return planar ? std::vector<FusedShape>{{8, 1}, {16, 1}} : std::vector<FusedShape>{{4, 4}};
+    if (mode == MODE_FP64) return planar ? std::vector<FusedShape>{{8, 1}, {16, 1}} : std::vector<FusedShape>{{4, 4}, {4, 2}};
     if (planar) {
         if (mode == MODE_FP32) return {{8, 1}, {16, 1}, {32, 1}};
         return {{8, 1}, {16, 1}};

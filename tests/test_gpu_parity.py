@@ -163,6 +163,24 @@ def test_persistent_walk_parity(torch_cuda, recipe, grid, prec, n):
     assert st["hist_objective"][-1] == pytest.approx(ref["hist"][-1][1], rel=1e-4)
 
 
+# ------------------------------------------------------------ float64 volumetric bricks
+# float64 3-D grids take 16 x 4 x 2 double-buffered bricks when 16 x 4 x 4 would
+# not fill the CUs, else 16 x 4 x 4: one grid on each side of the rule.
+@pytest.mark.parametrize("grid", [(40, 28, 24), (64, 64, 20)])
+def test_fp64_volumetric_bricks(torch_cuda, grid):
+    iters = 12
+    prob = synth.generate("c1", grid=grid, iters=iters)
+    ref = oracle.ladmm(prob.K, prob.m, prob.grid, prob.lam, prob.beta, iters, track_every=iters)
+    say("fp64 volumetric", grid, "rank", ref["rank"])
+    with _ffi.Mapper(prob.K, prob.grid) as mp:
+        z = run(mp, prob, "fp64", "fused", iters, ref, keep_aux=True, check_every=iters)
+        f, d = mp.aux()
+    assert relerr(z, ref["z"]) <= TOL["fp64"], relerr(z, ref["z"])
+    assert relerr(f, ref["f"]) <= 10 * TOL["fp64"], relerr(f, ref["f"])
+    assert relerr(d, ref["d"]) <= 10 * TOL["fp64"], relerr(d, ref["d"])
+    assert z.min() >= 0.0
+
+
 # ------------------------------------------------------------ edge cases
 EDGES = [
     ("zero iters", dict(P=6, Q=5, grid=(3, 2, 1), iters=0)),
