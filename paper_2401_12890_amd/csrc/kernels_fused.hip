@@ -1062,13 +1062,20 @@ FusedShape default_shape(int mode, const Grid &g) {
     // 16 x 16 x 1 at every size measured (128 x 128: 144 -> 106 us per iteration,
     // 1024 x 1024: 956 -> 850 us)
     if (mode == MODE_BF16X3) return g.nz == 1 ? FusedShape{8, 1} : FusedShape{4, 4};
+    // float32 planar: the double-buffered 16 x 16 x 1 brick, or 16 x 8 x 1 (several
+    // workgroups per CU) while its bricks fit one per CU (128 x 128 with Q = 1600:
+    // 160 -> 121 us per iteration; 176 x 176: 168 -> 131 us; 200 x 180, 312 such
+    // bricks: 174 against 186 us, so 16 x 16 x 1 there).
     // float32 volumetric: 16 x 8 x 4, or 16 x 4 x 4 (twice the bricks, two
     // workgroups per CU) when the 16 x 8 x 4 bricks would not fill the CUs
     // (32 x 32 x 32 with Q = 400: 86.6 -> 51.6 us per iteration; 48 x 48 x 32 with
     // Q = 1600: 332 -> 310 us)
-    if (g.nz == 1) return FusedShape{16, 1};
-    const int64_t b84 = ((g.nx + 15) / 16) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
     const int cus = device_cus();
+    if (g.nz == 1) {
+        const int64_t b16 = ((g.nx + 15) / 16) * ((g.ny + 15) / 16);
+        return 2 * b16 < (cus > 0 ? cus : 256) ? FusedShape{8, 1} : FusedShape{16, 1};
+    }
+    const int64_t b84 = ((g.nx + 15) / 16) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
     return b84 < (cus > 0 ? cus : 256) ? FusedShape{4, 4} : FusedShape{8, 4};
 }
 
