@@ -1021,6 +1021,8 @@ bool launch_shape(const FusedLaunch &L, hipStream_t s) {
         if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
         if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
         if (ty == 8 && tz == 4) return launch_t<MODE, RB, KSU, 8, 4>(L, s), true;
+        if constexpr (MODE == MODE_BF16X3)
+            if (ty == 4 && tz == 2) return launch_t<MODE, RB, KSU, 4, 2>(L, s), true;
         if constexpr (MODE == MODE_FP32)
             if (ty == 32 && tz == 1) return launch_t<MODE, RB, KSU, 32, 1>(L, s), true;
     }
@@ -1055,13 +1057,20 @@ FusedShape default_shape(int mode, const Grid &g) {
     if (mode == MODE_FP64) {
         if (g.nz == 1) return FusedShape{8, 1};
         const int64_t b44 = ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
-        const int cus = device_cus();
-        return b44 < (cus > 0 ? cus : 256) ? FusedShape{4, 2} : FusedShape{4, 4};
+        const int c = device_cus();
+        return b44 < (c > 0 ? c : 256) ? FusedShape{4, 2} : FusedShape{4, 4};
     }
     // bf16x3 planar: the 16 x 8 x 1 direct-LDS brick (two workgroups per CU) beat
     // 16 x 16 x 1 at every size measured (128 x 128: 144 -> 106 us per iteration,
-    // 1024 x 1024: 956 -> 850 us)
-    if (mode == MODE_BF16X3) return g.nz == 1 ? FusedShape{8, 1} : FusedShape{4, 4};
+    // 1024 x 1024: 956 -> 850 us). bf16x3 volumetric: 16 x 4 x 4, or 16 x 4 x 2 when
+    // the 16 x 4 x 4 bricks would not fill the CUs (32 x 32 x 32: 94.7 -> 75.0 us;
+    // at 288 bricks equal, at 384 16 x 4 x 4 is 9 % faster)
+    const int cus = device_cus();
+    if (mode == MODE_BF16X3) {
+        if (g.nz == 1) return FusedShape{8, 1};
+        const int64_t b44 = ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
+        return b44 < (cus > 0 ? cus : 256) ? FusedShape{4, 2} : FusedShape{4, 4};
+    }
     // float32 planar: the double-buffered 16 x 16 x 1 brick, or 16 x 8 x 1 (several
     // workgroups per CU) while its bricks fit one per CU (128 x 128 with Q = 1600:
     // 160 -> 121 us per iteration; 176 x 176: 168 -> 131 us; 200 x 180, 312 such
@@ -1070,7 +1079,6 @@ FusedShape default_shape(int mode, const Grid &g) {
     // workgroups per CU) when the 16 x 8 x 4 bricks would not fill the CUs
     // (32 x 32 x 32 with Q = 400: 86.6 -> 51.6 us per iteration; 48 x 48 x 32 with
     // Q = 1600: 332 -> 310 us)
-    const int cus = device_cus();
     if (g.nz == 1) {
         const int64_t b16 = ((g.nx + 15) / 16) * ((g.ny + 15) / 16);
         return 2 * b16 < (cus > 0 ? cus : 256) ? FusedShape{8, 1} : FusedShape{16, 1};
@@ -1085,6 +1093,7 @@ std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
         if (mode == MODE_FP32) return {{8, 1}, {16, 1}, {32, 1}};
         return {{8, 1}, {16, 1}};
     }
+    if (mode == MODE_BF16X3) return {{4, 4}, {4, 2}, {8, 4}};
     return {{4, 4}, {8, 4}};
 }
 
