@@ -1049,6 +1049,13 @@ bool fused_supported(int mode, int RP, int64_t N) {
 }
 
 FusedShape default_shape(int mode, const Grid &g) {
+    // Bricks per grid for a shape; a grid whose bricks would not fill the CUs is
+    // latency-bound, and a thinner brick (more workgroups) pays there.
+    const int dc = device_cus();
+    const int cus = dc > 0 ? dc : 256;
+    auto bricks = [&](int ty, int tz) -> int64_t {
+        return ((g.nx + 15) / 16) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz);
+    };
     // float64 planar: the double-buffered 16 x 8 x 1 brick (32 x 32 with Q = 100:
     // 31.3 -> 18.3 us per iteration against 16 x 16 x 1; 1024 x 1024: 777 -> 745 us).
     // float64 volumetric: 16 x 4 x 4, or the double-buffered 16 x 4 x 2 when the
@@ -1056,20 +1063,16 @@ FusedShape default_shape(int mode, const Grid &g) {
     // 23.8 us; from 64 x 64 x 32 up 16 x 4 x 4 is 7-17 % faster)
     if (mode == MODE_FP64) {
         if (g.nz == 1) return FusedShape{8, 1};
-        const int64_t b44 = ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
-        const int c = device_cus();
-        return b44 < (c > 0 ? c : 256) ? FusedShape{4, 2} : FusedShape{4, 4};
+        return bricks(4, 4) < cus ? FusedShape{4, 2} : FusedShape{4, 4};
     }
     // bf16x3 planar: the 16 x 8 x 1 direct-LDS brick (two workgroups per CU) beat
     // 16 x 16 x 1 at every size measured (128 x 128: 144 -> 106 us per iteration,
     // 1024 x 1024: 956 -> 850 us). bf16x3 volumetric: 16 x 4 x 4, or 16 x 4 x 2 when
     // the 16 x 4 x 4 bricks would not fill the CUs (32 x 32 x 32: 94.7 -> 75.0 us;
     // at 288 bricks equal, at 384 16 x 4 x 4 is 9 % faster)
-    const int cus = device_cus();
     if (mode == MODE_BF16X3) {
         if (g.nz == 1) return FusedShape{8, 1};
-        const int64_t b44 = ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
-        return b44 < (cus > 0 ? cus : 256) ? FusedShape{4, 2} : FusedShape{4, 4};
+        return bricks(4, 4) < cus ? FusedShape{4, 2} : FusedShape{4, 4};
     }
     // float32 planar: the double-buffered 16 x 16 x 1 brick, or 16 x 8 x 1 (several
     // workgroups per CU) while its bricks fit one per CU (128 x 128 with Q = 1600:
@@ -1079,12 +1082,8 @@ FusedShape default_shape(int mode, const Grid &g) {
     // workgroups per CU) when the 16 x 8 x 4 bricks would not fill the CUs
     // (32 x 32 x 32 with Q = 400: 86.6 -> 51.6 us per iteration; 48 x 48 x 32 with
     // Q = 1600: 332 -> 310 us)
-    if (g.nz == 1) {
-        const int64_t b16 = ((g.nx + 15) / 16) * ((g.ny + 15) / 16);
-        return 2 * b16 < (cus > 0 ? cus : 256) ? FusedShape{8, 1} : FusedShape{16, 1};
-    }
-    const int64_t b84 = ((g.nx + 15) / 16) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
-    return b84 < (cus > 0 ? cus : 256) ? FusedShape{4, 4} : FusedShape{8, 4};
+    if (g.nz == 1) return bricks(8, 1) < cus ? FusedShape{8, 1} : FusedShape{16, 1};
+    return bricks(8, 4) < cus ? FusedShape{4, 4} : FusedShape{8, 4};
 }
 
 std::vector<FusedShape> candidate_shapes(int mode, bool planar) {
