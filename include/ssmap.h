@@ -108,7 +108,7 @@ typedef struct {
     int rank;               /* r used                                             */
     int rank_padded;        /* r rounded up for the contraction tiles              */
     int precision;
-    int kernel;             /* ssmap_kernel actually used (1 or 2)                 */
+    int kernel;             /* ssmap_kernel actually used (1, 2 or 3)              */
     int iters;              /* iterations run                                      */
     int n_hist;             /* entries in the history arrays                       */
     double xi_p;            /* xi_p used                                           */

@@ -39,8 +39,10 @@ def z_solve_dct(b: np.ndarray, grid, lam: float, beta: float) -> np.ndarray:
     return idctn(Bh / (lam * mu + beta), type=2, axes=(0, 1, 2), norm="ortho").reshape(N, Q)
 
 
-def admm_previous(K, m, grid, lam, beta, iters):
-    """Algorithm 1 from zero initial values for a fixed number of iterations.
+def admm_previous(K, m, grid, lam, beta, iters, init=None):
+    """Algorithm 1 for a fixed number of iterations, from zero initial values
+    (as the algorithm states) or from `init`, a dict that may give any of
+    f, x, y, z, dx, dy, dz as (N, Q) arrays (the rest start at zero).
 
     Returns the primal variables f, x, y, z and the duals d_x, d_y, d_z
     (all (N, Q)); y is the nonnegative iterate."""
@@ -53,13 +55,11 @@ def admm_previous(K, m, grid, lam, beta, iters):
         raise ValueError("m must be (N, P)")
     Minv = np.linalg.inv(K.T @ K + beta * np.eye(Q))     # (K^T K + beta I)^{-1}
     g = m @ K                                           # g_n = K^T m_n
-    f = np.zeros((N, Q))
-    x = np.zeros((N, Q))
-    y = np.zeros((N, Q))
-    z = np.zeros((N, Q))
-    dx = np.zeros((N, Q))
-    dy = np.zeros((N, Q))
-    dz = np.zeros((N, Q))
+    init = init or {}
+    start = {k: np.array(init[k], dtype=np.float64) if k in init else np.zeros((N, Q))
+             for k in ("f", "x", "y", "z", "dx", "dy", "dz")}
+    f, x, y, z = start["f"], start["x"], start["y"], start["z"]
+    dx, dy, dz = start["dx"], start["dy"], start["dz"]
     for _ in range(iters):
         f = (beta * x + dx + beta * y + dy + beta * z + dz) / (3.0 * beta)
         x = (g + beta * f - dx) @ Minv.T

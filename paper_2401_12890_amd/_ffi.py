@@ -583,9 +583,9 @@ class Server:
         info = ssmap_server_poll(self.sv, job_id)
         if info["state"] != "done":
             return None
+        M, F = self.live.pop(job_id, (None, None))
         if info["status"] != SSMAP_OK:
             raise SsmapError(info["status"], f"job {job_id} failed")
-        M, F = self.live.pop(job_id)
         return F
 
     def drain(self) -> None:

@@ -1076,7 +1076,7 @@ FusedShape default_shape(int mode, const Grid &g) {
     }
     // float32 planar: the double-buffered 16 x 16 x 1 brick, or 16 x 8 x 1 (several
     // workgroups per CU) while its bricks fit one per CU (128 x 128 with Q = 1600:
-    // 160 -> 121 us per iteration; 176 x 176: 168 -> 131 us; 200 x 180, 312 such
+    // 160 -> 121 us per iteration; 176 x 176: 168 -> 131 us; 200 x 180, 299 such
     // bricks: 174 against 186 us, so 16 x 16 x 1 there).
     // float32 volumetric: 16 x 8 x 4, or 16 x 4 x 4 (twice the bricks, two
     // workgroups per CU) when the 16 x 8 x 4 bricks would not fill the CUs

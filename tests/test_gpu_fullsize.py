@@ -64,15 +64,21 @@ def test_full_size_sampled_parity(torch_cuda, name):
     prob = synth.generate(name)
     prec = prob.precision
     k = 4
-    say("full size", name, prob.grid, prec)
+    # the oracle's own rules on the full grid (not the library's values)
+    U, s, V = oracle.thin_svd(prob.K)
+    rank = oracle.rank_rule(s, 0)
+    xi = oracle.xi_rule(prob.lam, prob.grid)
+    say("full size", name, prob.grid, prec, "rank", rank, "xi", xi)
     with _ffi.Mapper(prob.K, prob.grid) as mp:
         M = torch.tensor(prob.m, dtype=torch.float32, device="cuda")
         F = mp.solve_torch(M, prob.lam, prob.beta, k, precision=prec)
         torch.cuda.synchronize()
         st = mp.stats()
         assert st["kernel"] == 2                       # the fused kernel the benchmark times
+        assert st["rank"] == rank
+        assert st["xi_p"] == pytest.approx(xi, rel=1e-13)
         for pt in sample_points(prob.grid, 12, seed=5):
-            ref = crop_ref(prob, pt, k, st["rank"], st["xi_p"])
+            ref = crop_ref(prob, pt, k, rank, xi)
             n = pt[0] + prob.grid[0] * (pt[1] + prob.grid[1] * pt[2])
             got = F[n].double().cpu().numpy()
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref)

@@ -58,6 +58,70 @@ def test_admm_keeps_eight_image_sized_arrays():
     assert len(state) + 1 == 8                       # f, x, y, z, dx, dy, dz and g
 
 
+def test_admm_fixed_point_is_left_unchanged():
+    """Algorithm 1 seeded at the minimiser z* (from FISTA, an independent
+    solver) with f = x = y = z = z* and the duals that the x-, y- and z-steps
+    imply there -- d_x = K^T (m - K z*), d_y = grad J(z*) (>= 0, zero where
+    z* > 0 by the KKT conditions), d_z = -lambda D^T D z* (so the three sum to
+    zero) -- stays where it is after one iteration."""
+    grid = (4, 3, 2)
+    K, m, lam = smooth_problem(grid, seed=13)
+    beta = 0.7
+    zs, _ = pins.fista(K, m, grid, lam)
+    D = pins.explicit_D(grid)
+    DtD = (D.T @ D).tocsr()
+    dx = (m - zs @ K.T) @ K
+    dz = -lam * (DtD @ zs)
+    dy = pins.grad_J(K, m, zs, grid, lam)
+    assert np.abs(dx + dy + dz).max() <= 1e-12 * np.abs(dx).max()
+    seed = dict(f=zs, x=zs, y=zs, z=zs, dx=dx, dy=dy, dz=dz)
+    out = oracle.admm_previous(K, m, grid, lam, beta, 1, init=seed)
+    scale = np.linalg.norm(zs)
+    for k in ("f", "x", "y", "z"):
+        assert np.linalg.norm(out[k] - zs) <= 1e-8 * scale, k
+    for k in ("dx", "dy", "dz"):
+        assert np.linalg.norm(out[k] - seed[k]) <= 1e-8 * beta * scale, k
+
+
+def test_admm_first_iterates_in_closed_form():
+    """From zero, Algorithm 1's first two iterations and the third f-step
+    written out by hand (dense solves with the explicit D instead of the
+    oracle's inverse and DCT), which fixes the order of the updates:
+      k=1: f = 0, x = M K^T m =: x1, y = z = 0, d_x = beta x1, d_y = d_z = 0;
+      k=2: f = 2 x1 / 3, x = M (K^T m - beta x1 / 3), y = max(0, 2 x1 / 3),
+           z = (lambda D^T D + beta I)^{-1} (2 beta x1 / 3),
+           d_x = beta x1 - beta (f - x), d_y = -beta (f - y), d_z = -beta (f - z);
+      k=3: f = (beta x + d_x + beta y + d_y + beta z + d_z) / (3 beta) of those."""
+    grid = (3, 3, 2)
+    rng = np.random.Generator(np.random.PCG64(21))
+    P, Q = 9, 5
+    K = rng.standard_normal((P, Q))
+    N = int(np.prod(grid))
+    m = rng.standard_normal((N, P))              # signed data: x1 has both signs
+    lam, beta = 0.4, 0.9
+    Mi = np.linalg.solve(K.T @ K + beta * np.eye(Q), np.eye(Q))
+    D = pins.explicit_D(grid).toarray()
+    A = lam * D.T @ D + beta * np.eye(N)
+    x1 = (m @ K) @ Mi.T
+    o1 = oracle.admm_previous(K, m, grid, lam, beta, 1)
+    ref1 = dict(f=0 * x1, x=x1, y=0 * x1, z=0 * x1, dx=beta * x1, dy=0 * x1, dz=0 * x1)
+    for k, v in ref1.items():
+        assert np.allclose(o1[k], v, rtol=0, atol=1e-12), k
+    f2 = 2.0 * x1 / 3.0
+    x2 = (m @ K - beta * x1 / 3.0) @ Mi.T
+    y2 = np.maximum(0.0, f2)
+    z2 = np.linalg.solve(A, beta * f2)
+    ref2 = dict(f=f2, x=x2, y=y2, z=z2, dx=beta * x1 - beta * (f2 - x2), dy=-beta * (f2 - y2),
+                dz=-beta * (f2 - z2))
+    assert (x1 < 0).any() and (x1 > 0).any()
+    o2 = oracle.admm_previous(K, m, grid, lam, beta, 2)
+    for k, v in ref2.items():
+        assert np.allclose(o2[k], v, rtol=0, atol=1e-12), k
+    f3 = (beta * x2 + ref2["dx"] + beta * y2 + ref2["dy"] + beta * z2 + ref2["dz"]) / (3.0 * beta)
+    o3 = oracle.admm_previous(K, m, grid, lam, beta, 3)
+    assert np.allclose(o3["f"], f3, rtol=0, atol=1e-12)
+
+
 # ------------------------------------------------------------- masked voxel sets
 def blob_mask(grid, seed=5, frac=0.6):
     rng = np.random.Generator(np.random.PCG64(seed))
