@@ -158,6 +158,26 @@ ssmap_status ssmap_solve_device(ssmap_ctx *ctx, const void *dM, double lambda,
                                 const ssmap_steps *steps, int iters, void *dF,
                                 void *hip_stream);
 
+/* Allocation-free variant of ssmap_solve_device, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Same arguments, result and ordering on
+ * `hip_stream` as ssmap_solve_device; it calls no hipMalloc, hipFree or other
+ * allocating routine. Every device buffer of the solve (state, r-vectors,
+ * constants, launch tables, monitoring sums) is carved from one static device
+ * array of SSMAP_NOALLOC_MAX_BYTES that each GPU the library runs on holds
+ * until the process ends; the solve initialises everything it reads there.
+ * Limits: EINVAL when the solve needs more than SSMAP_NOALLOC_MAX_BYTES (about
+ * (2 Qp + 3 RP) N words of state, Qp = Q rounded up to 16, RP = the rank
+ * rounded up to 16, plus the dictionary's constants), with SSMAP_KEEP_AUX or
+ * with SSMAP_KERNEL_GEMM; AUTO runs the fused kernel where the rank allows and
+ * the unfused kernels otherwise. All calls on one GPU share its array, which
+ * keeps the last call's contents: calls that overlap on one GPU (other streams,
+ * other threads or contexts) race and must be serialised by the caller. */
+#define SSMAP_NOALLOC_MAX_BYTES (64ull << 20)
+ssmap_status ssmap_solve_device_noalloc(ssmap_ctx *ctx, const void *dM, double lambda,
+                                        const ssmap_steps *steps, int iters, void *dF,
+                                        void *hip_stream);
+
 /* f^iters and d^iters of the last solve run with SSMAP_KEEP_AUX.
  *   f_out, d_out : N*Q float64 voxel-major host buffers; either may be NULL. */
 ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out);

@@ -27,7 +27,8 @@ KERNELS = {"auto": 0, "unfused": 1, "fused": 2, "gemm": 3}
 SSMAP_KEEP_AUX = 1
 MAX_HIST = 512
 
-EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_get_aux",
+EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_device_noalloc",
+           "ssmap_get_aux",
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
            "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_tune_beta",
            "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
@@ -37,6 +38,7 @@ EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_get_aux",
            "ssmap_server_get_stats", "ssmap_server_last_error", "ssmap_server_destroy"]
 SSMAP_AUTOTUNE = 2
 MAX_CLASSES = 16
+NOALLOC_MAX_BYTES = 64 << 20     # SSMAP_NOALLOC_MAX_BYTES
 
 
 class Steps(ctypes.Structure):
@@ -122,6 +124,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_solve.restype = ip
     lib.ssmap_solve_device.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Steps), ip, vp, vp]
     lib.ssmap_solve_device.restype = ip
+    lib.ssmap_solve_device_noalloc.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Steps), ip,
+                                               vp, vp]
+    lib.ssmap_solve_device_noalloc.restype = ip
     lib.ssmap_get_aux.argtypes = [vp, dp, dp]
     lib.ssmap_get_aux.restype = ip
     lib.ssmap_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -227,6 +232,13 @@ def ssmap_solve_device(ctx: int, dM: int, lam: float, steps: Steps, iters: int, 
                                           ctypes.c_void_p(stream)))
 
 
+def ssmap_solve_device_noalloc(ctx: int, dM: int, lam: float, steps: Steps, iters: int, dF: int,
+                               stream: int = 0):
+    _check(ctx, load().ssmap_solve_device_noalloc(ctx, ctypes.c_void_p(dM), float(lam),
+                                                  ctypes.byref(steps), int(iters),
+                                                  ctypes.c_void_p(dF), ctypes.c_void_p(stream)))
+
+
 def ssmap_get_aux(ctx: int, N: int, Q: int):
     f = np.empty((N, Q), dtype=np.float64)
     d = np.empty((N, Q), dtype=np.float64)
@@ -301,8 +313,9 @@ class Mapper:
     def solve(self, M, lam, beta, iters, **kw) -> np.ndarray:
         return ssmap_solve(self.ctx, M, lam, make_steps(beta, **kw), iters, self.N, self.Q)
 
-    def solve_torch(self, M, lam, beta, iters, F=None, stream=None, **kw):
-        """Device solve on torch tensors (float64 for fp64, float32 otherwise)."""
+    def solve_torch(self, M, lam, beta, iters, F=None, stream=None, noalloc=False, **kw):
+        """Device solve on torch tensors (float64 for fp64, float32 otherwise);
+        `noalloc` calls the allocation-free entry point."""
         import torch
         steps = make_steps(beta, **kw)
         dt = torch.float64 if steps.precision == 0 else torch.float32
@@ -315,7 +328,8 @@ class Mapper:
         if F.dtype != dt or not F.is_contiguous() or F.shape != (self.N, self.Q):
             raise ValueError("F must be a contiguous (N, Q) tensor of the I/O type")
         s = stream if stream is not None else torch.cuda.current_stream(M.device)
-        ssmap_solve_device(self.ctx, M.data_ptr(), lam, steps, iters, F.data_ptr(), s.cuda_stream)
+        fn = ssmap_solve_device_noalloc if noalloc else ssmap_solve_device
+        fn(self.ctx, M.data_ptr(), lam, steps, iters, F.data_ptr(), s.cuda_stream)
         return F
 
     def aux(self):

@@ -172,6 +172,15 @@ void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, 
 void launch_gemm_output(const float *z, void *F, bool to_double, int64_t N, int Q, int Qg,
                         hipStream_t s);
 
+// ---- allocation-free solves (kernels_common.hip)
+// Bytes of the static device array that an allocation-free solve takes its
+// device memory from (the SSMAP_NOALLOC_MAX_BYTES of the C ABI).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+// Device address of the current device's copy of that array (hipGetSymbolAddress
+// once per device, then cached); the HIP error of the lookup otherwise.
+hipError_t scratch_device_ptr(void **out);
+
 // Fill a device array of `count` elements of `elem_bytes` (4 or 8) with zero.
 void launch_zero(void *p, size_t count, int elem_bytes, hipStream_t s);
 

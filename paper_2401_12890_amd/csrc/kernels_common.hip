@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 namespace ssmap {
 
@@ -557,6 +558,36 @@ void launch_split_bf16(const float *V, uint16_t *hi, uint16_t *lo, size_t count,
     if (count == 0) return;
     hipLaunchKernelGGL(k_split_bf16, dim3(blocks_for((int64_t)count, 256)), dim3(256), 0, s, V,
                        hi, lo, count);
+}
+
+// ------------------------------------------------------------- allocation-free solves
+// The device memory of an allocation-free solve: one file-scope array, which
+// each device holds (at its own address) from the load of the library until
+// the process ends. Host code never passes the array's name to a kernel: the
+// name is a host-side stand-in, not a device address. The address of this
+// device's copy is looked up once per device and kept.
+namespace {
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_device_ptr(void **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace ssmap

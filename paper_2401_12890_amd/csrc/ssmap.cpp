@@ -127,6 +127,16 @@ struct ssmap_ctx {
     hipEvent_t ev[6] = {};
     double *host_stats = nullptr;         // pinned ST_COUNT doubles
     std::vector<hipEvent_t> gemm_ev;      // GEMM path: 3 timing events per iteration
+    // allocation-free solve in progress: every buffer of the solve is carved
+    // from the device's static scratch array instead of being allocated
+    struct Arena {
+        bool on = false;
+        char *base = nullptr;
+        size_t cap = 0, used = 0;
+        std::map<std::string, std::pair<void *, size_t>> bufs;
+    } arena;
+    void *scratch = nullptr;              // this device's scratch array (NULL: lookup failed)
+    hipError_t scratch_err = hipSuccess;
 };
 
 namespace {
@@ -148,8 +158,27 @@ size_t budget_bytes() {
     return (size_t)v;
 }
 
+size_t align256(size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; }
+
+// An allocation-free solve: the named buffer from the scratch array (the same
+// name gives the same range for the rest of the solve).
+void *carve(ssmap_ctx *c, const std::string &name, size_t bytes) {
+    auto &A = c->arena;
+    auto it = A.bufs.find(name);
+    if (it != A.bufs.end() && it->second.second >= bytes) return it->second.first;
+    const size_t sz = align256(bytes);
+    if (A.used + sz > A.cap)
+        fail(SSMAP_EINVAL, "allocation-free solve needs more than the " + std::to_string(A.cap) +
+                               " bytes of the scratch array (" + name + ")");
+    void *p = A.base + A.used;
+    A.used += sz;
+    A.bufs[name] = {p, bytes};
+    return p;
+}
+
 // Make sure the named buffer holds at least `bytes`; returns the pointer.
 void *ensure(ssmap_ctx *c, const std::string &name, size_t bytes) {
+    if (c->arena.on) return carve(c, name, bytes);
     bytes = std::max<size_t>(bytes, 256);
     auto it = c->bufs.find(name);
     if (it != c->bufs.end() && it->second.second >= bytes) return it->second.first;
@@ -191,8 +220,19 @@ const uint8_t *mask_dev(ssmap_ctx *c) {
     return it == c->bufs.end() ? nullptr : (const uint8_t *)it->second.first;
 }
 
-// Plan check before any allocation of a solve: fail early with ENOMEM.
+// Plan check before any allocation of a solve: fail early with ENOMEM (or, for an
+// allocation-free solve, EINVAL when the scratch array is too small).
 void plan_check(ssmap_ctx *c, const std::vector<std::pair<std::string, size_t>> &need) {
+    if (c->arena.on) {
+        size_t total = c->arena.used;
+        for (auto &kv : need)
+            if (!c->arena.bufs.count(kv.first)) total += align256(kv.second);
+        if (total > c->arena.cap)
+            fail(SSMAP_EINVAL, "allocation-free solve needs " + std::to_string(total) +
+                                   " device bytes, above the " + std::to_string(c->arena.cap) +
+                                   "-byte scratch array");
+        return;
+    }
     size_t extra = 0;
     for (auto &kv : need) {
         auto it = c->bufs.find(kv.first);
@@ -353,7 +393,15 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         need.push_back({"auxA", zbytes});
         need.push_back({"auxB", zbytes});
     }
-    if (pl.fused) need.push_back({"Vop", (size_t)c->nchunk * 8 * RP * 64 * 2});
+    if (pl.fused) {
+        need.push_back({"Vop", (size_t)c->nchunk * 8 * RP * 64 * 2});
+        // launch plan: two descriptors and at most this many bricks
+        const FusedShape sh = default_shape(pl.mode, c->g);
+        const size_t nb = (size_t)((c->g.nx + 15) / 16) * ((c->g.ny + sh.ty - 1) / sh.ty) *
+                          ((c->g.nz + sh.tz - 1) / sh.tz);
+        need.push_back({"jobs", 2 * sizeof(IterArgs)});
+        need.push_back({"tiles", nb * sizeof(TileRef)});
+    }
     if (pl.mode == MODE_BF16X3) {
         need.push_back({"Vhi", (size_t)Qp * RP * 2});
         need.push_back({"Vlo", (size_t)Qp * RP * 2});
@@ -709,7 +757,7 @@ void finish(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
     HIPC(c, hipStreamSynchronize(s));
     ssmap_stats &S = c->stats;
     S.iters = iters;
-    S.device_bytes = (double)c->held;
+    S.device_bytes = (double)(c->arena.on ? c->arena.used : c->held);
     if (P.aux) {
         c->aux_valid = true;
         c->aux_mode = P.pl.mode;
@@ -1055,6 +1103,12 @@ ssmap_status ssmap_create(const double *K, int P, int Q, const int64_t grid[3], 
             fail(SSMAP_ENODEV, std::string("device is ") + prop.gcnArchName + ", need gfx950");
         thin_svd(K, P, Q, c->U, c->s, c->V);
         c->dtd_norm = dtd_norm_closed(c->g);
+        // the device's scratch array for allocation-free solves (looked up once per device)
+        c->scratch_err = scratch_device_ptr(&c->scratch);
+        if (c->scratch_err != hipSuccess) {
+            (void)hipGetLastError();
+            c->scratch = nullptr;
+        }
         for (auto &e : c->ev) HIPC(c, hipEventCreate(&e));
         HIPC(c, hipHostMalloc((void **)&c->host_stats, ST_COUNT * sizeof(double)));
         auto t1 = std::chrono::steady_clock::now();
@@ -1077,6 +1131,49 @@ ssmap_status ssmap_solve_device(ssmap_ctx *ctx, const void *dM, double lambda,
         HIPC(ctx, hipSetDevice(ctx->device));
         const double setup = ctx->stats.setup_ms;
         solve_impl(ctx, dM, lambda, steps, iters, dF, (hipStream_t)hip_stream);
+        ctx->stats.setup_ms = setup;
+    });
+}
+
+ssmap_status ssmap_solve_device_noalloc(ssmap_ctx *ctx, const void *dM, double lambda,
+                                        const ssmap_steps *steps, int iters, void *dF,
+                                        void *hip_stream) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        if (!dM || !dF) fail(SSMAP_EINVAL, "NULL buffer");
+        validate_steps(ctx, lambda, steps, iters);
+        if (steps->flags & SSMAP_KEEP_AUX)
+            fail(SSMAP_EINVAL, "an allocation-free solve keeps no aux output (SSMAP_KEEP_AUX)");
+        if (steps->kernel == SSMAP_KERNEL_GEMM)
+            fail(SSMAP_EINVAL, "an allocation-free solve runs the fused or unfused kernels");
+        HIPC(ctx, hipSetDevice(ctx->device));
+        if (!ctx->scratch)
+            fail(SSMAP_EDEVICE, std::string("scratch array lookup failed: ") +
+                                    hipGetErrorString(ctx->scratch_err));
+        // AUTO: the fused kernel where it exists, else the unfused one (the GEMM
+        // path needs allocations of its own layouts)
+        ssmap_steps st = *steps;
+        if (st.kernel == SSMAP_KERNEL_AUTO) {
+            const int r = rank_rule(ctx->s, st.rank);
+            st.kernel = fused_supported(st.precision, (r + 15) / 16 * 16, ctx->g.N)
+                            ? SSMAP_KERNEL_FUSED : SSMAP_KERNEL_UNFUSED;
+        }
+        struct On {
+            ssmap_ctx *c;
+            explicit On(ssmap_ctx *c_) : c(c_) {
+                c->arena.on = true;
+                c->arena.base = (char *)c->scratch;
+                c->arena.cap = kScratchBytes;
+                c->arena.used = 0;
+                c->arena.bufs.clear();
+            }
+            ~On() {
+                c->arena.on = false;
+                c->arena.bufs.clear();
+            }
+        } on(ctx);
+        const double setup = ctx->stats.setup_ms;
+        solve_impl(ctx, dM, lambda, &st, iters, dF, (hipStream_t)hip_stream);
         ctx->stats.setup_ms = setup;
     });
 }
