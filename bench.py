@@ -464,6 +464,8 @@ def main():
                     help="solve the workload's recipe on another grid (nx ny nz)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-monitor", action="store_true",
+                    help="skip the monitored solve that measures the monitoring cost")
     ap.add_argument("--jobs", type=int, default=None, help="served stream: number of jobs")
     ap.add_argument("--rate", type=float, default=20.0, help="served stream: arrivals per s")
     ap.add_argument("--streams", type=int, default=4, help="served stream: HIP streams")
@@ -558,6 +560,19 @@ def main():
             roofline["note"] = ("the state arrays fit in the caches: the run is latency-bound and "
                                 "the fraction of the HBM peak does not bound it")
 
+    # monitoring cost: one more solve with the float64 reductions every 10 iterations
+    monitor = None
+    if not args.no_monitor:
+        mp.solve_torch(M, prob.lam, prob.beta, iters, F=F, stream=stream, check_every=10, **kw)
+        torch.cuda.synchronize()
+        sm = mp.stats()
+        plain = sum(loop_ms) / len(loop_ms)
+        monitor = {"check_every": 10, "checks": len(sm["hist_iter"]),
+                   "loop_ms": sm["iterate_ms"], "plain_loop_ms": plain,
+                   "overhead": sm["iterate_ms"] / plain - 1.0,
+                   "objective_last": sm["hist_objective"][-1] if sm["hist_objective"] else None}
+        log(f"monitored loop {sm['iterate_ms']:.2f} ms against {plain:.2f} ms")
+
     parity = None
     if not args.no_parity and rank == 0:
         log("sampled parity vs stored oracle values")
@@ -582,7 +597,7 @@ def main():
         "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
         "loop_voxel_iter_per_s": prob.N * iters / (sum(loop_ms) / len(loop_ms) / 1e3),
         "setup_ms": setup_ms, "project_ms": st["project_ms"], "output_ms": st["output_ms"],
-        "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "monitor": monitor,
     }
     print(json.dumps(out), flush=True)
 

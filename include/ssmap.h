@@ -67,19 +67,24 @@ typedef enum {
 /* Kernel family for the iteration (both compute the same iterates). */
 typedef enum {
     SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows (r <= 32); else
-                               the GEMM path for float32 / bf16x3 without monitoring
-                               or aux output; else unfused                        */
+                               the GEMM path for float32 / bf16x3 without aux output
+                               or primal residual; else unfused                   */
     SSMAP_KERNEL_UNFUSED = 1,
     SSMAP_KERNEL_FUSED = 2,
     SSMAP_KERNEL_GEMM = 3   /* any rank, float32 / bf16x3: the two contractions as
                                MFMA-tiled GEMMs over all voxels (compute bound at
                                high rank), the stencil / z-update and r-vector
-                               recursion as the GEMMs' epilogues; check_every = 0,
-                               no SSMAP_KEEP_AUX                                   */
+                               recursion as the GEMMs' epilogues; monitoring
+                               allowed, no SSMAP_KEEP_AUX or SSMAP_MONITOR_PRIMAL */
 } ssmap_kernel;
 
 enum {
-    SSMAP_KEEP_AUX = 1      /* keep f^K and d^K of the solve for ssmap_get_aux    */
+    SSMAP_KEEP_AUX = 1,     /* keep f^K and d^K of the solve for ssmap_get_aux    */
+    SSMAP_MONITOR_PRIMAL = 4 /* with check_every > 0: also the primal residual
+                               ||z^k - f^k|| at every check (and DFCS of f^k when a
+                               reference is set); f^k needs d^{k-1}, so the two
+                               iterations before each check are bracketed by two
+                               extra passes each (fused and unfused kernels only) */
 };
 
 /* LADMM parameters (Algorithm 2 inputs, Sec. III-E; selection rules, Sec. III-F). */
@@ -89,9 +94,11 @@ typedef struct {
     int rank;               /* 0: smallest r with ||K - K_r||_F < 5e-5 ||K||_F (Sec.
                                III-F); -1: min(P, Q), the unapproximated K; > 0: that r */
     int precision;          /* ssmap_precision                                           */
-    int check_every;        /* 0: no monitoring; k > 0: objective/residual reductions
-                               every k iterations and after the last one                 */
-    int flags;              /* SSMAP_KEEP_AUX                                            */
+    int check_every;        /* 0: no monitoring; k > 0: objective, residuals and DFCS
+                               (float64 reductions) every k iterations and after the
+                               last one, into the stats history                          */
+    int flags;              /* SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL (| SSMAP_AUTOTUNE for
+                               batches)                                                  */
     int kernel;             /* ssmap_kernel                                              */
     int reserved;
     double stop_tol;        /* 0: run all iters. > 0 (needs check_every > 0, no
@@ -126,6 +133,11 @@ typedef struct {
     double hist_objective[SSMAP_MAX_HIST];  /* 1/2||m - K_r z||^2 + lambda R(z)    */
     double hist_dual[SSMAP_MAX_HIST];       /* beta ||z^k - z^{k-1}||               */
     double hist_znorm[SSMAP_MAX_HIST];      /* ||z^k||                              */
+    double hist_primal[SSMAP_MAX_HIST];     /* ||z^k - f^k|| (SSMAP_MONITOR_PRIMAL), else -1 */
+    double hist_dfcs[SSMAP_MAX_HIST];       /* ||z^k - f*|| / ||f*|| (Eq. DFCS) with a
+                                               reference set, else -1                */
+    double hist_dfcs_f[SSMAP_MAX_HIST];     /* ||f^k - f*|| / ||f*|| (reference and
+                                               SSMAP_MONITOR_PRIMAL), else -1        */
 } ssmap_stats;
 
 /* Factor the dictionary and prepare a context for a fixed grid.
@@ -191,6 +203,13 @@ ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out);
  * Lanczos) enters the xi_p rule. Bricks with no inside voxel are not
  * launched. mask = NULL restores the whole box. */
 ssmap_status ssmap_set_mask(ssmap_ctx *ctx, const uint8_t *mask);
+
+/* Reference map for the distance from the converged solution (Eq. DFCS,
+ * Sec. IV: ||f^k - f*|| / ||f*||, f* the converged map of the unapproximated
+ * K). f_star: N*Q float64 voxel-major (as F_out), finite, not all zero;
+ * copied to the device. Every monitored solve on ctx then reports DFCS of z^k
+ * (and of f^k with SSMAP_MONITOR_PRIMAL). f_star = NULL removes it. */
+ssmap_status ssmap_set_reference(ssmap_ctx *ctx, const double *f_star);
 
 /* Penalty selection heuristic (Sec. III-F): solve the centre patch of the
  * grid (3 voxels per axis longer than 1, fewer on shorter axes; the box

@@ -196,7 +196,9 @@ def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
 
     Returns a dict with z, f, d (N, Q), the rank r, xi and, when
     track_every > 0, a history of (k, objective(z^k), DFCS(z^k)) where DFCS
-    follows Eq. (DFCS) against f_star when one is given.
+    follows Eq. (DFCS) against f_star when one is given, and beside it
+    hist_f of (k, ||z^k - f^k||, DFCS(f^k)) -- the primal residual of the
+    splitting f = z and the distance of f^k itself (f^0 = 0).
 
     mask (N booleans, optional): estimate the inside voxels only, on the graph
     of inside face neighbours (see graph_edges); outside voxels stay 0 and
@@ -226,11 +228,12 @@ def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
     d = np.zeros((N, Q)) if d0 is None else np.array(d0, dtype=np.float64)
     f = np.zeros((N, Q))
     K_r = (U_r * s_r) @ V_r.T
-    hist = []
+    hist, hist_f = [], []
     run = iters
     for k in range(iters):
         if track_every and k % track_every == 0:
             hist.append(_track(k, K_r, m, z, grid, lam, f_star))
+            hist_f.append(_track_f(k, z, f, f_star))
         c = g + beta * z - d
         f = f_step(c, V_r, s_w, beta)
         z_new = z_step(z, f, d, lam, xi, beta, grid)
@@ -242,7 +245,9 @@ def ladmm(K, m, grid, lam, beta, iters, rank=0, xi=None, z0=None, d0=None,
             break
     if track_every:
         hist.append(_track(run, K_r, m, z, grid, lam, f_star))
-    return dict(z=z, f=f, d=d, rank=r, xi=float(xi), sigma=s, hist=hist, K_r=K_r, iters=run)
+        hist_f.append(_track_f(run, z, f, f_star))
+    return dict(z=z, f=f, d=d, rank=r, xi=float(xi), sigma=s, hist=hist, hist_f=hist_f, K_r=K_r,
+                iters=run)
 
 
 def _converged(z, z_new, k, stop_tol, check_every):
@@ -345,6 +350,14 @@ def beta_heuristic(K, m, grid, lam, iters, betas, rank=0, size=3):
         J.append(objective(out["K_r"], mp, out["z"], pgrid, lam))
     J = np.asarray(J)
     return float(betas[int(np.argmin(J))]), J
+
+
+def _track_f(k, z, f, f_star):
+    """Primal residual ||z^k - f^k|| of the constraint f = z, and DFCS(f^k)."""
+    dfcs = None
+    if f_star is not None:
+        dfcs = float(np.linalg.norm(f - f_star) / np.linalg.norm(f_star))
+    return (k, float(np.linalg.norm(z - f)), dfcs)
 
 
 def _track(k, K_r, m, z, grid, lam, f_star):

@@ -25,12 +25,14 @@ STATUS_NAMES = {0: "SSMAP_OK", -1: "SSMAP_EINVAL", -2: "SSMAP_ENOMEM", -3: "SSMA
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KERNELS = {"auto": 0, "unfused": 1, "fused": 2, "gemm": 3}
 SSMAP_KEEP_AUX = 1
+SSMAP_MONITOR_PRIMAL = 4
 MAX_HIST = 512
 
 EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_device_noalloc",
            "ssmap_get_aux",
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
-           "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_tune_beta",
+           "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_set_reference",
+           "ssmap_tune_beta",
            "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
            "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
@@ -59,7 +61,10 @@ class Stats(ctypes.Structure):
                 ("hist_iter", ctypes.c_int * MAX_HIST),
                 ("hist_objective", ctypes.c_double * MAX_HIST),
                 ("hist_dual", ctypes.c_double * MAX_HIST),
-                ("hist_znorm", ctypes.c_double * MAX_HIST)]
+                ("hist_znorm", ctypes.c_double * MAX_HIST),
+                ("hist_primal", ctypes.c_double * MAX_HIST),
+                ("hist_dfcs", ctypes.c_double * MAX_HIST),
+                ("hist_dfcs_f", ctypes.c_double * MAX_HIST)]
 
 
 class BatchStats(ctypes.Structure):
@@ -139,6 +144,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_destroy.restype = None
     lib.ssmap_set_mask.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
     lib.ssmap_set_mask.restype = ip
+    lib.ssmap_set_reference.argtypes = [vp, dp]
+    lib.ssmap_set_reference.restype = ip
     lib.ssmap_tune_beta.argtypes = [vp, dp, ctypes.c_double, ctypes.POINTER(Steps), ip, dp, ip,
                                     dp, dp]
     lib.ssmap_tune_beta.restype = ip
@@ -189,8 +196,9 @@ def _dptr(a: np.ndarray):
 
 
 def make_steps(beta, xi_p=0.0, rank=0, precision="fp64", check_every=0, keep_aux=False,
-               kernel="auto", autotune=False, stop_tol=0.0) -> Steps:
-    flags = (SSMAP_KEEP_AUX if keep_aux else 0) | (SSMAP_AUTOTUNE if autotune else 0)
+               kernel="auto", autotune=False, stop_tol=0.0, primal=False) -> Steps:
+    flags = (SSMAP_KEEP_AUX if keep_aux else 0) | (SSMAP_AUTOTUNE if autotune else 0) | \
+        (SSMAP_MONITOR_PRIMAL if primal else 0)
     return Steps(beta=float(beta), xi_p=float(xi_p), rank=int(rank),
                  precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                  check_every=int(check_every), flags=flags,
@@ -255,7 +263,9 @@ def ssmap_get_stats(ctx: int) -> dict:
                 sigma_max=s.sigma_max, setup_ms=s.setup_ms, project_ms=s.project_ms,
                 iterate_ms=s.iterate_ms, output_ms=s.output_ms, device_bytes=s.device_bytes,
                 gemm_ms=s.gemm_ms, gemm_flops=s.gemm_flops, hist_iter=list(s.hist_iter[:n]), hist_objective=list(s.hist_objective[:n]),
-                hist_dual=list(s.hist_dual[:n]), hist_znorm=list(s.hist_znorm[:n]))
+                hist_dual=list(s.hist_dual[:n]), hist_znorm=list(s.hist_znorm[:n]),
+                hist_primal=list(s.hist_primal[:n]), hist_dfcs=list(s.hist_dfcs[:n]),
+                hist_dfcs_f=list(s.hist_dfcs_f[:n]))
 
 
 def ssmap_get_singular_values(ctx: int) -> np.ndarray:
@@ -282,6 +292,15 @@ def ssmap_set_mask(ctx: int, mask) -> None:
         return
     mk = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
     _check(ctx, load().ssmap_set_mask(ctx, mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+
+def ssmap_set_reference(ctx: int, f_star) -> None:
+    """f_star: (N, Q) float64 reference map for DFCS, or None to remove it."""
+    if f_star is None:
+        _check(ctx, load().ssmap_set_reference(ctx, None))
+        return
+    f = np.ascontiguousarray(f_star, dtype=np.float64)
+    _check(ctx, load().ssmap_set_reference(ctx, _dptr(f)))
 
 
 def ssmap_tune_beta(ctx: int, M: np.ndarray, lam: float, steps: Steps, iters: int, betas):
@@ -343,6 +362,11 @@ class Mapper:
 
     def set_mask(self, mask) -> None:
         ssmap_set_mask(self.ctx, mask)
+
+    def set_reference(self, f_star) -> None:
+        if f_star is not None and np.shape(f_star) != (self.N, self.Q):
+            raise ValueError("f_star must be (N, Q)")
+        ssmap_set_reference(self.ctx, f_star)
 
     def tune_beta(self, M, lam, iters, betas, **kw):
         """Patch heuristic for beta; returns (best beta, objectives)."""

@@ -16,8 +16,11 @@ enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2 };
 // multiple of QC with rows of V equal to zero, which keeps padded z at 0.
 constexpr int QC = 16;
 
-// Monitoring reduction slots.
-enum { ST_DATA = 0, ST_REG, ST_ZNORM, ST_DZ, ST_NONFINITE, ST_COUNT = 8 };
+// Monitoring reduction slots (float64 sums): data term ||m - K_r z||^2, forward-edge
+// regulariser sum ||z_n - z_m||^2, ||z||^2, ||z - zprev||^2, non-finite count,
+// ||z - f*||^2, ||f*||^2, ||z - f||^2, ||f - f*||^2.
+enum { ST_DATA = 0, ST_REG, ST_ZNORM, ST_DZ, ST_NONFINITE, ST_DFCS, ST_FSTAR, ST_PRIMAL,
+       ST_DFCS_F, ST_COUNT = 12 };
 
 void thin_svd(const double *K, int P, int Q, std::vector<double> &U,
               std::vector<double> &s, std::vector<double> &V);
@@ -110,10 +113,20 @@ void launch_project(int mode, const void *M, int P, const double *Ur, const doub
 
 // Monitoring: per-block float64 partial sums of the objective terms, then a
 // fixed-order final reduction into out[ST_COUNT].
-void launch_monitor(int mode, const void *z, const void *zprev, const double *V64,
-                    const double *sig, const double *t, const double *mperp2, int r,
-                    int RP, int nchunk, Grid g, const uint8_t *code, double *partial,
-                    int nblocks_cap, double *out, hipStream_t s);
+struct MonArgs {
+    const void *z;            // the iterate (state type; chunked, or voxel-major when ld > 0)
+    const void *zprev;        // the iterate before it (same layout), or NULL
+    const void *f;            // f of the same iteration (chunked state layout), or NULL
+    const double *fstar;      // reference map for DFCS (N x Q float64, voxel-major), or NULL
+    const double *V64;        // V_r in float64, (16 nchunk) x RP, zero padded
+    const double *sig, *t, *mperp2;   // singular values (RP), U_r^T m (r x N), ||m_perp||^2 (N)
+    int r, RP, nchunk, Q;
+    int64_t ld;               // voxel-major row length (0: chunked layout)
+    Grid g;
+    const uint8_t *code;      // mask codes or NULL
+};
+constexpr int kMonitorBlocks = 4096;  // partial sums: kMonitorBlocks x ST_COUNT doubles
+void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hipStream_t s);
 int monitor_blocks(int64_t N);
 
 // Chunked state -> voxel-major output (element type of the mode's I/O, or

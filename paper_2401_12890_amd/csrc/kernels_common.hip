@@ -276,108 +276,175 @@ k_aux_post(T *__restrict__ t, const T *__restrict__ znew, T beta, size_t count) 
 }
 
 // ------------------------------------------------------------- monitoring
-template <int MODE>
-__global__ void __launch_bounds__(256)
-k_monitor(const typename StateT<MODE>::T *__restrict__ z,
-          const typename StateT<MODE>::T *__restrict__ zprev, const double *__restrict__ V64,
-          const double *__restrict__ sig, const double *__restrict__ t,
-          const double *__restrict__ mperp2, int r, int RP, int nchunk, Grid g,
-          const uint8_t *__restrict__ code, double *__restrict__ partial) {
-    using T = typename StateT<MODE>::T;
-    const int64_t N = g.N;
-    double acc[5] = {0, 0, 0, 0, 0};
-    // an edge counts when both voxels are inside (every edge without a mask)
-    auto in = [&](int64_t v) { return !code || (code[v] & 0x80u) != 0; };
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        // data term: ||m_perp||^2 + sum_i (t_i - sigma_i y_i)^2 with y = V_r^T z in float64
-        double data = mperp2[n];
-        for (int i0 = 0; i0 < r; i0 += 8) {
-            double yv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int c = 0; c < nchunk; ++c) {
-                const T *zp = z + ((int64_t)c * N + n) * QC;
-                for (int qq = 0; qq < QC; ++qq) {
-                    const double zv = (double)zp[qq];
-                    const double *vrow = V64 + (size_t)(c * QC + qq) * RP + i0;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        if (i0 + j < RP) yv[j] += vrow[j] * zv;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = i0 + j;
-                if (i < r) {
-                    const double e = t[(size_t)i * N + n] - sig[i] * yv[j];
-                    data += e * e;
-                }
-            }
-        }
-        // regulariser: each forward edge once; norms; non-finite count
-        const int64_t x = n % g.nx, yy = (n / g.nx) % g.ny, zz = n / (g.nx * g.ny);
-        const bool ein = in(n);
-        const bool ex = ein && x < g.nx - 1 && in(n + 1);
-        const bool ey = ein && yy < g.ny - 1 && in(n + g.nx);
-        const bool ez = ein && zz < g.nz - 1 && in(n + g.nx * g.ny);
-        double reg = 0.0, zsq = 0.0, dsq = 0.0, bad = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
-            const int64_t base = ((int64_t)c * N + n) * QC;
-            for (int qq = 0; qq < QC; ++qq) {
-                const double zc = (double)z[base + qq];
-                if (!__builtin_isfinite(zc)) bad += 1.0;
-                zsq += zc * zc;
-                if (zprev) {
-                    const double dz = zc - (double)zprev[base + qq];
-                    dsq += dz * dz;
-                }
-                if (ex) {
-                    const double dd = zc - (double)z[base + qq + QC];
-                    reg += dd * dd;
-                }
-                if (ey) {
-                    const double dd = zc - (double)z[base + qq + g.nx * QC];
-                    reg += dd * dd;
-                }
-                if (ez) {
-                    const double dd = zc - (double)z[base + qq + g.nx * g.ny * QC];
-                    reg += dd * dd;
-                }
-            }
-        }
-        acc[0] += data;
-        acc[1] += reg;
-        acc[2] += zsq;
-        acc[3] += dsq;
-        acc[4] += bad;
+// Objective of Eq. (spat) with R of Eq. (l2), residuals and DFCS (Eq. DFCS) of
+// an iterate, all summed in float64. A wave takes 16 consecutive voxels at a
+// time; lane l holds voxel l % 16 and the four nodes 4 (l / 16) .. + 3 of each
+// 16-node chunk. The data term uses
+//     ||m_n - K_r z_n||^2 = ||m_n||^2 - ||t_n||^2 + sum_i (t_i - sigma_i y_i)^2,
+// t = U_r^T m_n, y = V_r^T z_n, with y contracted on the matrix cores in
+// float64 (v_mfma_f64_16x16x4: M = 16 ranks, N = 16 voxels, K = 4 nodes; the
+// lane's own z values are the B operand, K-row l / 16 of step s being node
+// 4 (l / 16) + s; output rank 16 rb + l / 16 + 4 i in lane l). The regulariser
+// takes every forward face edge once (both ends inside a mask). Sums are
+// reduced across the wave by shuffles, across the four waves through LDS,
+// then in a fixed order over the blocks, so every result is bitwise repeatable.
+typedef double v4d_m __attribute__((ext_vector_type(4)));
+
+template <typename T, bool VM>
+__device__ __forceinline__ void load4(const T *base, int64_t off, bool ok, T out[4]) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = ok ? *(const float4 *)(base + off) : float4{0.f, 0.f, 0.f, 0.f};
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+        const double2 a = ok ? *(const double2 *)(base + off) : double2{0.0, 0.0};
+        const double2 b = ok ? *(const double2 *)(base + off + 2) : double2{0.0, 0.0};
+        out[0] = a.x; out[1] = a.y; out[2] = b.x; out[3] = b.y;
     }
-    __shared__ double red[5][256];
-    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < ST_COUNT; ++k)
-            partial[(size_t)blockIdx.x * ST_COUNT + k] = k < 5 ? red[k][0] : 0.0;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+constexpr int MON_RG = 4;                // 16-rank blocks per pass over z
+
+template <typename T, bool VM>
+__global__ void __launch_bounds__(256)
+k_monitor(MonArgs a, double *__restrict__ partial) {
+    const T *z = (const T *)a.z;
+    const T *zp = (const T *)a.zprev;
+    const T *fz = (const T *)a.f;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, i4 = lane >> 4;
+    const int64_t N = a.g.N, nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int RB = a.RP / 16;
+    // element (q, n): chunked z[((q / 16) N + n) 16 + q % 16], or voxel-major z[n ld + q]
+    auto at = [&](int c, int64_t n) -> int64_t {
+        return VM ? n * a.ld + 16 * c + 4 * i4 : ((int64_t)c * N + n) * QC + 4 * i4;
+    };
+    auto in = [&](int64_t v) { return !a.code || (a.code[v] & 0x80u) != 0; };
+    double acc[ST_COUNT];
+#pragma unroll
+    for (int k = 0; k < ST_COUNT; ++k) acc[k] = 0.0;
+    const int64_t ntile = (N + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+        const int64_t n = tile * 16 + j;
+        const bool valid = n < N;
+        const int64_t x = n % nx, yy = (n / nx) % ny, zz = n / (nx * ny);
+        const bool ein = valid && in(n);
+        const bool ex = ein && x + 1 < nx && in(n + 1);
+        const bool ey = ein && yy + 1 < ny && in(n + nx);
+        const bool ez = ein && zz + 1 < nz && in(n + nx * ny);
+        for (int rg = 0; rg < RB || rg == 0; rg += MON_RG) {
+            v4d_m yacc[MON_RG];
+#pragma unroll
+            for (int g = 0; g < MON_RG; ++g) yacc[g] = v4d_m{0.0, 0.0, 0.0, 0.0};
+            for (int c = 0; c < a.nchunk; ++c) {
+                T zv[4];
+                load4<T, VM>(z, at(c, n), valid, zv);
+                if (rg == 0) {
+                    T nb[3][4], pv[4], fv[4];
+                    load4<T, VM>(z, at(c, n + 1), ex, nb[0]);
+                    load4<T, VM>(z, at(c, n + nx), ey, nb[1]);
+                    load4<T, VM>(z, at(c, n + nx * ny), ez, nb[2]);
+                    if (zp) load4<T, VM>(zp, at(c, n), valid, pv);
+                    if (fz) load4<T, VM>(fz, at(c, n), valid, fv);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double v = (double)zv[s];
+                        if (!__builtin_isfinite(v)) acc[ST_NONFINITE] += 1.0;
+                        acc[ST_ZNORM] += v * v;
+#pragma unroll
+                        for (int e = 0; e < 3; ++e) {
+                            const double dd = v - (double)nb[e][s];
+                            acc[ST_REG] += (e == 0 ? ex : e == 1 ? ey : ez) ? dd * dd : 0.0;
+                        }
+                        if (zp) {
+                            const double dd = v - (double)pv[s];
+                            acc[ST_DZ] += dd * dd;
+                        }
+                        const int q = 16 * c + 4 * i4 + s;
+                        const bool has_ref = a.fstar && valid && q < a.Q;
+                        const double fs = has_ref ? a.fstar[n * a.Q + q] : 0.0;
+                        if (a.fstar) {
+                            const double dd = has_ref ? v - fs : 0.0;
+                            acc[ST_DFCS] += dd * dd;
+                            acc[ST_FSTAR] += fs * fs;
+                        }
+                        if (fz) {
+                            const double f = (double)fv[s];
+                            const double dd = v - f;
+                            acc[ST_PRIMAL] += dd * dd;
+                            if (a.fstar) {
+                                const double df = has_ref ? f - fs : 0.0;
+                                acc[ST_DFCS_F] += df * df;
+                            }
+                        }
+                    }
+                }
+                // y of ranks 16 (rg + g) .. + 15 over this chunk's 16 nodes
+#pragma unroll
+                for (int g = 0; g < MON_RG; ++g) {
+                    const int rb = rg + g;
+                    if (rb < RB) {
+                        const double *Vc = a.V64 + (size_t)(16 * c + 4 * i4) * a.RP + 16 * rb + j;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            yacc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vc[(size_t)s * a.RP],
+                                                                          (double)zv[s], yacc[g], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < MON_RG; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int rr = 16 * (rg + g) + i4 + 4 * i;
+                    if (valid && rr < a.r) {
+                        const double e = a.t[(size_t)rr * N + n] - a.sig[rr] * yacc[g][i];
+                        acc[ST_DATA] += e * e;
+                    }
+                }
+        }
+        if (valid && i4 == 0) acc[ST_DATA] += a.mperp2[n];
+    }
+    __shared__ double red[4][ST_COUNT];
+#pragma unroll
+    for (int k = 0; k < ST_COUNT; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_COUNT) {
+        const int k = threadIdx.x;
+        partial[(size_t)blockIdx.x * ST_COUNT + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+// Fixed-order sum of the per-block partials: thread t adds blocks t, t + 256, ...
+// in turn; then shuffles within each wave and the four wave sums in order.
 __global__ void __launch_bounds__(256)
 k_reduce_partials(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
-    __shared__ double red[ST_COUNT][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double red[4][ST_COUNT];
     double acc[ST_COUNT];
+#pragma unroll
     for (int k = 0; k < ST_COUNT; ++k) acc[k] = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
         for (int k = 0; k < ST_COUNT; ++k) acc[k] += partial[(size_t)b * ST_COUNT + k];
-    for (int k = 0; k < ST_COUNT; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < ST_COUNT; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ST_COUNT; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
     }
-    if (threadIdx.x < ST_COUNT) out[threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < ST_COUNT) {
+        const int k = threadIdx.x;
+        out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
 }
 
 // ------------------------------------------------------------- output
@@ -492,22 +559,20 @@ void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t co
 }
 
 int monitor_blocks(int64_t N) {
-    const int64_t b = (N + 255) / 256;
-    return (int)(b < 2048 ? b : 2048);
+    const int64_t b = ((N + 15) / 16 + 3) / 4;     // four 16-voxel tiles per block
+    return (int)(b < kMonitorBlocks ? (b > 0 ? b : 1) : kMonitorBlocks);
 }
 
-void launch_monitor(int mode, const void *z, const void *zprev, const double *V64,
-                    const double *sig, const double *t, const double *mperp2, int r, int RP,
-                    int nchunk, Grid g, const uint8_t *code, double *partial, int nblocks_cap,
-                    double *out, hipStream_t s) {
-    int nb = monitor_blocks(g.N);
-    if (nb > nblocks_cap) nb = nblocks_cap;
-    if (mode == MODE_FP64)
-        hipLaunchKernelGGL(k_monitor<MODE_FP64>, dim3(nb), dim3(256), 0, s, (const double *)z,
-                           (const double *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, code, partial);
-    else
-        hipLaunchKernelGGL(k_monitor<MODE_FP32>, dim3(nb), dim3(256), 0, s, (const float *)z,
-                           (const float *)zprev, V64, sig, t, mperp2, r, RP, nchunk, g, code, partial);
+void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hipStream_t s) {
+    const int nb = monitor_blocks(a.g.N);
+    const bool vm = a.ld > 0;
+    if (mode == MODE_FP64) {
+        if (vm) hipLaunchKernelGGL((k_monitor<double, true>), dim3(nb), dim3(256), 0, s, a, partial);
+        else hipLaunchKernelGGL((k_monitor<double, false>), dim3(nb), dim3(256), 0, s, a, partial);
+    } else {
+        if (vm) hipLaunchKernelGGL((k_monitor<float, true>), dim3(nb), dim3(256), 0, s, a, partial);
+        else hipLaunchKernelGGL((k_monitor<float, false>), dim3(nb), dim3(256), 0, s, a, partial);
+    }
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
 }
 

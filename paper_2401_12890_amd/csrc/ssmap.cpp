@@ -136,6 +136,7 @@ struct ssmap_ctx {
         std::map<std::string, std::pair<void *, size_t>> bufs;
     } arena;
     void *scratch = nullptr;              // this device's scratch array (NULL: lookup failed)
+    bool has_ref = false;                 // a reference map f* for DFCS is on the device ("fstar")
     hipError_t scratch_err = hipSuccess;
 };
 
@@ -220,6 +221,13 @@ const uint8_t *mask_dev(ssmap_ctx *c) {
     return it == c->bufs.end() ? nullptr : (const uint8_t *)it->second.first;
 }
 
+// Device copy of the reference map f* (NULL when none is set).
+const double *ref_dev(ssmap_ctx *c) {
+    if (!c->has_ref) return nullptr;
+    auto it = c->bufs.find("fstar");
+    return it == c->bufs.end() ? nullptr : (const double *)it->second.first;
+}
+
 // Plan check before any allocation of a solve: fail early with ENOMEM (or, for an
 // allocation-free solve, EINVAL when the scratch array is too small).
 void plan_check(ssmap_ctx *c, const std::vector<std::pair<std::string, size_t>> &need) {
@@ -292,11 +300,11 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
     if (st->kernel == SSMAP_KERNEL_FUSED && !can_fuse)
         fail(SSMAP_EINVAL, "no fused kernel for this precision and rank");
     p.fused = st->kernel == SSMAP_KERNEL_FUSED || (st->kernel == SSMAP_KERNEL_AUTO && can_fuse);
-    // GEMM path: float32 / bf16x3 without monitoring or aux output; AUTO takes
-    // it where no fused kernel exists
-    const bool gemm_ok = p.mode != MODE_FP64 && st->check_every == 0 && !(st->flags & SSMAP_KEEP_AUX);
+    // GEMM path: float32 / bf16x3 without aux output or primal residual (f is never
+    // formed there); AUTO takes it where no fused kernel exists
+    const bool gemm_ok = p.mode != MODE_FP64 && !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL));
     if (st->kernel == SSMAP_KERNEL_GEMM && !gemm_ok)
-        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without monitoring or aux output");
+        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without aux output or primal residual");
     p.gemm = st->kernel == SSMAP_KERNEL_GEMM || (st->kernel == SSMAP_KERNEL_AUTO && !can_fuse && gemm_ok);
     p.Qg = (c->Q + 127) / 128 * 128;
     p.Rg = (p.r + 127) / 128 * 128;
@@ -313,10 +321,14 @@ struct Prepared {
     Plan pl;
     IterArgs a{};             // z / znew of iteration 0
     void *z[2] = {nullptr, nullptr};
-    bool monitor = false, aux = false;
+    bool monitor = false, aux = false, primal = false;
     double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr,
            *sig = nullptr;
+    const double *fstar = nullptr;
+    // f and d around an iteration (aux output, primal residual): d^k is kept in dbuf
+    // once known; tbuf takes the other pass's values (see step_job)
     void *auxA = nullptr, *auxB = nullptr;
+    mutable void *dbuf = nullptr, *tbuf = nullptr;
     const void *dM = nullptr;
     int iters = 0;
     double stop_tol = 0.0;
@@ -347,7 +359,7 @@ void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
                    P.t, P.mperp2, (void *)P.a.ah, P.a.w, P.a.y, bad, mask_dev(c), s);
     launch_zero(P.z[0], (size_t)c->Qp * N, (int)esz, s);
     launch_zero(P.z[1], (size_t)c->Qp * N, (int)esz, s);
-    if (P.aux) {
+    if (P.aux || P.primal) {
         launch_zero(P.auxA, (size_t)c->Qp * N, (int)esz, s);
         launch_zero(P.auxB, (size_t)c->Qp * N, (int)esz, s);
     }
@@ -360,6 +372,11 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
                  hipStream_t s) {
     Prepared P;
     P.pl = make_plan(c, lambda, st);
+    P.monitor = st->check_every > 0;
+    P.check_every = st->check_every;
+    P.stop_tol = st->stop_tol;
+    P.aux = (st->flags & SSMAP_KEEP_AUX) != 0;
+    P.primal = P.monitor && (st->flags & SSMAP_MONITOR_PRIMAL) != 0;
     if (P.pl.gemm) {
         P.dM = dM;
         P.iters = iters;
@@ -371,10 +388,6 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     const int64_t N = c->g.N;
     const int Pm = c->P, Q = c->Q, Qp = c->Qp, r = pl.r, RP = pl.RP;
     const size_t esz = pl.mode == MODE_FP64 ? 8 : 4;
-    P.monitor = st->check_every > 0;
-    P.check_every = st->check_every;
-    P.stop_tol = st->stop_tol;
-    P.aux = (st->flags & SSMAP_KEEP_AUX) != 0;
     const size_t zbytes = (size_t)Qp * N * esz;
     const size_t rbytes = (size_t)RP * N * esz;
 
@@ -386,10 +399,10 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         need.push_back({"t", (size_t)r * N * 8});
         need.push_back({"mperp2", (size_t)N * 8});
         need.push_back({"V64", (size_t)Qp * RP * 8});
-        need.push_back({"partial", (size_t)2048 * ST_COUNT * 8});
+        need.push_back({"partial", (size_t)kMonitorBlocks * ST_COUNT * 8});
         need.push_back({"stat", (size_t)ST_COUNT * 8});
     }
-    if (P.aux) {
+    if (P.aux || P.primal) {
         need.push_back({"auxA", zbytes});
         need.push_back({"auxB", zbytes});
     }
@@ -440,13 +453,16 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         HIPC(c, hipMemcpyAsync(P.V64, hc.Vh.data(), hc.Vh.size() * 8, hipMemcpyHostToDevice, s));
         P.t = (double *)ensure(c, "t", (size_t)r * N * 8);
         P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
-        P.partial = (double *)ensure(c, "partial", (size_t)2048 * ST_COUNT * 8);
+        P.partial = (double *)ensure(c, "partial", (size_t)kMonitorBlocks * ST_COUNT * 8);
         P.stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
+        P.fstar = ref_dev(c);
     }
-    if (P.aux) {
+    if (P.aux || P.primal) {
         P.auxA = ensure(c, "auxA", zbytes);
         P.auxB = ensure(c, "auxB", zbytes);
     }
+    P.dbuf = P.auxA;
+    P.tbuf = P.auxB;
     HIPC(c, hipStreamSynchronize(s));         // host staging vectors are locals
 
     IterArgs &a = P.a;
@@ -511,6 +527,13 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     } else {
         need.push_back({"gw", rb});
     }
+    if (P.monitor) {
+        need.push_back({"t", (size_t)r * N * 8});
+        need.push_back({"mperp2", (size_t)N * 8});
+        need.push_back({"V64", (size_t)Qg * RP * 8});
+        need.push_back({"partial", (size_t)kMonitorBlocks * ST_COUNT * 8});
+        need.push_back({"stat", (size_t)ST_COUNT * 8});
+    }
     plan_check(c, need);
     for (int k = 0; k < 2; ++k) P.gz[k] = (float *)ensure(c, k ? "gz1" : "gz0", zb);
     P.gs = (float *)ensure(c, "gs", rb);
@@ -533,6 +556,19 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     // hi | hi | lo along K against the operands' hi | lo | hi
     HostConsts hc;
     host_consts(pl.mode, c->U, c->s, c->V, c->kmin, Pm, Q, Qp, r, RP, pl.beta, false, hc);
+    if (P.monitor) {
+        // float64 V_r for the monitor's contraction, Qg x RP (rows beyond Qp are zero)
+        P.V64 = (double *)ensure(c, "V64", (size_t)Qg * RP * 8);
+        std::vector<double> v64((size_t)Qg * RP, 0.0);
+        std::copy(hc.Vh.begin(), hc.Vh.end(), v64.begin());
+        HIPC(c, hipMemcpyAsync(P.V64, v64.data(), v64.size() * 8, hipMemcpyHostToDevice, s));
+        P.t = (double *)ensure(c, "t", (size_t)r * N * 8);
+        P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
+        P.partial = (double *)ensure(c, "partial", (size_t)kMonitorBlocks * ST_COUNT * 8);
+        P.stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
+        P.fstar = ref_dev(c);
+        HIPC(c, hipStreamSynchronize(s));      // v64 is a local
+    }
     auto Vf = [&](int q, int i) -> float {
         return (q < Q && i < r) ? (float)hc.Vh[(size_t)q * RP + i] : 0.0f;
     };
@@ -604,7 +640,7 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     HIPC(c, hipEventRecord(c->ev[0], s));
     int *bad = (int *)ensure(c, "bad", 256);
     launch_zero(bad, 1, 4, s);
-    launch_project(pl.mode, P.dM, Pm, Ur, P.sig, acoef, r, RP, N, nullptr, nullptr, gt0, gt0, gt1,
+    launch_project(pl.mode, P.dM, Pm, Ur, P.sig, acoef, r, RP, N, P.t, P.mperp2, gt0, gt0, gt1,
                    bad, mask_dev(c), s);
     launch_gemm_from_ranks(gt0, RP, P.gah, nullptr, N, Rg, s);
     launch_gemm_from_ranks(gt0, RP, P.gs, P.gws, N, Rg, s);
@@ -683,24 +719,50 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
     return L;
 }
 
-// Monitoring after iteration k (z^{k+1} against z^k). Returns true when the
-// residual stopping rule fires: k + 1 is a multiple of check_every and
-// ||z^{k+1} - z^k|| <= stop_tol ||z^{k+1}||.
+// Monitoring after iteration k (z^{k+1} against z^k; f^{k+1} when the primal
+// residual is asked for, left in tbuf by the bracket of iteration k). Returns
+// true when the residual stopping rule fires: k + 1 is a multiple of check_every
+// and ||z^{k+1} - z^k|| <= stop_tol ||z^{k+1}||.
 bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     const Plan &pl = P.pl;
-    launch_monitor(pl.mode, P.z[(k + 1) & 1], P.z[k & 1], P.V64, P.sig, P.t, P.mperp2, pl.r, pl.RP,
-                   c->nchunk, c->g, mask_dev(c), P.partial, 2048, P.stat, s);
+    MonArgs m{};
+    if (pl.gemm) {
+        m.z = P.gz[(k + 1) & 1];
+        m.zprev = P.gz[k & 1];
+        m.ld = pl.Qg;
+        m.nchunk = pl.Qg / QC;
+    } else {
+        m.z = P.z[(k + 1) & 1];
+        m.zprev = P.z[k & 1];
+        m.f = P.primal ? P.tbuf : nullptr;
+        m.nchunk = c->nchunk;
+    }
+    m.fstar = P.fstar;
+    m.V64 = P.V64;
+    m.sig = P.sig;
+    m.t = P.t;
+    m.mperp2 = P.mperp2;
+    m.r = pl.r;
+    m.RP = pl.RP;
+    m.Q = c->Q;
+    m.g = c->g;
+    m.code = mask_dev(c);
+    launch_monitor(pl.mode, m, P.partial, P.stat, s);
     HIPC(c, hipGetLastError());
     HIPC(c, hipMemcpyAsync(c->host_stats, P.stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipStreamSynchronize(s));
     const double *h = c->host_stats;
     ssmap_stats &S = c->stats;
     if (S.n_hist < SSMAP_MAX_HIST) {
-        S.hist_iter[S.n_hist] = k + 1;
-        S.hist_objective[S.n_hist] = 0.5 * h[ST_DATA] + pl.lam * h[ST_REG];
-        S.hist_dual[S.n_hist] = pl.beta * std::sqrt(h[ST_DZ]);
-        S.hist_znorm[S.n_hist] = std::sqrt(h[ST_ZNORM]);
-        S.n_hist++;
+        const int i = S.n_hist++;
+        S.hist_iter[i] = k + 1;
+        S.hist_objective[i] = 0.5 * h[ST_DATA] + pl.lam * h[ST_REG];
+        S.hist_dual[i] = pl.beta * std::sqrt(h[ST_DZ]);
+        S.hist_znorm[i] = std::sqrt(h[ST_ZNORM]);
+        S.hist_primal[i] = P.primal ? std::sqrt(h[ST_PRIMAL]) : -1.0;
+        const double fs = std::sqrt(h[ST_FSTAR]);
+        S.hist_dfcs[i] = P.fstar && fs > 0 ? std::sqrt(h[ST_DFCS]) / fs : -1.0;
+        S.hist_dfcs_f[i] = P.fstar && P.primal && fs > 0 ? std::sqrt(h[ST_DFCS_F]) / fs : -1.0;
     }
     if (h[ST_NONFINITE] != 0.0 || !std::isfinite(h[ST_DATA]))
         fail(SSMAP_ENONFINITE, "non-finite iterate at iteration " + std::to_string(k + 1));
@@ -712,6 +774,18 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
 // fused single-job launch with the aux passes around it).
 void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s);
 
+// Whether the monitor runs after iteration k (k + 1 iterations done).
+bool checked_after(const Prepared &P, int k) {
+    return P.monitor && ((k + 1) % P.check_every == 0 || k + 1 == P.iters);
+}
+
+// f^{k+1} is formed in iteration k when the monitor after it reports the primal
+// residual, or for the aux output after the last iteration.
+bool wants_f(const Prepared &P, int k) {
+    if (k >= P.iters) return false;
+    return (P.primal && checked_after(P, k)) || (P.aux && k == P.iters - 1);
+}
+
 void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipStream_t s) {
     const Plan &pl = P.pl;
     if (pl.gemm) {
@@ -719,28 +793,32 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
         return;
     }
     IterArgs a = args_for(P, k);
-    const int iters = P.iters;
-    if (P.aux && k == iters - 2) a.dout = P.auxA;                    // d^{K-1}
-    if (P.aux && k == iters - 1) {
-        a.dprev = iters >= 2 ? P.auxA : nullptr;                     // d^{K-1} (0 when K = 1)
-        a.fout = P.auxA;                                            // f^K, in place
-        a.dout = P.auxB;                                            // d^K
+    // f and d around iteration k. The iteration never forms them; when f^{k+1}
+    // is wanted (it needs d^k, itself formed around iteration k - 1; d^0 = 0),
+    // iteration k is bracketed: t = z^k + V_r w^k and f^{k+1} = t - d^k / beta
+    // (over d^k, in place) before it, d^{k+1} = beta (t - z^{k+1}) after it.
+    // Afterwards dbuf holds d^{k+1} and tbuf f^{k+1}.
+    const bool need_f = wants_f(P, k);
+    const bool bracket = need_f || wants_f(P, k + 1);
+    void *fbuf = need_f ? P.dbuf : nullptr;
+    const void *dprev = need_f && k > 0 ? P.dbuf : nullptr;
+    if (bracket) {
+        a.dprev = dprev;
+        a.fout = fbuf;
+        a.dout = P.tbuf;
     }
     if (pl.fused) {
-        // f and d are not part of the fused pass; bracket the last two iterations
         const size_t cnt = (size_t)c->Qp * c->g.N;
-        if (P.aux && k == iters - 2) launch_aux_pre(pl.mode, a, P.auxA, nullptr, nullptr, s);
-        if (P.aux && k == iters - 1)   // auxB = z + u, auxA: d^{K-1} -> f^K (d^0 = 0 if K = 1)
-            launch_aux_pre(pl.mode, a, P.auxB, P.auxA, iters >= 2 ? P.auxA : nullptr, s);
+        if (bracket) launch_aux_pre(pl.mode, a, P.tbuf, fbuf, dprev, s);
         FusedLaunch Lk = *L;
         Lk.round = k;
         if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
-        if (P.aux && k == iters - 2) launch_aux_post(pl.mode, P.auxA, a.znew, pl.beta, cnt, s);
-        if (P.aux && k == iters - 1) launch_aux_post(pl.mode, P.auxB, a.znew, pl.beta, cnt, s);
+        if (bracket) launch_aux_post(pl.mode, P.tbuf, a.znew, pl.beta, cnt, s);
     } else {
-        launch_update_unfused(pl.mode, a, s);
+        launch_update_unfused(pl.mode, a, s);     // writes f^{k+1} and d^{k+1} itself
         launch_projw_unfused(pl.mode, a, s);
     }
+    if (bracket) std::swap(P.dbuf, P.tbuf);
 }
 
 void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s);
@@ -762,8 +840,8 @@ void finish(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
         c->aux_valid = true;
         c->aux_mode = P.pl.mode;
         c->aux_iters = iters;
-        c->aux_f = P.auxA;
-        c->aux_d = P.auxB;
+        c->aux_f = P.tbuf;
+        c->aux_d = P.dbuf;
     }
 }
 
@@ -776,8 +854,7 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
     HIPC(c, hipEventRecord(c->ev[2], s));
     for (int k = 0; k < iters; ++k) {
         step_job(c, P, &L, k, s);
-        if (P.monitor && ((k + 1) % st->check_every == 0 || k + 1 == iters) &&
-            monitor_step(c, P, k, s) && k + 1 < iters) {
+        if (checked_after(P, k) && monitor_step(c, P, k, s) && k + 1 < iters) {
             P.iters = k + 1;             // residual stopping rule
             break;
         }
@@ -1233,6 +1310,27 @@ ssmap_status ssmap_set_mask(ssmap_ctx *ctx, const uint8_t *mask) {
         ctx->dtd_norm = masked_dtd_norm(ctx->g, code);
         ctx->code.swap(code);
         ctx->inside = inside;
+    });
+}
+
+ssmap_status ssmap_set_reference(ssmap_ctx *ctx, const double *f_star) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        HIPC(ctx, hipSetDevice(ctx->device));
+        if (!f_star) {
+            ctx->has_ref = false;
+            return;
+        }
+        const size_t n = (size_t)ctx->g.N * ctx->Q;
+        double ss = 0.0;
+        for (size_t i = 0; i < n; ++i) {
+            if (!std::isfinite(f_star[i])) fail(SSMAP_ENONFINITE, "f_star holds a NaN or Inf");
+            ss += f_star[i] * f_star[i];
+        }
+        if (!(ss > 0)) fail(SSMAP_EINVAL, "f_star is zero");
+        void *d = ensure(ctx, "fstar", n * 8);
+        HIPC(ctx, hipMemcpy(d, f_star, n * 8, hipMemcpyHostToDevice));
+        ctx->has_ref = true;
     });
 }
 

@@ -32,11 +32,39 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) <= exported
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's structs equal what a C compiler
+    makes of include/ssmap.h."""
     import ctypes
-    # ssmap_steps: 2 doubles + 6 ints + 1 double; ssmap_stats ends with 3 double arrays
-    assert ctypes.sizeof(_ffi.Steps) == 16 + 6 * 4 + 8
-    assert _ffi.Stats.hist_znorm.offset + 8 * _ffi.MAX_HIST == ctypes.sizeof(_ffi.Stats)
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"ssmap_steps": _ffi.Steps, "ssmap_stats": _ffi.Stats,
+               "ssmap_batch_stats": _ffi.BatchStats, "ssmap_server_opts": _ffi.ServerOpts,
+               "ssmap_job_info": _ffi.JobInfo, "ssmap_server_stats": _ffi.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ssmap.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, fname, v = line.split()
+            got[(cname, fname)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_argument_errors_before_any_device_work():

@@ -223,3 +223,27 @@ def test_beta_heuristic_picks_the_lowest_patch_objective():
     # a converged patch objective bounds every candidate from below
     zf, Jf = pins.fista(oracle.ladmm(p.K, mp, pgrid, p.lam, 1.0, 1)["K_r"], mp, pgrid, p.lam)
     assert np.all(J >= Jf * (1 - 1e-9))
+
+
+# ------------------------------------------------------------- monitored quantities
+def test_primal_residual_history_equals_the_dual_step():
+    """The oracle's primal residual ||z^k - f^k|| equals ||d^k - d^{k-1}|| / beta
+    (the dual update of Algorithm 2 read backwards), from two fixed-length
+    runs; DFCS of f^k and z^k follow Eq. (DFCS) against a reference."""
+    p = synth.generate("c1", grid=(7, 5, 1))
+    f_star = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, 400, rank=-1)["z"]
+    out = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, 30, track_every=10, f_star=f_star)
+    assert [h[0] for h in out["hist_f"]] == [0, 10, 20, 30]
+    for (k, primal, dfcs_f), (k2, _, dfcs_z) in zip(out["hist_f"], out["hist"]):
+        assert k == k2
+        if k == 0:
+            assert primal == 0.0
+            continue
+        a = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, k - 1)
+        b = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, k)
+        ref = np.linalg.norm(b["d"] - a["d"]) / p.beta
+        assert abs(primal - ref) <= 1e-10 * max(ref, 1e-300)
+        assert dfcs_f == pytest.approx(np.linalg.norm(b["f"] - f_star) / np.linalg.norm(f_star),
+                                       rel=1e-14)
+        assert dfcs_z == pytest.approx(np.linalg.norm(b["z"] - f_star) / np.linalg.norm(f_star),
+                                       rel=1e-14)
