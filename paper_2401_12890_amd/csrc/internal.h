@@ -74,6 +74,8 @@ struct FusedLaunch {
     int ntiles;
     int round;             // iteration counter of the shared loop
     int maxchunk;          // largest chunk count among the jobs (0: unknown)
+    double *mon;           // monitored iteration: per-brick sums of (z^{k+1} - z^k)^2
+                           // (ntiles float64 slots), else NULL
 };
 // fused_supported(): whether (mode, padded rank, voxel count) has a fused kernel.
 bool fused_supported(int mode, int RP, int64_t N);
@@ -119,6 +121,10 @@ struct MonArgs {
     const void *f;            // f of the same iteration (chunked state layout), or NULL
     const double *fstar;      // reference map for DFCS (N x Q float64, voxel-major), or NULL
     const double *V64;        // V_r in float64, (16 nchunk) x RP, zero padded
+    const void *y;            // y = V_r^T z as the iteration left it (state type, RP x N
+                              // rank-major), or NULL: the monitor contracts V64 with z
+    const double *dzpart;     // per-brick sums of (z - zprev)^2 from the iteration, or NULL
+    int ndz;
     const double *sig, *t, *mperp2;   // singular values (RP), U_r^T m (r x N), ||m_perp||^2 (N)
     int r, RP, nchunk, Q;
     int64_t ld;               // voxel-major row length (0: chunked layout)

@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 
@@ -281,10 +282,14 @@ k_aux_post(T *__restrict__ t, const T *__restrict__ znew, T beta, size_t count) 
 // time; lane l holds voxel l % 16 and the four nodes 4 (l / 16) .. + 3 of each
 // 16-node chunk. The data term uses
 //     ||m_n - K_r z_n||^2 = ||m_n||^2 - ||t_n||^2 + sum_i (t_i - sigma_i y_i)^2,
-// t = U_r^T m_n, y = V_r^T z_n, with y contracted on the matrix cores in
-// float64 (v_mfma_f64_16x16x4: M = 16 ranks, N = 16 voxels, K = 4 nodes; the
-// lane's own z values are the B operand, K-row l / 16 of step s being node
-// 4 (l / 16) + s; output rank 16 rb + l / 16 + 4 i in lane l). The regulariser
+// t = U_r^T m_n, y = V_r^T z_n. The iteration kernels leave y of the new iterate
+// in their r-vector state (contracted there in the state precision; the objective
+// then differs from the float64 contraction by about 1e-8 relative in float32
+// and 1e-6 in bf16x3), which the monitor reads when it is given. Otherwise (the
+// GEMM path keeps no y) y is contracted here on the matrix cores in float64
+// (v_mfma_f64_16x16x4: M = 16 ranks, N = 16 voxels, K = 4 nodes; the lane's own
+// z values are the B operand, K-row l / 16 of step s being node 4 (l / 16) + s;
+// output rank 16 rb + l / 16 + 4 i in lane l). The regulariser
 // takes every forward face edge once (both ends inside a mask). Sums are
 // reduced across the wave by shuffles, across the four waves through LDS,
 // then in a fixed order over the blocks, so every result is bitwise repeatable.
@@ -337,7 +342,15 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
         const bool ex = ein && x + 1 < nx && in(n + 1);
         const bool ey = ein && yy + 1 < ny && in(n + nx);
         const bool ez = ein && zz + 1 < nz && in(n + nx * ny);
+        const bool contract = a.y == nullptr;
+        if (!contract && valid)             // data term from the iteration's y
+            for (int rr = i4; rr < a.r; rr += 4) {
+                const double yv = (double)((const T *)a.y)[(size_t)rr * N + n];
+                const double e = a.t[(size_t)rr * N + n] - a.sig[rr] * yv;
+                acc[ST_DATA] += e * e;
+            }
         for (int rg = 0; rg < RB || rg == 0; rg += MON_RG) {
+            if (!contract && rg > 0) break;
             v4d_m yacc[MON_RG];
 #pragma unroll
             for (int g = 0; g < MON_RG; ++g) yacc[g] = v4d_m{0.0, 0.0, 0.0, 0.0};
@@ -388,7 +401,7 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
 #pragma unroll
                 for (int g = 0; g < MON_RG; ++g) {
                     const int rb = rg + g;
-                    if (rb < RB) {
+                    if (contract && rb < RB) {
                         const double *Vc = a.V64 + (size_t)(16 * c + 4 * i4) * a.RP + 16 * rb + j;
 #pragma unroll
                         for (int s = 0; s < 4; ++s)
@@ -402,7 +415,7 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int rr = 16 * (rg + g) + i4 + 4 * i;
-                    if (valid && rr < a.r) {
+                    if (contract && valid && rr < a.r) {
                         const double e = a.t[(size_t)rr * N + n] - a.sig[rr] * yacc[g][i];
                         acc[ST_DATA] += e * e;
                     }
@@ -423,10 +436,160 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
     }
 }
 
+// 16 bytes (four float or two double values) through a raw buffer resource;
+// offsets are 32-bit within one chunk of the state
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mon_rsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, unsigned off, T out[4]) {
+    typedef unsigned v4u_m __attribute__((ext_vector_type(4)));
+    const v4u_m a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = __uint_as_float(a[i]);
+    } else {
+        const v4u_m b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+        out[0] = __hiloint2double(a[1], a[0]);
+        out[1] = __hiloint2double(a[3], a[2]);
+        out[2] = __hiloint2double(b[1], b[0]);
+        out[3] = __hiloint2double(b[3], b[2]);
+    }
+}
+
+// The same sums for the chunked layout when the iteration left y: a streaming
+// pass. grid.y = chunk; a block takes whole rows of the grid (fixed y, z) in
+// turn, each lane one quarter (four values) of a voxel's 16-node chunk row, so
+// a block reads a row's chunk as one contiguous run, like a copy. The three
+// forward neighbours of a value are the same quarter at voxel n + 1, n + nx,
+// n + nx ny (read through the caches). The squares are summed in the state
+// precision over a tile of up to 8 rows, then accumulated in float64. The
+// per-voxel data term from y and t is spread over all blocks.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_monitor_stream(MonArgs a, double *__restrict__ partial) {
+    const uint32_t N = (uint32_t)a.g.N, nx = (uint32_t)a.g.nx, ny = (uint32_t)a.g.ny,
+                   nz = (uint32_t)a.g.nz, nxy = nx * ny;
+    const unsigned cbytes = (unsigned)((size_t)N * QC * sizeof(T));
+    const bool hasp = a.zprev != nullptr, hasf = a.f != nullptr;
+    auto in = [&](uint32_t v) { return !a.code || (a.code[v] & 0x80u) != 0; };
+    double acc[ST_COUNT];
+#pragma unroll
+    for (int k = 0; k < ST_COUNT; ++k) acc[k] = 0.0;
+    // rows in tiles of (one y, up to 8 consecutive z), tiles y-fastest within a band of
+    // 8 z-planes, for each chunk in turn. The grid holds about as many blocks as run at
+    // once, and each takes a contiguous range of (chunk, tile) items and walks each
+    // tile along z, so the z neighbour row is the next one it reads and the y neighbour
+    // row comes 8 rows later (both still in its L2).
+    const uint32_t rowq = 4 * nx, nzb = (nz + 7) / 8, ntile = ny * nzb;
+    const uint32_t total = ntile * (uint32_t)a.nchunk;
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t w0 = blockIdx.x * per, w1 = min(total, w0 + per);
+    const unsigned sx = QC * sizeof(T), sy = nx * QC * sizeof(T), sz = nxy * QC * sizeof(T);
+    for (uint32_t w = w0; w < w1; ++w) {
+        const int c = (int)(w / ntile);
+        const uint32_t tile = w - (uint32_t)c * ntile;
+        const uint32_t yy = tile % ny, zb = (tile / ny) * 8;
+        const size_t cbase = (size_t)c * N * QC;
+        const __amdgpu_buffer_rsrc_t zr = mon_rsrc((const T *)a.z + cbase, cbytes);
+        const __amdgpu_buffer_rsrc_t pr = mon_rsrc(hasp ? (const T *)a.zprev + cbase : nullptr,
+                                                   hasp ? cbytes : 0);
+        const __amdgpu_buffer_rsrc_t fr = mon_rsrc(hasf ? (const T *)a.f + cbase : nullptr,
+                                                   hasf ? cbytes : 0);
+        // squares of one tile summed in the state type, then added in float64
+        T zsq = 0, reg = 0, dsq = 0, psq = 0;
+        int bad = 0;
+        for (uint32_t zz = zb; zz < min(zb + 8, nz); ++zz) {
+            const uint32_t nrow = (yy + ny * zz) * nx;
+            const bool rowy = yy + 1 < ny, rowz = zz + 1 < nz;
+#pragma unroll 2
+            for (uint32_t e = threadIdx.x; e < rowq; e += blockDim.x) {
+                const uint32_t x = e >> 2, qd = e & 3u, n = nrow + x;
+                const bool ein = in(n);
+                const bool ex = ein && x + 1 < nx && in(n + 1);
+                const bool ey = ein && rowy && in(n + nx);
+                const bool ez = ein && rowz && in(n + nxy);
+                const unsigned off = (n * QC + 4 * qd) * (unsigned)sizeof(T);
+                // every load unconditional (a missing neighbour reads the voxel itself and
+                // is masked below), so they issue together
+                T zv[4], nb[3][4], pv[4], fv[4];
+                bload4<T>(zr, off, zv);
+                bload4<T>(zr, off + (ex ? sx : 0u), nb[0]);
+                bload4<T>(zr, off + (ey ? sy : 0u), nb[1]);
+                bload4<T>(zr, off + (ez ? sz : 0u), nb[2]);
+                if (hasp) bload4<T>(pr, off, pv);
+                if (hasf) bload4<T>(fr, off, fv);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const T v = zv[s];
+                    zsq += v * v;
+                    const T d0 = v - nb[0][s], d1 = v - nb[1][s], d2 = v - nb[2][s];
+                    reg += d0 * d0 + d1 * d1 + d2 * d2;      // masked neighbours read v itself
+                    if (hasp) {
+                        const T dd = v - pv[s];
+                        dsq += dd * dd;
+                    }
+                    if (hasf) {
+                        const T dd = v - fv[s];
+                        psq += dd * dd;
+                    }
+                }
+                if (a.fstar) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int q = 16 * c + 4 * (int)qd + s;
+                        const double fs = q < a.Q ? a.fstar[(size_t)n * a.Q + q] : 0.0;
+                        const double dd = q < a.Q ? (double)zv[s] - fs : 0.0;
+                        acc[ST_DFCS] += dd * dd;
+                        acc[ST_FSTAR] += fs * fs;
+                        if (hasf) {
+                            const double df = q < a.Q ? (double)fv[s] - fs : 0.0;
+                            acc[ST_DFCS_F] += df * df;
+                        }
+                    }
+                }
+            }
+        }
+        // a NaN or Inf anywhere in the tile (or a square beyond the state type's range)
+        // leaves the tile's sum of squares non-finite
+        bad += !__builtin_isfinite(zsq);
+        acc[ST_NONFINITE] += (double)bad;
+        acc[ST_ZNORM] += (double)zsq;
+        acc[ST_REG] += (double)reg;
+        acc[ST_DZ] += (double)dsq;
+        acc[ST_PRIMAL] += (double)psq;
+    }
+    {                                        // data term: ||m_perp||^2 + sum_i (t_i - sigma_i y_i)^2,
+        const T *y = (const T *)a.y;         // voxels spread over every block of the grid
+        const uint32_t all = gridDim.x * blockDim.x;
+        for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += all) {
+            double d = a.mperp2[n];
+            for (int i = 0; i < a.r; ++i) {
+                const double e = a.t[(size_t)i * N + n] - a.sig[i] * (double)y[(size_t)i * N + n];
+                d += e * e;
+            }
+            acc[ST_DATA] += d;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double red[4][ST_COUNT];
+#pragma unroll
+    for (int k = 0; k < ST_COUNT; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_COUNT) {
+        const int k = threadIdx.x;
+        partial[(size_t)blockIdx.x * ST_COUNT + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
 // Fixed-order sum of the per-block partials: thread t adds blocks t, t + 256, ...
 // in turn; then shuffles within each wave and the four wave sums in order.
 __global__ void __launch_bounds__(256)
-k_reduce_partials(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
+k_reduce_partials(const double *__restrict__ partial, int nblocks, const double *__restrict__ dzpart,
+                  int ndz, double *__restrict__ out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ double red[4][ST_COUNT];
     double acc[ST_COUNT];
@@ -435,6 +598,8 @@ k_reduce_partials(const double *__restrict__ partial, int nblocks, double *__res
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
 #pragma unroll
         for (int k = 0; k < ST_COUNT; ++k) acc[k] += partial[(size_t)b * ST_COUNT + k];
+    if (dzpart)                              // the iteration's per-brick sums of (z - zprev)^2
+        for (int b = threadIdx.x; b < ndz; b += blockDim.x) acc[ST_DZ] += dzpart[b];
 #pragma unroll
     for (int k = 0; k < ST_COUNT; ++k) {
         const double v = wave_sum(acc[k]);
@@ -558,12 +723,48 @@ void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t co
                            (float)beta, count);
 }
 
+// Blocks of the streaming monitor that the current device runs at once (per CU
+// occupancy x CUs), at most kMonitorBlocks; looked up once per device and mode.
+int stream_blocks(int mode) {
+    static std::mutex mu;
+    static int cache[kMaxDevices][2] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 1024;
+    const int m = mode == MODE_FP64 ? 1 : 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[dev][m] == 0) {
+        int per = 0, cus = 0;
+        const hipError_t e1 = m ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                      &per, k_monitor_stream<double>, 256, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                      &per, k_monitor_stream<float>, 256, 0);
+        const hipError_t e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int n = (e1 == hipSuccess && e2 == hipSuccess && per > 0 && cus > 0) ? per * cus : 1024;
+        cache[dev][m] = std::min(n, kMonitorBlocks);
+    }
+    return cache[dev][m];
+}
+
 int monitor_blocks(int64_t N) {
     const int64_t b = ((N + 15) / 16 + 3) / 4;     // four 16-voxel tiles per block
     return (int)(b < kMonitorBlocks ? (b > 0 ? b : 1) : kMonitorBlocks);
 }
 
 void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hipStream_t s) {
+    const int64_t esz = mode == MODE_FP64 ? 8 : 4;
+    if (a.y && a.ld == 0 && a.nchunk > 0 && a.nchunk <= kMonitorBlocks &&
+        a.g.N * QC * esz + 64 < ((int64_t)1 << 31)) {
+        // streaming pass: about as many blocks as the device runs at once (no tail)
+        const int64_t items = a.g.ny * ((a.g.nz + 7) / 8) * a.nchunk;
+        const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(items, stream_blocks(mode)));
+        if (mode == MODE_FP64)
+            hipLaunchKernelGGL(k_monitor_stream<double>, dim3(gx), dim3(256), 0, s, a, partial);
+        else
+            hipLaunchKernelGGL(k_monitor_stream<float>, dim3(gx), dim3(256), 0, s, a, partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, gx, a.dzpart, a.ndz,
+                           out);
+        return;
+    }
     const int nb = monitor_blocks(a.g.N);
     const bool vm = a.ld > 0;
     if (mode == MODE_FP64) {
@@ -573,7 +774,7 @@ void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hi
         if (vm) hipLaunchKernelGGL((k_monitor<float, true>), dim3(nb), dim3(256), 0, s, a, partial);
         else hipLaunchKernelGGL((k_monitor<float, false>), dim3(nb), dim3(256), 0, s, a, partial);
     }
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, a.dzpart, a.ndz, out);
 }
 
 void launch_output(int mode, const void *z, void *F, int Q, int64_t N, bool to_double,

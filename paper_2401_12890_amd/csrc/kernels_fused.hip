@@ -187,6 +187,27 @@ template <> struct Buf<double, v4d> {
     }
 };
 
+// Monitored iterations: the brick's sum of (z^{k+1} - z^k)^2 (float64) over the
+// waves, written to mon[tile] (one slot per brick, summed in a fixed order later).
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+template <int NW>
+__device__ __forceinline__ void brick_sum_out(double v, double *red, double *mon, int tile) {
+    v = wave_sum64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w];
+        mon[tile] = t;
+    }
+}
+
 // KSU: K-steps of the u contraction actually needed (ceil(r / 4)); RB: 16-row
 // blocks of r in the y contraction. bf16x3 uses one 32-wide K-step (KSU unused).
 // Small volumetric bricks (16 x 4 x 4: two rows per wave) of the float32 and
@@ -198,10 +219,10 @@ constexpr bool fused_small(int mode, int ty, int tz) {
 }
 constexpr int fused_occupancy(int mode, int ty, int tz) { return fused_small(mode, ty, tz) ? 4 : 1; }
 
-template <int MODE, int RB, int KSU, int TY, int TZ>
+template <int MODE, int RB, int KSU, int TY, int TZ, bool MON>
 __global__ void __launch_bounds__(NT, fused_occupancy(MODE, TY, TZ))
 k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles,
-        int round) {
+        int round, double *__restrict__ mon) {
     using F = FT<MODE>;
     using T = typename F::T;
     using V4 = typename F::V4;
@@ -234,6 +255,7 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     constexpr int NBUF = DBL ? 2 : 1;
     __shared__ V4 lds[NBUF][4 * B::NSP + 1];   // z^k of the brick, [quad][slot], + one sink entry
     __shared__ uint4 ldsv[NBUF][NT];           // V operands of the chunk (entries >= VB/16 unused)
+    __shared__ double mred[MON ? NW : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -363,6 +385,8 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     }
 
     int g = 0;                           // chunks computed so far (LDS buffer parity)
+    T dzacc = 0;                         // monitored iterations: this lane's sum of
+                                         // (z^{k+1} - z^k)^2 over a brick (state type)
     for (int it = 0;; ++it) {
         const int tile = tile_of(it);
         if (tile < 0) break;
@@ -389,11 +413,11 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
             valid[b] = gx < nx && gy < ny && gz < nz;
             nvox[b] = valid[b] ? gx + nx * (gy + ny * gz) : 0;
             deg[b] = (T)((gx > 0) + (gx + 1 < nx) + (gy > 0) + (gy + 1 < ny) + (gz > 0) + (gz + 1 < nz));
-            inside[b] = true;
+            inside[b] = valid[b];        // lanes beyond the grid compute z^{k+1} = 0 (never stored)
             if (a.code) {                // masked grid: outside voxels hold z = 0, so the
                 const unsigned cb = a.code[nvox[b]];   // box neighbour sum stays exact
                 deg[b] = (T)(cb & 7u);
-                inside[b] = (cb & 0x80u) != 0;
+                inside[b] = valid[b] && (cb & 0x80u) != 0;
             }
             soff[b] = valid[b] ? (unsigned)((nvox[b] * QC + 4 * i4) * sizeof(T)) : OOB;
         }
@@ -535,6 +559,13 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
     #pragma unroll
                 for (int i = 0; i < 4; ++i) zn[i] = (zn[i] > (T)0 && inside[b]) ? zn[i] : (T)0;
                 IO::store(zn, zo, soff[b]);
+                if constexpr (MON) {
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const T dd = zn[i] - zc[i];      // 0 outside the grid
+                        dzacc += dd * dd;
+                    }
+                }
                 if constexpr (BF) {
                     // K = the 16 nodes of the chunk in their natural lane order
                     v4s zh, zl;
@@ -675,6 +706,10 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
                     }
             }
         }
+        if constexpr (MON) {
+            brick_sum_out<NW>((double)dzacc, mred, mon, tile);
+            dzacc = 0;
+        }
         if constexpr (!DBL) break;   // one brick per workgroup
     }
 }
@@ -708,10 +743,10 @@ __device__ __forceinline__ void lds_dma16(__amdgpu_buffer_rsrc_t r, void *lds, u
                                              voff, 0, 0, 0);
 }
 
-template <int MODE, int RB, int KSU, int TY, int TZ>
+template <int MODE, int RB, int KSU, int TY, int TZ, bool MON>
 __global__ void __launch_bounds__(NT, 1)
 k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, int ntiles,
-        int round) {
+        int round, double *__restrict__ mon) {
     static_assert(MODE != MODE_FP64, "float64 uses the register-staged kernel");
     using F = FT<MODE>;
     using V4 = v4f;
@@ -730,6 +765,8 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
 
     __shared__ uint4 zbuf[2][BX::NG * 64];
     __shared__ uint4 vbuf[2][VB / 16];
+    __shared__ double mred[MON ? NW : 1];
+    float dzacc = 0.0f;
 
     int tile = blockIdx.x;
     if ((ntiles & 7) == 0) {             // keep neighbouring bricks on one XCD (shared L2)
@@ -801,11 +838,11 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
         valid[b] = gx < nx && gy < ny && gz < nz;
         nvox[b] = valid[b] ? gx + nx * (gy + ny * gz) : 0;
         deg[b] = (float)((gx > 0) + (gx + 1 < nx) + (gy > 0) + (gy + 1 < ny) + (gz > 0) + (gz + 1 < nz));
-        inside[b] = true;
+        inside[b] = valid[b];            // lanes beyond the grid compute z^{k+1} = 0 (never stored)
         if (a.code) {
             const unsigned cb = a.code[nvox[b]];
             deg[b] = (float)(cb & 7u);
-            inside[b] = (cb & 0x80u) != 0;
+            inside[b] = valid[b] && (cb & 0x80u) != 0;
         }
         soff[b] = valid[b] ? (unsigned)((nvox[b] * QC + 4 * i4) * sizeof(float)) : OOB;
         const int s0 = (j + 1) + BX::SX * ((by + 1) + BX::SY * (bz + 1));
@@ -905,6 +942,13 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
 #pragma unroll
             for (int i = 0; i < 4; ++i) zn[i] = (zn[i] > 0.0f && inside[b]) ? zn[i] : 0.0f;
             zkeep[b] = zn;
+            if constexpr (MON) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float dd = zn[i] - zc[i];      // 0 outside the grid
+                    dzacc += dd * dd;
+                }
+            }
             if constexpr (BF) {
                 v4s zh, zl;
                 split4(zn, zh, zl);
@@ -962,6 +1006,7 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, yn), yr, ob, 0, 0);
             }
     }
+    if constexpr (MON) brick_sum_out<NW>((double)dzacc, mred, mon, tile);
 }
 
 // Longest brick (in 16-node chunks) that the double-buffered shapes run persistent.
@@ -980,14 +1025,14 @@ int device_cus() {
     return n;
 }
 
-template <int MODE, int RB, int KSU, int TY, int TZ>
+template <int MODE, int RB, int KSU, int TY, int TZ, bool MON>
 void launch_t(const FusedLaunch &L, hipStream_t s) {
     // bf16x3 stages the small volumetric brick through registers (four waves
     // per SIMD) and the others through direct LDS loads; float32 and float64
     // always through registers
     if constexpr (MODE == MODE_BF16X3 && !fused_small(MODE, TY, TZ))
-        hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ>), dim3(L.ntiles), dim3(NT), 0, s,
-                           L.jobs, L.tiles, L.ntiles, L.round);
+        hipLaunchKernelGGL((k_fused_dma<MODE, RB, KSU, TY, TZ, MON>), dim3(L.ntiles), dim3(NT), 0, s,
+                           L.jobs, L.tiles, L.ntiles, L.round, L.mon);
     else {
         // Short bricks of the double-buffered shapes (one workgroup per CU) run a
         // persistent grid, at most one workgroup per CU: the loads of a brick's
@@ -1003,28 +1048,35 @@ void launch_t(const FusedLaunch &L, hipStream_t s) {
             const int cus = device_cus();
             if (L.maxchunk > 0 && L.maxchunk <= kPersistChunks && cus > 0 && cus < nwg) nwg = cus;
         }
-        hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ>), dim3(nwg), dim3(NT), 0, s, L.jobs, L.tiles,
-                           L.ntiles, L.round);
+        hipLaunchKernelGGL((k_fused<MODE, RB, KSU, TY, TZ, MON>), dim3(nwg), dim3(NT), 0, s, L.jobs,
+                           L.tiles, L.ntiles, L.round, L.mon);
     }
+}
+
+// Monitored iterations (L.mon set) run the variant that also sums (z^{k+1} - z^k)^2.
+template <int MODE, int RB, int KSU, int TY, int TZ>
+void launch_m(const FusedLaunch &L, hipStream_t s) {
+    if (L.mon) launch_t<MODE, RB, KSU, TY, TZ, true>(L, s);
+    else launch_t<MODE, RB, KSU, TY, TZ, false>(L, s);
 }
 
 template <int MODE, int RB, int KSU>
 bool launch_shape(const FusedLaunch &L, hipStream_t s) {
     const int ty = L.shape.ty, tz = L.shape.tz;
     if constexpr (MODE == MODE_FP64) {
-        if (ty == 8 && tz == 1) return launch_t<MODE, RB, KSU, 8, 1>(L, s), true;
-        if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
-        if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
-        if (ty == 4 && tz == 2) return launch_t<MODE, RB, KSU, 4, 2>(L, s), true;
+        if (ty == 8 && tz == 1) return launch_m<MODE, RB, KSU, 8, 1>(L, s), true;
+        if (ty == 16 && tz == 1) return launch_m<MODE, RB, KSU, 16, 1>(L, s), true;
+        if (ty == 4 && tz == 4) return launch_m<MODE, RB, KSU, 4, 4>(L, s), true;
+        if (ty == 4 && tz == 2) return launch_m<MODE, RB, KSU, 4, 2>(L, s), true;
     } else {
-        if (ty == 8 && tz == 1) return launch_t<MODE, RB, KSU, 8, 1>(L, s), true;
-        if (ty == 16 && tz == 1) return launch_t<MODE, RB, KSU, 16, 1>(L, s), true;
-        if (ty == 4 && tz == 4) return launch_t<MODE, RB, KSU, 4, 4>(L, s), true;
-        if (ty == 8 && tz == 4) return launch_t<MODE, RB, KSU, 8, 4>(L, s), true;
+        if (ty == 8 && tz == 1) return launch_m<MODE, RB, KSU, 8, 1>(L, s), true;
+        if (ty == 16 && tz == 1) return launch_m<MODE, RB, KSU, 16, 1>(L, s), true;
+        if (ty == 4 && tz == 4) return launch_m<MODE, RB, KSU, 4, 4>(L, s), true;
+        if (ty == 8 && tz == 4) return launch_m<MODE, RB, KSU, 8, 4>(L, s), true;
         if constexpr (MODE == MODE_BF16X3)
-            if (ty == 4 && tz == 2) return launch_t<MODE, RB, KSU, 4, 2>(L, s), true;
+            if (ty == 4 && tz == 2) return launch_m<MODE, RB, KSU, 4, 2>(L, s), true;
         if constexpr (MODE == MODE_FP32)
-            if (ty == 32 && tz == 1) return launch_t<MODE, RB, KSU, 32, 1>(L, s), true;
+            if (ty == 32 && tz == 1) return launch_m<MODE, RB, KSU, 32, 1>(L, s), true;
     }
     return false;
 }

@@ -329,6 +329,8 @@ struct Prepared {
     // once known; tbuf takes the other pass's values (see step_job)
     void *auxA = nullptr, *auxB = nullptr;
     mutable void *dbuf = nullptr, *tbuf = nullptr;
+    double *monpart = nullptr;    // fused path: per-brick (z^{k+1} - z^k)^2 of a monitored iteration
+    int ntiles = 0;
     const void *dM = nullptr;
     int iters = 0;
     double stop_tol = 0.0;
@@ -414,6 +416,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
                           ((c->g.nz + sh.tz - 1) / sh.tz);
         need.push_back({"jobs", 2 * sizeof(IterArgs)});
         need.push_back({"tiles", nb * sizeof(TileRef)});
+        if (P.monitor) need.push_back({"monpart", nb * 8});
     }
     if (pl.mode == MODE_BF16X3) {
         need.push_back({"Vhi", (size_t)Qp * RP * 2});
@@ -456,6 +459,12 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         P.partial = (double *)ensure(c, "partial", (size_t)kMonitorBlocks * ST_COUNT * 8);
         P.stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
         P.fstar = ref_dev(c);
+        if (pl.fused) {
+            const FusedShape sh = default_shape(pl.mode, c->g);
+            const size_t nb = (size_t)((c->g.nx + 15) / 16) * ((c->g.ny + sh.ty - 1) / sh.ty) *
+                              ((c->g.nz + sh.tz - 1) / sh.tz);
+            P.monpart = (double *)ensure(c, "monpart", nb * 8);
+        }
     }
     if (P.aux || P.primal) {
         P.auxA = ensure(c, "auxA", zbytes);
@@ -732,8 +741,16 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
         m.ld = pl.Qg;
         m.nchunk = pl.Qg / QC;
     } else {
+        // the iteration left y^{k+1} = V_r^T z^{k+1} in its r-vector state; the fused
+        // kernel also summed (z^{k+1} - z^k)^2 per brick
         m.z = P.z[(k + 1) & 1];
-        m.zprev = P.z[k & 1];
+        m.y = P.a.y;
+        if (pl.fused) {
+            m.dzpart = P.monpart;
+            m.ndz = P.ntiles;
+        } else {
+            m.zprev = P.z[k & 1];
+        }
         m.f = P.primal ? P.tbuf : nullptr;
         m.nchunk = c->nchunk;
     }
@@ -812,6 +829,7 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
         if (bracket) launch_aux_pre(pl.mode, a, P.tbuf, fbuf, dprev, s);
         FusedLaunch Lk = *L;
         Lk.round = k;
+        if (checked_after(P, k)) Lk.mon = P.monpart;
         if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
         if (bracket) launch_aux_post(pl.mode, P.tbuf, a.znew, pl.beta, cnt, s);
     } else {
@@ -851,6 +869,7 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
     Prepared P = prepare(c, dM, lambda, st, iters, s);
     FusedLaunch L{};
     if (P.pl.fused) L = single_launch(c, P, s);
+    P.ntiles = L.ntiles;
     HIPC(c, hipEventRecord(c->ev[2], s));
     for (int k = 0; k < iters; ++k) {
         step_job(c, P, &L, k, s);

@@ -64,8 +64,11 @@ def test_auto_takes_the_gemm_path_above_rank_32(torch_cuda):
     with _ffi.Mapper(p.K, p.grid) as mp:
         mp.solve(p.m, p.lam, p.beta, 10, precision="fp32", rank=40)
         assert mp.stats()["kernel"] == 3
-        # monitoring keeps the unfused path
+        # monitoring runs on the GEMM path too; the primal residual needs f,
+        # which only the unfused path forms
         mp.solve(p.m, p.lam, p.beta, 10, precision="fp32", rank=40, check_every=5)
+        assert mp.stats()["kernel"] == 3
+        mp.solve(p.m, p.lam, p.beta, 10, precision="fp32", rank=40, check_every=5, primal=True)
         assert mp.stats()["kernel"] == 1
         mp.solve(p.m, p.lam, p.beta, 10, precision="fp32")
         assert mp.stats()["kernel"] == 2
@@ -87,7 +90,7 @@ def test_gemm_path_with_a_mask(torch_cuda):
 def test_gemm_path_rejections(torch_cuda):
     p = synth.generate("c1", grid=(6, 5, 1))
     with _ffi.Mapper(p.K, p.grid) as mp:
-        for kw in (dict(precision="fp64"), dict(precision="fp32", check_every=5),
+        for kw in (dict(precision="fp64"), dict(precision="fp32", check_every=5, primal=True),
                    dict(precision="fp32", keep_aux=True)):
             with pytest.raises(_ffi.SsmapError) as e:
                 mp.solve(p.m, p.lam, p.beta, 5, kernel="gemm", **kw)
