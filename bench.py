@@ -496,7 +496,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "unfused"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "unfused", "split"])
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--grid", type=int, nargs=3, default=None,
                     help="solve the workload's recipe on another grid (nx ny nz)")
@@ -570,7 +570,8 @@ def main():
     per_launch_ms = (sum(loop_ms) / len(loop_ms)) / iters
     alg = alg_bytes_per_voxel_iter(prob.Q, r, wbytes) * prob.N
     achieved = alg / (per_launch_ms / 1e3) / 1e9
-    kern_name = {1: "k_update+k_projw (unfused)", 2: "k_fused", 3: "k_gemm_tn (GEMM path)"}[st["kernel"]]
+    kern_name = {1: "k_update+k_projw (unfused)", 2: "k_fused", 3: "k_gemm_tn (GEMM path)",
+                 4: "k_split (chunk split)"}[st["kernel"]]
     if st["kernel"] == 3:
         # dominant kernel: the GEMM (two launches per iteration, equal flops), timed by the
         # library's HIP events around each launch. Algorithmic flops: the two contractions

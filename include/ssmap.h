@@ -66,11 +66,18 @@ typedef enum {
 
 /* Kernel family for the iteration (both compute the same iterates). */
 typedef enum {
-    SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows (r <= 32); else
-                               the GEMM path for float32 / bf16x3 without aux output
-                               or primal residual; else unfused                   */
+    SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows (r <= 32), split
+                               over chunks for small grids (see SPLIT); else the GEMM
+                               path for float32 / bf16x3 without aux output or
+                               primal residual; else unfused                      */
     SSMAP_KERNEL_UNFUSED = 1,
     SSMAP_KERNEL_FUSED = 2,
+    SSMAP_KERNEL_SPLIT = 4, /* small grids, float64 / float32, r <= 32: the fused step
+                               split over 16-node chunks, one workgroup per (brick,
+                               chunk), the rank vectors carried as per-chunk partial
+                               products summed in chunk order; no SSMAP_KEEP_AUX or
+                               SSMAP_MONITOR_PRIMAL. AUTO takes it for grids of at
+                               most 32 bricks and 2..32 chunks                    */
     SSMAP_KERNEL_GEMM = 3   /* any rank, float32 / bf16x3: the two contractions as
                                MFMA-tiled GEMMs over all voxels (compute bound at
                                high rank), the stencil / z-update and r-vector
@@ -115,7 +122,7 @@ typedef struct {
     int rank;               /* r used                                             */
     int rank_padded;        /* r rounded up for the contraction tiles              */
     int precision;
-    int kernel;             /* ssmap_kernel actually used (1, 2 or 3)              */
+    int kernel;             /* ssmap_kernel actually used (1 to 4)                 */
     int iters;              /* iterations run                                      */
     int n_hist;             /* entries in the history arrays                       */
     double xi_p;            /* xi_p used                                           */
@@ -181,8 +188,8 @@ ssmap_status ssmap_solve_device(ssmap_ctx *ctx, const void *dM, double lambda,
  * Limits: EINVAL when the solve needs more than SSMAP_NOALLOC_MAX_BYTES (about
  * (2 Qp + 3 RP) N words of state, Qp = Q rounded up to 16, RP = the rank
  * rounded up to 16, plus the dictionary's constants), with SSMAP_KEEP_AUX or
- * with SSMAP_KERNEL_GEMM; AUTO runs the fused kernel where the rank allows and
- * the unfused kernels otherwise. All calls on one GPU share its array, which
+ * with SSMAP_KERNEL_GEMM; AUTO chooses as for ssmap_solve_device, with the
+ * unfused kernels where that would be the GEMM path. All calls on one GPU share its array, which
  * keeps the last call's contents: calls that overlap on one GPU (other streams,
  * other threads or contexts) race and must be serialised by the caller. */
 #define SSMAP_NOALLOC_MAX_BYTES (64ull << 20)
@@ -249,7 +256,7 @@ const char *ssmap_version(void);
  * (precision, padded rank, planar or volumetric grid) share each fused
  * launch: one launch walks the bricks of all of them, so many small problems
  * fill the GPU. Each problem's iterates are exactly those of ssmap_solve on
- * it alone (same kernels, same arithmetic order).
+ * it alone with kernel SSMAP_KERNEL_FUSED (same kernels, same arithmetic order).
  * ---------------------------------------------------------------------- */
 typedef struct ssmap_batch ssmap_batch;
 

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "SSMAP_OK", -1: "SSMAP_EINVAL", -2: "SSMAP_ENOMEM", -3: "SSMA
                 -4: "SSMAP_ENONFINITE", -5: "SSMAP_ENODEV"}
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-KERNELS = {"auto": 0, "unfused": 1, "fused": 2, "gemm": 3}
+KERNELS = {"auto": 0, "unfused": 1, "fused": 2, "gemm": 3, "split": 4}
 SSMAP_KEEP_AUX = 1
 SSMAP_MONITOR_PRIMAL = 4
 MAX_HIST = 512

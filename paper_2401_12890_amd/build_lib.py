@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libssmap.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["ssmap.cpp", "server.cpp", "mask.cpp", "svd.cpp", "kernels_common.hip",
-           "kernels_fused.hip", "kernels_gemm.hip"]
+           "kernels_fused.hip", "kernels_gemm.hip", "kernels_split.hip"]
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++20", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 

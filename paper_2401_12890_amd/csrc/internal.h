@@ -97,6 +97,23 @@ inline bool fused_tail(int mode, int RP, int r) {
 }
 void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vector<uint16_t> &Vop);
 
+// Small problems split over spectral chunks (kernels_split.hip): one workgroup
+// per (brick, chunk). The r-vectors travel as partial products: pin holds the
+// per-chunk partials of y^k ([chunk][rank][voxel], RP x N per chunk), win/yin
+// w^{k-1} and y^{k-1}; the launch writes its chunks' partials of y^{k+1} to
+// pout and, from the chunk-0 workgroups, w^k and y^k to wout/yout.
+struct SplitArgs {
+    IterArgs a;
+    const void *pin;
+    void *pout;
+    const void *win;
+    void *wout;
+    const void *yin;
+    void *yout;
+};
+bool launch_split(int mode, const SplitArgs &sa, FusedShape sh, const TileRef *tiles, int ntiles,
+                  hipStream_t s);   // false: no such mode or shape
+
 // f and d around a fused iteration (see kernels_common.hip):
 // pre: t = z^k + V_r w^k and, if f != NULL, f = t - dprev / beta (dprev NULL: d^k = 0;
 // f may alias dprev); post: t <- beta (t - z^{k+1}) = d^{k+1}.

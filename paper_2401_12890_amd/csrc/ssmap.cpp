@@ -259,6 +259,7 @@ struct Plan {
     int mode, r, RP;
     double xi, tau, beta, lam;
     bool fused;
+    bool split;        // small problems: the fused step split over chunks (kernels_split.hip)
     bool gemm;         // exact-rank path: contractions as GEMMs (ranks above 32)
     int Qg, Rg;        // its padded node and rank counts (multiples of 128)
 };
@@ -279,7 +280,7 @@ void validate_steps(ssmap_ctx *c, double lambda, const ssmap_steps *st, int iter
     if (st->precision < SSMAP_FP64 || st->precision > SSMAP_BF16X3)
         fail(SSMAP_EINVAL, "unknown precision");
     if (st->check_every < 0) fail(SSMAP_EINVAL, "check_every must be >= 0");
-    if (st->kernel < SSMAP_KERNEL_AUTO || st->kernel > SSMAP_KERNEL_GEMM)
+    if (st->kernel < SSMAP_KERNEL_AUTO || st->kernel > SSMAP_KERNEL_SPLIT)
         fail(SSMAP_EINVAL, "unknown kernel");
     if (!(std::isfinite(st->stop_tol) && st->stop_tol >= 0))
         fail(SSMAP_EINVAL, "stop_tol must be finite and >= 0");
@@ -287,7 +288,17 @@ void validate_steps(ssmap_ctx *c, double lambda, const ssmap_steps *st, int iter
         fail(SSMAP_EINVAL, "stop_tol needs check_every > 0 and no SSMAP_KEEP_AUX");
 }
 
-Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
+// Bricks of a grid for a brick shape (without a mask).
+int64_t brick_count(const Grid &g, FusedShape sh) {
+    return ((g.nx + 15) / 16) * ((g.ny + sh.ty - 1) / sh.ty) * ((g.nz + sh.tz - 1) / sh.tz);
+}
+// AUTO takes the chunk split up to this many bricks and chunks (a 32 x 32 grid with
+// Q = 100 is 8 bricks of 16 x 8 and 7 chunks)
+constexpr int64_t kSplitMaxBricks = 32;
+constexpr int kSplitMaxChunks = 32;
+
+// allow_split: false for batches, whose shared launches run the fused kernel.
+Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_split = true) {
     Plan p{};
     p.mode = st->precision;
     p.r = rank_rule(c->s, st->rank);
@@ -306,6 +317,20 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st) {
     if (st->kernel == SSMAP_KERNEL_GEMM && !gemm_ok)
         fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without aux output or primal residual");
     p.gemm = st->kernel == SSMAP_KERNEL_GEMM || (st->kernel == SSMAP_KERNEL_AUTO && !can_fuse && gemm_ok);
+    // Chunk split: float64 / float32 grids with few bricks and short spectra, where
+    // one workgroup per brick would leave most CUs idle (no aux output or primal
+    // residual: f and d are formed from the fused r-vector state)
+    const int64_t esz = p.mode == MODE_FP64 ? 8 : 4;
+    const bool split_ok = can_fuse && p.mode != MODE_BF16X3 && c->nchunk >= 2 &&
+                          (int64_t)c->nchunk * p.RP * c->g.N * esz < ((int64_t)1 << 31) &&
+                          !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL));
+    if (st->kernel == SSMAP_KERNEL_SPLIT && !split_ok)
+        fail(SSMAP_EINVAL, "the split kernel runs float64 or float32 with at least two chunks, "
+                           "no aux output and no primal residual");
+    p.split = st->kernel == SSMAP_KERNEL_SPLIT ||
+              (st->kernel == SSMAP_KERNEL_AUTO && allow_split && split_ok && c->nchunk <= kSplitMaxChunks &&
+               brick_count(c->g, default_shape(p.mode, c->g)) <= kSplitMaxBricks);
+    if (p.split) p.fused = true;
     p.Qg = (c->Q + 127) / 128 * 128;
     p.Rg = (p.r + 127) / 128 * 128;
     return p;
@@ -331,6 +356,8 @@ struct Prepared {
     mutable void *dbuf = nullptr, *tbuf = nullptr;
     double *monpart = nullptr;    // fused path: per-brick (z^{k+1} - z^k)^2 of a monitored iteration
     int ntiles = 0;
+    // chunk split: partials of y (two iterations), w^{k-1} and y^{k-1} (two each)
+    void *sp[2] = {nullptr, nullptr}, *sw[2] = {nullptr, nullptr}, *sy[2] = {nullptr, nullptr};
     const void *dM = nullptr;
     int iters = 0;
     double stop_tol = 0.0;
@@ -365,15 +392,20 @@ void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
         launch_zero(P.auxA, (size_t)c->Qp * N, (int)esz, s);
         launch_zero(P.auxB, (size_t)c->Qp * N, (int)esz, s);
     }
+    if (pl.split) {          // y^0 = 0 (its partials), w^{-1} = y^{-1} = 0: then w^0 = a.h
+        launch_zero(P.sp[0], (size_t)c->nchunk * pl.RP * N, (int)esz, s);
+        launch_zero(P.sw[0], (size_t)pl.RP * N, (int)esz, s);
+        launch_zero(P.sy[0], (size_t)pl.RP * N, (int)esz, s);
+    }
     HIPC(c, hipGetLastError());
 }
 
 Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s);
 
 Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *st, int iters,
-                 hipStream_t s) {
+                 hipStream_t s, bool allow_split = true) {
     Prepared P;
-    P.pl = make_plan(c, lambda, st);
+    P.pl = make_plan(c, lambda, st, allow_split);
     P.monitor = st->check_every > 0;
     P.check_every = st->check_every;
     P.stop_tol = st->stop_tol;
@@ -418,6 +450,10 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         need.push_back({"tiles", nb * sizeof(TileRef)});
         if (P.monitor) need.push_back({"monpart", nb * 8});
     }
+    if (pl.split)
+        for (const char *nm : {"sp0", "sp1"}) need.push_back({nm, (size_t)c->nchunk * rbytes});
+    if (pl.split)
+        for (const char *nm : {"sw0", "sw1", "sy0", "sy1"}) need.push_back({nm, rbytes});
     if (pl.mode == MODE_BF16X3) {
         need.push_back({"Vhi", (size_t)Qp * RP * 2});
         need.push_back({"Vlo", (size_t)Qp * RP * 2});
@@ -472,6 +508,13 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     }
     P.dbuf = P.auxA;
     P.tbuf = P.auxB;
+    if (pl.split) {
+        const char *names[3][2] = {{"sp0", "sp1"}, {"sw0", "sw1"}, {"sy0", "sy1"}};
+        void **dst[3] = {P.sp, P.sw, P.sy};
+        for (int b = 0; b < 3; ++b)
+            for (int k = 0; k < 2; ++k)
+                dst[b][k] = ensure(c, names[b][k], b == 0 ? (size_t)c->nchunk * rbytes : rbytes);
+    }
     HIPC(c, hipStreamSynchronize(s));         // host staging vectors are locals
 
     IterArgs &a = P.a;
@@ -499,7 +542,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     S.rank = r;
     S.rank_padded = RP;
     S.precision = pl.mode;
-    S.kernel = pl.fused ? SSMAP_KERNEL_FUSED : SSMAP_KERNEL_UNFUSED;
+    S.kernel = pl.split ? SSMAP_KERNEL_SPLIT : pl.fused ? SSMAP_KERNEL_FUSED : SSMAP_KERNEL_UNFUSED;
     S.xi_p = pl.xi;
     S.tau = pl.tau;
     S.dtd_norm = c->dtd_norm;
@@ -744,11 +787,14 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
         // the iteration left y^{k+1} = V_r^T z^{k+1} in its r-vector state; the fused
         // kernel also summed (z^{k+1} - z^k)^2 per brick
         m.z = P.z[(k + 1) & 1];
-        m.y = P.a.y;
-        if (pl.fused) {
+        if (pl.split) {              // y^{k+1} exists only as per-chunk partials
+            m.zprev = P.z[k & 1];
+        } else if (pl.fused) {
+            m.y = P.a.y;
             m.dzpart = P.monpart;
             m.ndz = P.ntiles;
         } else {
+            m.y = P.a.y;
             m.zprev = P.z[k & 1];
         }
         m.f = P.primal ? P.tbuf : nullptr;
@@ -807,6 +853,19 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
     const Plan &pl = P.pl;
     if (pl.gemm) {
         step_gemm(c, P, k, s);
+        return;
+    }
+    if (pl.split) {
+        SplitArgs sa{};
+        sa.a = args_for(P, k);
+        sa.pin = P.sp[k & 1];
+        sa.pout = P.sp[(k + 1) & 1];
+        sa.win = P.sw[k & 1];
+        sa.wout = P.sw[(k + 1) & 1];
+        sa.yin = P.sy[k & 1];
+        sa.yout = P.sy[(k + 1) & 1];
+        if (!launch_split(pl.mode, sa, L->shape, L->tiles, L->ntiles, s))
+            fail(SSMAP_EINVAL, "no split kernel for this precision and brick shape");
         return;
     }
     IterArgs a = args_for(P, k);
@@ -1014,7 +1073,7 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
     Ps.reserve(nj);
     for (int j = 0; j < nj; ++j) {
         try {
-            Ps.push_back(prepare(b->jobs[j], dM[j], lambda[j], &steps[j], iters, s));
+            Ps.push_back(prepare(b->jobs[j], dM[j], lambda[j], &steps[j], iters, s, false));
         } catch (const Fail &f) {
             throw Fail{f.status, "job " + std::to_string(j) + ": " + f.msg};
         }
@@ -1246,13 +1305,13 @@ ssmap_status ssmap_solve_device_noalloc(ssmap_ctx *ctx, const void *dM, double l
         if (!ctx->scratch)
             fail(SSMAP_EDEVICE, std::string("scratch array lookup failed: ") +
                                     hipGetErrorString(ctx->scratch_err));
-        // AUTO: the fused kernel where it exists, else the unfused one (the GEMM
-        // path needs allocations of its own layouts)
+        // AUTO as in ssmap_solve_device, except that where it would take the GEMM
+        // path (its own layouts) the unfused kernels run
         ssmap_steps st = *steps;
         if (st.kernel == SSMAP_KERNEL_AUTO) {
             const int r = rank_rule(ctx->s, st.rank);
-            st.kernel = fused_supported(st.precision, (r + 15) / 16 * 16, ctx->g.N)
-                            ? SSMAP_KERNEL_FUSED : SSMAP_KERNEL_UNFUSED;
+            if (!fused_supported(st.precision, (r + 15) / 16 * 16, ctx->g.N))
+                st.kernel = SSMAP_KERNEL_UNFUSED;
         }
         struct On {
             ssmap_ctx *c;
