@@ -324,8 +324,10 @@ void ssmap_batch_destroy(ssmap_batch *b);
  * above of state moved per iteration) advance together, one iteration per shared
  * fused launch; a job joins its class at an iteration boundary and leaves
  * after its last iteration while the others keep running (continuous
- * batching). Classes are spread over up to four HIP streams and progress
- * independently of one another. A served job's result is exactly that of
+ * batching). Jobs of the large band iterate one at a time, in arrival order
+ * (two of them sharing the GPU would each take about twice as long); small and
+ * middle jobs run beside them. Classes are spread over up to four HIP streams
+ * and progress independently of one another. A served job's result is exactly that of
  * ssmap_solve_device with kernel SSMAP_KERNEL_FUSED on the same input (same
  * kernels, same arithmetic order). A server is not thread-safe.
  * ---------------------------------------------------------------------- */

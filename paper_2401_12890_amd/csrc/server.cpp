@@ -215,6 +215,13 @@ struct ssmap_server {
     std::vector<Job> jobs;
     std::deque<int64_t> queue;
     std::vector<Class> classes;
+    // Jobs of the large size band iterate one at a time, in arrival order: two such
+    // jobs sharing the GPU would each take about twice as long, so the later one
+    // gains nothing while the earlier one finishes late. Admitted large jobs wait
+    // here (state resident, projection done) until the running one retires; small
+    // and middle jobs keep running beside it.
+    std::deque<int64_t> large_wait;
+    int64_t large_running = -1;
     hipEvent_t epoch = nullptr;
     Clock::time_point t0;
     ssmap_server_stats stats{};
@@ -441,6 +448,23 @@ void upload_tables(ssmap_server *sv, Class &C) {
     C.dirty = false;
 }
 
+// A job starts iterating: it joins its class at the class's current round.
+void start_job(ssmap_server *sv, int64_t id) {
+    Job &j = sv->jobs[id];
+    Class &C = sv->classes[j.cls];
+    j.r0 = C.round;
+    C.members.push_back(id);
+    C.dirty = true;
+}
+
+// The next waiting large job, if none is running.
+void start_next_large(ssmap_server *sv) {
+    if (sv->large_running >= 0 || sv->large_wait.empty()) return;
+    sv->large_running = sv->large_wait.front();
+    sv->large_wait.pop_front();
+    start_job(sv, sv->large_running);
+}
+
 // Output, flag read-back, completion event and release of the job's memory.
 void retire(ssmap_server *sv, Job &j, int li) {
     hipStream_t s = sv->lanes[li].s;
@@ -515,9 +539,12 @@ bool admit_one(ssmap_server *sv) {
         retire(sv, j, li);
         return true;
     }
-    j.r0 = C.round;
-    C.members.push_back(id);
-    C.dirty = true;
+    if (C.band == 2) {
+        sv->large_wait.push_back(id);
+        start_next_large(sv);
+    } else {
+        start_job(sv, id);
+    }
     return true;
 }
 
@@ -592,9 +619,14 @@ void run_class(ssmap_server *sv, Class &C, double horizon_ms) {
         for (size_t k = 0; k < C.members.size();) {
             Job &j = sv->jobs[C.members[k]];
             if (C.round - j.r0 == j.iters) {
+                const int64_t id = C.members[k];
                 retire(sv, j, C.lane);
                 C.members.erase(C.members.begin() + (ptrdiff_t)k);
                 C.dirty = true;
+                if (id == sv->large_running) {
+                    sv->large_running = -1;
+                    start_next_large(sv);    // may join this class at once
+                }
             } else {
                 ++k;
             }
