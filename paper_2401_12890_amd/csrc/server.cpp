@@ -21,6 +21,7 @@
 
 #include "../../include/ssmap.h"
 #include "internal.h"
+#include "slab.h"
 
 #include <hip/hip_runtime_api.h>
 
@@ -40,7 +41,6 @@ using namespace ssmap;
 
 namespace {
 
-constexpr int kMaxLanes = 4;
 constexpr size_t kAlign = 256;
 constexpr size_t kStagingBytes = (size_t)64 << 20;
 constexpr int kFlagSlots = 4096;
@@ -56,67 +56,6 @@ struct SvFail {
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 using Clock = std::chrono::steady_clock;
-
-struct Fence {
-    uint64_t seq[kMaxLanes] = {};
-};
-void merge_fence(Fence &a, const Fence &b) {
-    for (int i = 0; i < kMaxLanes; ++i) a.seq[i] = std::max(a.seq[i], b.seq[i]);
-}
-
-// First-fit allocator over [0, cap). A free range carries the fences of the
-// work that used it last (merged conservatively when ranges coalesce).
-class Slab {
-  public:
-    void init(size_t cap) {
-        free_.clear();
-        free_[0] = Range{cap, Fence{}};
-        used_ = peak_ = 0;
-    }
-    bool alloc(size_t n, size_t &off, Fence &f) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second.size < n) continue;
-            off = it->first;
-            f = it->second.fence;
-            const size_t rest = it->second.size - n;
-            free_.erase(it);
-            if (rest) free_[off + n] = Range{rest, f};
-            used_ += n;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n, const Fence &f) {
-        used_ -= n;
-        Range r{n, f};
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            r.size += next->second.size;
-            merge_fence(r.fence, next->second.fence);
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second.size == off) {
-                prev->second.size += r.size;
-                merge_fence(prev->second.fence, r.fence);
-                return;
-            }
-        }
-        free_[off] = r;
-    }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-
-  private:
-    struct Range {
-        size_t size;
-        Fence fence;
-    };
-    std::map<size_t, Range> free_;
-    size_t used_ = 0, peak_ = 0;
-};
 
 struct Lane {
     hipStream_t s = nullptr;
