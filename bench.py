@@ -570,7 +570,8 @@ def main():
     per_launch_ms = (sum(loop_ms) / len(loop_ms)) / iters
     alg = alg_bytes_per_voxel_iter(prob.Q, r, wbytes) * prob.N
     achieved = alg / (per_launch_ms / 1e3) / 1e9
-    kern_name = {1: "k_update+k_projw (unfused)", 2: "k_fused", 3: "k_gemm_tn (GEMM path)",
+    kern_name = {1: "k_update+k_projw (unfused)", 2: "k_fused",
+                 3: "hipBLASLt GEMM (GEMM path)" if st.get("gemm_library") else "k_gemm_tn (GEMM path)",
                  4: "k_split (chunk split)"}[st["kernel"]]
     if st["kernel"] == 3:
         # dominant kernel: the GEMM (two launches per iteration, equal flops), timed by the

@@ -134,7 +134,8 @@ typedef struct {
     double iterate_ms;      /* the iteration loop, monitoring included             */
     double output_ms;       /* z^K to the voxel-major output                        */
     double device_bytes;    /* device memory held by the context                   */
-    double gemm_ms;         /* GEMM path: time in the two products (events)        */
+    double gemm_ms;         /* GEMM path: time in the two products (events; with the
+                               fused kernels, their epilogues included)             */
     double gemm_flops;      /* GEMM path: flops of the two products as issued      */
     int hist_iter[SSMAP_MAX_HIST];
     double hist_objective[SSMAP_MAX_HIST];  /* 1/2||m - K_r z||^2 + lambda R(z)    */
@@ -145,6 +146,9 @@ typedef struct {
                                                reference set, else -1                */
     double hist_dfcs_f[SSMAP_MAX_HIST];     /* ||f^k - f*|| / ||f*|| (reference and
                                                SSMAP_MONITOR_PRIMAL), else -1        */
+    int gemm_library;       /* GEMM path: 1 when the two products ran as library GEMMs
+                               (hipBLASLt) with the elementwise steps as separate
+                               passes, 0 for the library's own fused MFMA kernels   */
 } ssmap_stats;
 
 /* Factor the dictionary and prepare a context for a fixed grid.

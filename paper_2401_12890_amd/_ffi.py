@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("hist_znorm", ctypes.c_double * MAX_HIST),
                 ("hist_primal", ctypes.c_double * MAX_HIST),
                 ("hist_dfcs", ctypes.c_double * MAX_HIST),
-                ("hist_dfcs_f", ctypes.c_double * MAX_HIST)]
+                ("hist_dfcs_f", ctypes.c_double * MAX_HIST),
+                ("gemm_library", ctypes.c_int)]
 
 
 class BatchStats(ctypes.Structure):
@@ -265,7 +266,7 @@ def ssmap_get_stats(ctx: int) -> dict:
                 gemm_ms=s.gemm_ms, gemm_flops=s.gemm_flops, hist_iter=list(s.hist_iter[:n]), hist_objective=list(s.hist_objective[:n]),
                 hist_dual=list(s.hist_dual[:n]), hist_znorm=list(s.hist_znorm[:n]),
                 hist_primal=list(s.hist_primal[:n]), hist_dfcs=list(s.hist_dfcs[:n]),
-                hist_dfcs_f=list(s.hist_dfcs_f[:n]))
+                hist_dfcs_f=list(s.hist_dfcs_f[:n]), gemm_library=s.gemm_library)
 
 
 def ssmap_get_singular_values(ctx: int) -> np.ndarray:

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libssmap.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["ssmap.cpp", "server.cpp", "mask.cpp", "svd.cpp", "kernels_common.hip",
-           "kernels_fused.hip", "kernels_gemm.hip", "kernels_split.hip"]
+           "kernels_fused.hip", "kernels_gemm.hip", "kernels_split.hip", "libgemm.cpp"]
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++20", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
@@ -49,7 +49,8 @@ def build(verbose: bool = False, csrc: str = CSRC, out: str = LIB, objdir: str |
         for f in [ex.submit(run, c) for c in cmds]:
             f.result()
     tmp = out + ".tmp"
-    run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"])
+    run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+        ["-L/opt/rocm/lib", "-lhipblaslt", "-lpthread"])
     os.replace(tmp, out)
     return out
 

@@ -204,7 +204,21 @@ bool launch_gemm_u(bool bf16, const void *A, const void *B, int K, const float *
 bool launch_gemm_y(bool bf16, const void *A, const void *B, int K, int64_t N, int Rg, const float *ah,
                    float *sv, float *w, uint16_t *ws, const float *bcoef, hipStream_t s);
 void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, int64_t N, int Rg,
-                            hipStream_t s);
+                            hipStream_t s, int nseg = 2);
+// The same epilogues as separate passes over a product left in memory by a library
+// GEMM (U: N x Qg, Y: N x Rg, voxel-major); splits are written hi | lo | hi.
+void launch_epi_z(const float *U, const float *z, float *zn, uint16_t *zs3, Grid g, int Qg, double tau,
+                  double lam2, double beta, const uint8_t *code, hipStream_t s);
+void launch_epi_w(const float *Y, int64_t N, int Rg, const float *ah, float *sv, float *w, uint16_t *ws3,
+                  const float *bcoef, hipStream_t s);
+// Library product (hipBLASLt): C[n][m] = sum_k A[m][k] B[n][k] for m < M, n < N,
+// k < K; A M x K and B N x K row-major, bf16 or float32, C float32 (N x M).
+// false when the library offers no algorithm for the shape.
+struct LibGemm;
+LibGemm *libgemm_create();
+void libgemm_destroy(LibGemm *g);
+bool libgemm_tn(LibGemm *g, bool bf16, const void *A, const void *B, float *C, int M, int64_t N, int K,
+                hipStream_t s);
 void launch_gemm_output(const float *z, void *F, bool to_double, int64_t N, int Q, int Qg,
                         hipStream_t s);
 

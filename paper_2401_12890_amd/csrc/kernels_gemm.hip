@@ -61,8 +61,10 @@ __device__ __forceinline__ void split2(float v, uint16_t *dst, int k, int L) {
     dst[L + k] = l;
 }
 
-// The same split of 4 consecutive values (k a multiple of 4): two 8-byte stores.
-__device__ __forceinline__ void split2x4(const v4f &v, uint16_t *dst, int k, int L) {
+// The same split of 4 consecutive values (k a multiple of 4): two 8-byte stores,
+// three with nseg = 3 (hi | lo | hi: the operand of a library product, whose K
+// does not wrap).
+__device__ __forceinline__ void split2x4(const v4f &v, uint16_t *dst, int k, int L, int nseg = 2) {
     unsigned h[4], l[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -73,6 +75,7 @@ __device__ __forceinline__ void split2x4(const v4f &v, uint16_t *dst, int k, int
     const uint2 ll{l[0] | (l[1] << 16), l[2] | (l[3] << 16)};
     *(uint2 *)(dst + k) = hh;
     *(uint2 *)(dst + L + k) = ll;
+    if (nseg == 3) *(uint2 *)(dst + 2 * L + k) = hh;
 }
 
 // Epilogue of u = V_r w: z^{k+1} = max(0, z - tau (2 lambda (deg z - sum of
@@ -85,6 +88,7 @@ struct EpiZ {
     int Qg;
     float tau, lam2, beta;
     const uint8_t *code;     // mask codes or null
+    int nseg;                // split segments per row: 2 (hi | lo) or 3 (hi | lo | hi)
 };
 
 // Per-voxel part of the z-update, shared by the voxel's nodes: the rows of z
@@ -152,7 +156,7 @@ __device__ __forceinline__ void epilogue_batch(const EpiZ &e, const ColZ &c, con
             r[i] = (v > 0.0f && c.inside) ? v : 0.0f;
         }
         *(v4f *)(e.zn + c.n * (int64_t)e.Qg + q[g]) = r;
-        if (e.zs) split2x4(r, e.zs + c.n * 2 * (int64_t)e.Qg, q[g], e.Qg);
+        if (e.zs) split2x4(r, e.zs + c.n * e.nseg * (int64_t)e.Qg, q[g], e.Qg, e.nseg);
     }
 }
 
@@ -166,6 +170,7 @@ struct EpiW {
     uint16_t *ws;            // its bf16 split (bf16x3), or null
     const float *bcoef;
     int Rg;
+    int nseg;                // split segments per row: 2 or 3
 };
 
 struct ColW {
@@ -193,7 +198,7 @@ __device__ __forceinline__ void epilogue_batch(const EpiW &e, const ColW &c, con
             s1[t] = y[g][t] + w[t];
         }
         *(v4f *)(e.s + c.o + q[g]) = s1;
-        if (e.ws) split2x4(w, e.ws + 2 * c.o, q[g], e.Rg);
+        if (e.ws) split2x4(w, e.ws + e.nseg * c.o, q[g], e.Rg, e.nseg);
         else *(v4f *)(e.w + c.o + q[g]) = w;
     }
 }
@@ -357,14 +362,42 @@ k_gemm_tn(const T *__restrict__ A, const T *__restrict__ B, int M, int K, int KB
 // optionally the bf16 split of the result.
 __global__ void __launch_bounds__(256)
 k_gemm_from_ranks(const float *__restrict__ src, int RP, float *__restrict__ dst, uint16_t *__restrict__ ds,
-                  int64_t N, int Rg) {
+                  int64_t N, int Rg, int nseg) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= N * Rg) return;
     const int64_t n = idx / Rg;
     const int i = (int)(idx % Rg);
     const float v = i < RP ? src[(size_t)i * N + n] : 0.0f;
     dst[idx] = v;
-    if (ds) split2(v, ds + (size_t)n * 2 * Rg, i, Rg);
+    if (ds) {
+        uint16_t *row = ds + (size_t)n * nseg * Rg;
+        split2(v, row, i, Rg);
+        if (nseg == 3) row[2 * Rg + i] = row[i];
+    }
+}
+
+// The epilogues on a product that a library GEMM left in memory (voxel-major,
+// P[n][m], m over M = Qg or Rg): one lane per voxel and 4 consecutive rows m.
+__global__ void __launch_bounds__(256)
+k_epi_z(EpiZ e, const float *__restrict__ U) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = e.Qg / 4;
+    if (idx >= e.g.N * per) return;
+    const int64_t n = idx / per;
+    const int q[1] = {4 * (int)(idx % per)};
+    const v4f u[1] = {*(const v4f *)(U + n * (int64_t)e.Qg + q[0])};
+    epilogue_batch<1>(e, column(e, n), q, u);
+}
+
+__global__ void __launch_bounds__(256)
+k_epi_w(EpiW e, const float *__restrict__ Y, int64_t N) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = e.Rg / 4;
+    if (idx >= N * per) return;
+    const int64_t n = idx / per;
+    const int q[1] = {4 * (int)(idx % per)};
+    const v4f y[1] = {*(const v4f *)(Y + n * (int64_t)e.Rg + q[0])};
+    epilogue_batch<1>(e, column(e, n), q, y);
 }
 
 // z (N x Qg) -> F (N x Q), float32 or float64 output.
@@ -412,20 +445,32 @@ bool gemm_tn(bool bf16, const void *A, const void *B, int M, int K, int KB, int6
 bool launch_gemm_u(bool bf16, const void *A, const void *B, int K, const float *z, float *zn,
                    uint16_t *zs, Grid g, int Qg, double tau, double lam2, double beta,
                    const uint8_t *code, hipStream_t s) {
-    const EpiZ e{z, zn, zs, g, Qg, (float)tau, (float)lam2, (float)beta, code};
+    const EpiZ e{z, zn, zs, g, Qg, (float)tau, (float)lam2, (float)beta, code, 2};
     return gemm_tn(bf16, A, B, Qg, K, bf16 ? K / 3 * 2 : K, g.N, e, s);
 }
 
 bool launch_gemm_y(bool bf16, const void *A, const void *B, int K, int64_t N, int Rg, const float *ah,
                    float *sv, float *w, uint16_t *ws, const float *bcoef, hipStream_t s) {
-    const EpiW e{ah, sv, w, ws, bcoef, Rg};
+    const EpiW e{ah, sv, w, ws, bcoef, Rg, 2};
     return gemm_tn(bf16, A, B, Rg, K, bf16 ? K / 3 * 2 : K, N, e, s);
 }
 
+void launch_epi_z(const float *U, const float *z, float *zn, uint16_t *zs3, Grid g, int Qg, double tau,
+                  double lam2, double beta, const uint8_t *code, hipStream_t s) {
+    const EpiZ e{z, zn, zs3, g, Qg, (float)tau, (float)lam2, (float)beta, code, 3};
+    hipLaunchKernelGGL(k_epi_z, dim3(nblocks(g.N * (Qg / 4), 256)), dim3(256), 0, s, e, U);
+}
+
+void launch_epi_w(const float *Y, int64_t N, int Rg, const float *ah, float *sv, float *w, uint16_t *ws3,
+                  const float *bcoef, hipStream_t s) {
+    const EpiW e{ah, sv, w, ws3, bcoef, Rg, 3};
+    hipLaunchKernelGGL(k_epi_w, dim3(nblocks(N * (Rg / 4), 256)), dim3(256), 0, s, e, Y, N);
+}
+
 void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, int64_t N, int Rg,
-                            hipStream_t s) {
+                            hipStream_t s, int nseg) {
     hipLaunchKernelGGL(k_gemm_from_ranks, dim3(nblocks(N * Rg, 256)), dim3(256), 0, s, src, RP, dst, ds,
-                       N, Rg);
+                       N, Rg, nseg);
 }
 
 void launch_gemm_output(const float *z, void *F, bool to_double, int64_t N, int Q, int Qg,

@@ -137,6 +137,8 @@ struct ssmap_ctx {
     } arena;
     void *scratch = nullptr;              // this device's scratch array (NULL: lookup failed)
     bool has_ref = false;                 // a reference map f* for DFCS is on the device ("fstar")
+    LibGemm *lg = nullptr;                // exact-rank path: the library products (hipBLASLt)
+    bool lg_tried = false;
     hipError_t scratch_err = hipSuccess;
 };
 
@@ -203,15 +205,16 @@ void *ensure(ssmap_ctx *c, const std::string &name, size_t bytes) {
     return p;
 }
 
-// The three timing events of GEMM-path iteration k (created on first use).
+// The four timing events of GEMM-path iteration k (created on first use): before
+// and after each of the two products.
 hipEvent_t *gemm_events(ssmap_ctx *c, int k) {
-    const size_t need = 3 * (size_t)(k + 1);
+    const size_t need = 4 * (size_t)(k + 1);
     while (c->gemm_ev.size() < need) {
         hipEvent_t e = nullptr;
         HIPC(c, hipEventCreate(&e));
         c->gemm_ev.push_back(e);
     }
-    return &c->gemm_ev[3 * (size_t)k];
+    return &c->gemm_ev[4 * (size_t)k];
 }
 
 // Device copy of the mask codes (NULL without a mask).
@@ -367,6 +370,9 @@ struct Prepared {
     float *gz[2] = {nullptr, nullptr}, *gs = nullptr, *gw = nullptr, *gah = nullptr, *gb = nullptr;
     uint16_t *gzs = nullptr, *gws = nullptr;
     const void *gAu = nullptr, *gAy = nullptr;
+    bool glib = false;            // products by the library (hipBLASLt), epilogues as passes
+    float *gU = nullptr, *gY = nullptr;   // their results: u (N x Qg), y (N x Rg)
+    int nseg = 2;                 // bf16 split segments per row (3 for the library products)
 };
 
 IterArgs args_for(const Prepared &P, int k) {
@@ -569,15 +575,28 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     const int Ku = bf ? 3 * Rg : Rg, Ky = bf ? 3 * Qg : Qg;
     const size_t esA = bf ? 2 : 4;
     const size_t zb = (size_t)N * Qg * 4, rb = (size_t)N * Rg * 4, tb = (size_t)N * RP * 4;
+    // the library products when hipBLASLt has an algorithm for both shapes
+    if (!c->lg_tried) {
+        c->lg = libgemm_create();
+        c->lg_tried = true;
+        (void)hipGetLastError();
+    }
+    P.glib = c->lg && libgemm_tn(c->lg, bf, nullptr, nullptr, nullptr, Qg, N, Ku, s) &&
+             libgemm_tn(c->lg, bf, nullptr, nullptr, nullptr, Rg, N, Ky, s);
+    P.nseg = P.glib ? 3 : 2;
     std::vector<std::pair<std::string, size_t>> need = {
         {"gz0", zb}, {"gz1", zb}, {"gs", rb}, {"gah", rb}, {"gt0", tb}, {"gt1", tb},
         {"gb", (size_t)Rg * 4}, {"gAu", (size_t)Qg * Ku * esA}, {"gAy", (size_t)Rg * Ky * esA},
         {"Ur", (size_t)Pm * r * 8}, {"sig", (size_t)RP * 8}, {"acoef", (size_t)RP * 8}, {"bad", 256}};
     if (bf) {
-        need.push_back({"gzs", (size_t)N * 2 * Qg * 2});
-        need.push_back({"gws", (size_t)N * 2 * Rg * 2});
+        need.push_back({"gzs", (size_t)N * P.nseg * Qg * 2});
+        need.push_back({"gws", (size_t)N * P.nseg * Rg * 2});
     } else {
         need.push_back({"gw", rb});
+    }
+    if (P.glib) {
+        need.push_back({"gU", zb});
+        need.push_back({"gY", rb});
     }
     if (P.monitor) {
         need.push_back({"t", (size_t)r * N * 8});
@@ -594,8 +613,8 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     float *gt0 = (float *)ensure(c, "gt0", tb), *gt1 = (float *)ensure(c, "gt1", tb);
     P.gb = (float *)ensure(c, "gb", (size_t)Rg * 4);
     if (bf) {
-        P.gzs = (uint16_t *)ensure(c, "gzs", (size_t)N * 2 * Qg * 2);
-        P.gws = (uint16_t *)ensure(c, "gws", (size_t)N * 2 * Rg * 2);
+        P.gzs = (uint16_t *)ensure(c, "gzs", (size_t)N * P.nseg * Qg * 2);
+        P.gws = (uint16_t *)ensure(c, "gws", (size_t)N * P.nseg * Rg * 2);
     } else {
         P.gw = (float *)ensure(c, "gw", rb);
     }
@@ -695,7 +714,11 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     launch_project(pl.mode, P.dM, Pm, Ur, P.sig, acoef, r, RP, N, P.t, P.mperp2, gt0, gt0, gt1,
                    bad, mask_dev(c), s);
     launch_gemm_from_ranks(gt0, RP, P.gah, nullptr, N, Rg, s);
-    launch_gemm_from_ranks(gt0, RP, P.gs, P.gws, N, Rg, s);
+    if (P.glib) {
+        P.gU = (float *)ensure(c, "gU", zb);
+        P.gY = (float *)ensure(c, "gY", rb);
+    }
+    launch_gemm_from_ranks(gt0, RP, P.gs, P.gws, N, Rg, s, P.nseg);
     if (!bf) launch_gemm_from_ranks(gt0, RP, P.gw, nullptr, N, Rg, s);
     for (int k = 0; k < 2; ++k) launch_zero(P.gz[k], (size_t)N * Qg, 4, s);
     HIPC(c, hipGetLastError());
@@ -718,15 +741,31 @@ void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     const float *z = P.gz[k & 1];
     float *zn = P.gz[(k + 1) & 1];
     hipEvent_t *ev = gemm_events(c, k);
+    const void *Bu = bf ? (const void *)P.gws : (const void *)P.gw;
+    const void *By = bf ? (const void *)P.gzs : (const void *)zn;
+    const int Ku = bf ? 3 * Rg : Rg, Ky = bf ? 3 * Qg : Qg;
+    if (P.glib) {
+        // library products, then the epilogues as passes over u and y
+        HIPC(c, hipEventRecord(ev[0], s));
+        if (!libgemm_tn(c->lg, bf, P.gAu, Bu, P.gU, Qg, N, Ku, s)) fail(SSMAP_EDEVICE, "hipBLASLt product failed");
+        HIPC(c, hipEventRecord(ev[1], s));
+        launch_epi_z(P.gU, z, zn, bf ? P.gzs : nullptr, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta, mask_dev(c), s);
+        HIPC(c, hipEventRecord(ev[2], s));
+        if (!libgemm_tn(c->lg, bf, P.gAy, By, P.gY, Rg, N, Ky, s)) fail(SSMAP_EDEVICE, "hipBLASLt product failed");
+        HIPC(c, hipEventRecord(ev[3], s));
+        launch_epi_w(P.gY, N, Rg, P.gah, P.gs, bf ? nullptr : P.gw, bf ? P.gws : nullptr, P.gb, s);
+        HIPC(c, hipGetLastError());
+        return;
+    }
     HIPC(c, hipEventRecord(ev[0], s));
-    if (!launch_gemm_u(bf, P.gAu, bf ? (const void *)P.gws : (const void *)P.gw, bf ? 3 * Rg : Rg, z, zn,
-                       P.gzs, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta, mask_dev(c), s))
+    if (!launch_gemm_u(bf, P.gAu, Bu, Ku, z, zn, P.gzs, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta,
+                       mask_dev(c), s))
         fail(SSMAP_EINVAL, "GEMM shape not supported");
     HIPC(c, hipEventRecord(ev[1], s));
-    if (!launch_gemm_y(bf, P.gAy, bf ? (const void *)P.gzs : (const void *)zn, bf ? 3 * Qg : Qg, N, Rg,
-                       P.gah, P.gs, P.gw, P.gws, P.gb, s))
-        fail(SSMAP_EINVAL, "GEMM shape not supported");
     HIPC(c, hipEventRecord(ev[2], s));
+    if (!launch_gemm_y(bf, P.gAy, By, Ky, N, Rg, P.gah, P.gs, P.gw, P.gws, P.gb, s))
+        fail(SSMAP_EINVAL, "GEMM shape not supported");
+    HIPC(c, hipEventRecord(ev[3], s));
 }
 
 void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
@@ -741,9 +780,10 @@ void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
     double ms = 0.0;
     for (int k = 0; k < iters; ++k) {
         hipEvent_t *ev = gemm_events(c, k);
-        ms += elapsed_ms(ev[0], ev[2]);
+        ms += elapsed_ms(ev[0], ev[1]) + elapsed_ms(ev[2], ev[3]);
     }
     S.gemm_ms = ms;
+    S.gemm_library = P.glib ? 1 : 0;
     const bool bf = P.pl.mode == MODE_BF16X3;
     S.gemm_flops = 2.0 * 2.0 * (double)P.pl.Qg * P.pl.Rg * (bf ? 3.0 : 1.0) * (double)c->g.N * iters;
 }
@@ -978,6 +1018,7 @@ void free_ctx(ssmap_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->gemm_ev) (void)hipEventDestroy(e);
+    libgemm_destroy(c->lg);
     if (c->host_stats) (void)hipHostFree(c->host_stats);
     delete c;
 }
