@@ -457,107 +457,134 @@ __device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, unsigned off, T
     }
 }
 
-// The same sums for the chunked layout when the iteration left y: a streaming
-// pass. grid.y = chunk; a block takes whole rows of the grid (fixed y, z) in
-// turn, each lane one quarter (four values) of a voxel's 16-node chunk row, so
-// a block reads a row's chunk as one contiguous run, like a copy. The three
-// forward neighbours of a value are the same quarter at voxel n + 1, n + nx,
-// n + nx ny (read through the caches). The squares are summed in the state
-// precision over a tile of up to 8 rows, then accumulated in float64. The
-// per-voxel data term from y and t is spread over all blocks.
-template <typename T>
+// The same sums for the chunked layout when the iteration left y, in one pass
+// that reads each value of z about once. A column is one 16 x 16 voxel tile of
+// one chunk over all z-planes; a block marches a column along z. Each lane holds
+// one quarter (four values) of a voxel's 16-node chunk row in four rows of the
+// tile (rows 4 wave .. 4 wave + 3). The x neighbour comes from the lane four
+// places on (the tile's last column reads the next tile's first voxel), the y
+// neighbour from the lane's next row (its last row reads the row after it, which
+// the next wave also loads), and the z neighbour is the next plane, which the
+// block loads for this plane and keeps for the next. Workgroups are dealt to the
+// eight XCDs in turn (block b on XCD b mod 8): each XCD takes a contiguous run of
+// columns and its blocks march neighbouring columns side by side, so the halo
+// rows one block reads are those its neighbours load at about the same time,
+// through the XCD's L2. Squares are summed in the state precision over a plane,
+// then accumulated in float64; the per-voxel data term from y and t is spread
+// over all blocks. EXTRA: zprev, f or the reference map may be given (the build
+// without them holds fewer registers and runs more waves).
+constexpr int MT_X = 16, MT_Y = 16, MT_RW = 4;
+template <typename T, bool EXTRA>
 __global__ void __launch_bounds__(256)
-k_monitor_stream(MonArgs a, double *__restrict__ partial) {
+k_monitor_march(MonArgs a, double *__restrict__ partial) {
     const uint32_t N = (uint32_t)a.g.N, nx = (uint32_t)a.g.nx, ny = (uint32_t)a.g.ny,
                    nz = (uint32_t)a.g.nz, nxy = nx * ny;
     const unsigned cbytes = (unsigned)((size_t)N * QC * sizeof(T));
-    const bool hasp = a.zprev != nullptr, hasf = a.f != nullptr;
+    constexpr unsigned kFar = 0x80000000u;   // beyond every chunk: the buffer load returns 0
+    const bool hasp = EXTRA && a.zprev != nullptr, hasf = EXTRA && a.f != nullptr,
+               hasr = EXTRA && a.fstar != nullptr;
     auto in = [&](uint32_t v) { return !a.code || (a.code[v] & 0x80u) != 0; };
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t qd = lane & 3, xv = lane >> 2;
     double acc[ST_COUNT];
 #pragma unroll
     for (int k = 0; k < ST_COUNT; ++k) acc[k] = 0.0;
-    // rows in tiles of (one y, up to 8 consecutive z), tiles y-fastest within a band of
-    // 8 z-planes, for each chunk in turn. The grid holds about as many blocks as run at
-    // once, and each takes a contiguous range of (chunk, tile) items and walks each
-    // tile along z, so the z neighbour row is the next one it reads and the y neighbour
-    // row comes 8 rows later (both still in its L2).
-    const uint32_t rowq = 4 * nx, nzb = (nz + 7) / 8, ntile = ny * nzb;
-    const uint32_t total = ntile * (uint32_t)a.nchunk;
-    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
-    const uint32_t w0 = blockIdx.x * per, w1 = min(total, w0 + per);
-    const unsigned sx = QC * sizeof(T), sy = nx * QC * sizeof(T), sz = nxy * QC * sizeof(T);
-    for (uint32_t w = w0; w < w1; ++w) {
-        const int c = (int)(w / ntile);
-        const uint32_t tile = w - (uint32_t)c * ntile;
-        const uint32_t yy = tile % ny, zb = (tile / ny) * 8;
+    const uint32_t ntx = (nx + MT_X - 1) / MT_X, nty = (ny + MT_Y - 1) / MT_Y, ntile = ntx * nty;
+    // columns of this block: XCD x = b mod 8 owns [x cx, (x + 1) cx); its gx blocks take
+    // columns l, l + gx, ... of that run (gridDim.x = 8 gx)
+    const uint32_t ncol = ntile * (uint32_t)a.nchunk, cx = (ncol + 7) / 8, gx = gridDim.x / 8;
+    const uint32_t xcd = blockIdx.x & 7, col_end = min(ncol, (xcd + 1) * cx);
+    const unsigned sx = QC * sizeof(T), sz = nxy * QC * sizeof(T);
+    T cur[MT_RW][4];
+    bool have = false;
+    uint32_t col = xcd * cx + (blockIdx.x >> 3), zz = 0;
+    for (; col < col_end; zz = zz + 1 < nz ? zz + 1 : 0, col += zz == 0 ? gx : 0) {
+        const uint32_t c = col / ntile, tile = col - c * ntile;
+        const uint32_t x = (tile % ntx) * MT_X + xv, y0 = (tile / ntx) * MT_Y + MT_RW * wave;
         const size_t cbase = (size_t)c * N * QC;
         const __amdgpu_buffer_rsrc_t zr = mon_rsrc((const T *)a.z + cbase, cbytes);
-        const __amdgpu_buffer_rsrc_t pr = mon_rsrc(hasp ? (const T *)a.zprev + cbase : nullptr,
-                                                   hasp ? cbytes : 0);
-        const __amdgpu_buffer_rsrc_t fr = mon_rsrc(hasf ? (const T *)a.f + cbase : nullptr,
-                                                   hasf ? cbytes : 0);
-        // squares of one tile summed in the state type, then added in float64
+        const bool xok = x < nx, znext = zz + 1 < nz;
+        // byte offset of this lane's quarter at row y0 + j of plane zz (kFar outside the grid)
+        unsigned off[MT_RW];
+#pragma unroll
+        for (int j = 0; j < MT_RW; ++j)
+            off[j] = (xok && y0 + j < ny) ? ((x + nx * (y0 + j + ny * zz)) * QC + 4 * qd) * (unsigned)sizeof(T)
+                                          : kFar;
+        if (!have)
+#pragma unroll
+            for (int j = 0; j < MT_RW; ++j) bload4<T>(zr, off[j], cur[j]);
+        // the next plane (z neighbours), the row after the lane's last (y neighbours) and,
+        // in the tile's last column, the voxel after it (x neighbours)
+        T nxt[MT_RW][4], yx[4], hx[MT_RW][4];
+#pragma unroll
+        for (int j = 0; j < MT_RW; ++j) bload4<T>(zr, znext && off[j] != kFar ? off[j] + sz : kFar, nxt[j]);
+        bload4<T>(zr, (xok && y0 + MT_RW < ny) ? ((x + nx * (y0 + MT_RW + ny * zz)) * QC + 4 * qd) *
+                                                     (unsigned)sizeof(T)
+                                               : kFar, yx);
+        const bool halo = xv == MT_X - 1 && x + 1 < nx;
+#pragma unroll
+        for (int j = 0; j < MT_RW; ++j) {
+            if (halo) bload4<T>(zr, off[j] != kFar ? off[j] + sx : kFar, hx[j]);
+            else
+#pragma unroll
+                for (int s = 0; s < 4; ++s) hx[j][s] = 0;
+        }
         T zsq = 0, reg = 0, dsq = 0, psq = 0;
-        int bad = 0;
-        for (uint32_t zz = zb; zz < min(zb + 8, nz); ++zz) {
-            const uint32_t nrow = (yy + ny * zz) * nx;
-            const bool rowy = yy + 1 < ny, rowz = zz + 1 < nz;
-#pragma unroll 2
-            for (uint32_t e = threadIdx.x; e < rowq; e += blockDim.x) {
-                const uint32_t x = e >> 2, qd = e & 3u, n = nrow + x;
-                const bool ein = in(n);
-                const bool ex = ein && x + 1 < nx && in(n + 1);
-                const bool ey = ein && rowy && in(n + nx);
-                const bool ez = ein && rowz && in(n + nxy);
-                const unsigned off = (n * QC + 4 * qd) * (unsigned)sizeof(T);
-                // every load unconditional (a missing neighbour reads the voxel itself and
-                // is masked below), so they issue together
-                T zv[4], nb[3][4], pv[4], fv[4];
-                bload4<T>(zr, off, zv);
-                bload4<T>(zr, off + (ex ? sx : 0u), nb[0]);
-                bload4<T>(zr, off + (ey ? sy : 0u), nb[1]);
-                bload4<T>(zr, off + (ez ? sz : 0u), nb[2]);
-                if (hasp) bload4<T>(pr, off, pv);
-                if (hasf) bload4<T>(fr, off, fv);
+#pragma unroll
+        for (int j = 0; j < MT_RW; ++j) {
+            const uint32_t yj = y0 + j, n = x + nx * (yj + ny * zz);
+            const bool ein = off[j] != kFar && in(n);
+            const bool ex = ein && x + 1 < nx && in(n + 1);
+            const bool ey = ein && yj + 1 < ny && in(n + nx);
+            const bool ez = ein && znext && in(n + nxy);
+            T pv[4], fv[4];
+            if (hasp) bload4<T>(mon_rsrc((const T *)a.zprev + cbase, cbytes), off[j], pv);
+            if (hasf) bload4<T>(mon_rsrc((const T *)a.f + cbase, cbytes), off[j], fv);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const T v = cur[j][s];
+                const T sh = __shfl_down(v, 4, 64);          // same quarter, voxel x + 1
+                const T xn = halo ? hx[j][s] : sh;
+                const T yn = j + 1 < MT_RW ? cur[j + 1 < MT_RW ? j + 1 : j][s] : yx[s];
+                zsq += v * v;
+                const T d0 = ex ? v - xn : (T)0, d1 = ey ? v - yn : (T)0, d2 = ez ? v - nxt[j][s] : (T)0;
+                reg += d0 * d0 + d1 * d1 + d2 * d2;
+                if (hasp) {
+                    const T dd = v - pv[s];
+                    dsq += dd * dd;
+                }
+                if (hasf) {
+                    const T dd = v - fv[s];
+                    psq += dd * dd;
+                }
+            }
+            if (hasr && off[j] != kFar) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const T v = zv[s];
-                    zsq += v * v;
-                    const T d0 = v - nb[0][s], d1 = v - nb[1][s], d2 = v - nb[2][s];
-                    reg += d0 * d0 + d1 * d1 + d2 * d2;      // masked neighbours read v itself
-                    if (hasp) {
-                        const T dd = v - pv[s];
-                        dsq += dd * dd;
-                    }
+                    const int q = 16 * (int)c + 4 * (int)qd + s;
+                    const double fs = q < a.Q ? a.fstar[(size_t)n * a.Q + q] : 0.0;
+                    const double dd = q < a.Q ? (double)cur[j][s] - fs : 0.0;
+                    acc[ST_DFCS] += dd * dd;
+                    acc[ST_FSTAR] += fs * fs;
                     if (hasf) {
-                        const T dd = v - fv[s];
-                        psq += dd * dd;
-                    }
-                }
-                if (a.fstar) {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int q = 16 * c + 4 * (int)qd + s;
-                        const double fs = q < a.Q ? a.fstar[(size_t)n * a.Q + q] : 0.0;
-                        const double dd = q < a.Q ? (double)zv[s] - fs : 0.0;
-                        acc[ST_DFCS] += dd * dd;
-                        acc[ST_FSTAR] += fs * fs;
-                        if (hasf) {
-                            const double df = q < a.Q ? (double)fv[s] - fs : 0.0;
-                            acc[ST_DFCS_F] += df * df;
-                        }
+                        const double df = q < a.Q ? (double)fv[s] - fs : 0.0;
+                        acc[ST_DFCS_F] += df * df;
                     }
                 }
             }
         }
-        // a NaN or Inf anywhere in the tile (or a square beyond the state type's range)
-        // leaves the tile's sum of squares non-finite
-        bad += !__builtin_isfinite(zsq);
-        acc[ST_NONFINITE] += (double)bad;
+        // a NaN or Inf anywhere in the unit (or a square beyond the state type's range)
+        // leaves the unit's sum of squares non-finite
+        acc[ST_NONFINITE] += __builtin_isfinite(zsq) ? 0.0 : 1.0;
         acc[ST_ZNORM] += (double)zsq;
         acc[ST_REG] += (double)reg;
         acc[ST_DZ] += (double)dsq;
         acc[ST_PRIMAL] += (double)psq;
+#pragma unroll
+        for (int j = 0; j < MT_RW; ++j)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cur[j][s] = nxt[j][s];
+        have = znext;
     }
     {                                        // data term: ||m_perp||^2 + sum_i (t_i - sigma_i y_i)^2,
         const T *y = (const T *)a.y;         // voxels spread over every block of the grid
@@ -571,7 +598,6 @@ k_monitor_stream(MonArgs a, double *__restrict__ partial) {
             acc[ST_DATA] += d;
         }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ double red[4][ST_COUNT];
 #pragma unroll
     for (int k = 0; k < ST_COUNT; ++k) {
@@ -723,26 +749,35 @@ void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t co
                            (float)beta, count);
 }
 
-// Blocks of the streaming monitor that the current device runs at once (per CU
-// occupancy x CUs), at most kMonitorBlocks; looked up once per device and mode.
-int stream_blocks(int mode) {
+// Blocks of the marching monitor that the current device runs at once (per CU
+// occupancy x CUs), at most kMonitorBlocks; looked up once per device and build.
+template <typename T, bool EXTRA>
+int march_blocks() {
     static std::mutex mu;
-    static int cache[kMaxDevices][2] = {};
+    static int cache[kMaxDevices] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 1024;
-    const int m = mode == MODE_FP64 ? 1 : 0;
     std::lock_guard<std::mutex> lk(mu);
-    if (cache[dev][m] == 0) {
+    if (cache[dev] == 0) {
         int per = 0, cus = 0;
-        const hipError_t e1 = m ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                      &per, k_monitor_stream<double>, 256, 0)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                      &per, k_monitor_stream<float>, 256, 0);
+        const hipError_t e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_monitor_march<T, EXTRA>, 256, 0);
         const hipError_t e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        int n = (e1 == hipSuccess && e2 == hipSuccess && per > 0 && cus > 0) ? per * cus : 1024;
-        cache[dev][m] = std::min(n, kMonitorBlocks);
+        const int n = (e1 == hipSuccess && e2 == hipSuccess && per > 0 && cus > 0) ? per * cus : 1024;
+        cache[dev] = std::min(n, kMonitorBlocks);
     }
-    return cache[dev][m];
+    return cache[dev];
+}
+
+// Eight times the blocks per XCD: as few rounds of columns as the resident blocks
+// allow, the XCD's run of columns spread evenly over them.
+template <typename T, bool EXTRA>
+int launch_march(const MonArgs &a, double *partial, hipStream_t s) {
+    const int64_t ncol = ((a.g.nx + MT_X - 1) / MT_X) * ((a.g.ny + MT_Y - 1) / MT_Y) * a.nchunk;
+    const int64_t cx = (ncol + 7) / 8, gmax = std::max(1, march_blocks<T, EXTRA>() / 8);
+    const int64_t rounds = (cx + gmax - 1) / gmax, per = (cx + rounds - 1) / rounds;
+    const int gx = (int)(8 * std::max<int64_t>(1, per));
+    hipLaunchKernelGGL((k_monitor_march<T, EXTRA>), dim3(gx), dim3(256), 0, s, a, partial);
+    return gx;
 }
 
 int monitor_blocks(int64_t N) {
@@ -754,13 +789,12 @@ void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hi
     const int64_t esz = mode == MODE_FP64 ? 8 : 4;
     if (a.y && a.ld == 0 && a.nchunk > 0 && a.nchunk <= kMonitorBlocks &&
         a.g.N * QC * esz + 64 < ((int64_t)1 << 31)) {
-        // streaming pass: about as many blocks as the device runs at once (no tail)
-        const int64_t items = a.g.ny * ((a.g.nz + 7) / 8) * a.nchunk;
-        const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(items, stream_blocks(mode)));
-        if (mode == MODE_FP64)
-            hipLaunchKernelGGL(k_monitor_stream<double>, dim3(gx), dim3(256), 0, s, a, partial);
-        else
-            hipLaunchKernelGGL(k_monitor_stream<float>, dim3(gx), dim3(256), 0, s, a, partial);
+        // one pass along z: about as many blocks as the device runs at once (no tail)
+        const bool extra = a.zprev || a.f || a.fstar;
+        const int gx = mode == MODE_FP64 ? (extra ? launch_march<double, true>(a, partial, s)
+                                                  : launch_march<double, false>(a, partial, s))
+                                         : (extra ? launch_march<float, true>(a, partial, s)
+                                                  : launch_march<float, false>(a, partial, s));
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, gx, a.dzpart, a.ndz,
                            out);
         return;

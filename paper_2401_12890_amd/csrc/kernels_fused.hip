@@ -453,6 +453,11 @@ k_fused(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles, in
 #pragma unroll
             for (int rb = 0; rb < RBM; ++rb) yacc[b][rb] = V4{0, 0, 0, 0};
         }
+        // the w operands arrive before the chunk loop starts. Without this wait the
+        // compiler cannot count the loads still in flight inside the loop: it waits
+        // for every one (the previous chunk's z stores too), or for the chunk
+        // prefetch it has just issued, stalling each chunk on its own loads.
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
 
         for (int c = 0; c < a.nchunk; ++c, ++g) {
             int cb = 0;                  // LDS buffer holding chunk c
