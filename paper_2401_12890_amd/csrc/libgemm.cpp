@@ -4,8 +4,11 @@
 // constant M x K operand A and the voxels' N x K operand B, both row-major with
 // k contiguous; in hipBLASLt's column-major terms C (M x N) = op(A) op(B) with
 // op(A) = A^T (A stored K x M) and op(B) = B (stored K x N). Each distinct shape
-// gets its matmul descriptor, layouts and the library's first heuristic
-// algorithm once; the workspace is allocated once.
+// gets its matmul descriptor, layouts and up to kCandidates of the library's
+// heuristic algorithms once; the first product of a shape times each candidate
+// on the caller's stream (one warm-up and two timed runs) and keeps the fastest
+// for the life of the context, so repeated solves use one algorithm (one
+// summation order). The workspace is allocated once.
 #include "internal.h"
 
 #include <hip/hip_runtime_api.h>
@@ -27,6 +30,8 @@ struct LibGemm {
         hipblasLtMatmulDesc_t md = nullptr;
         hipblasLtMatrixLayout_t la = nullptr, lb = nullptr, lc = nullptr;
         hipblasLtMatmulAlgo_t algo{};
+        std::vector<hipblasLtMatmulAlgo_t> cands;
+        bool tuned = false;
     };
     std::vector<Plan> plans;
 };
@@ -34,6 +39,7 @@ struct LibGemm {
 namespace {
 
 constexpr size_t kWorkspace = (size_t)64 << 20;
+constexpr int kCandidates = 8;
 
 LibGemm::Plan *plan_for(LibGemm *g, bool bf16, int M, int64_t N, int K) {
     for (auto &p : g->plans)
@@ -60,12 +66,15 @@ LibGemm::Plan *plan_for(LibGemm *g, bool bf16, int M, int64_t N, int K) {
         ok = hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wsz,
                                                    sizeof(wsz)) == HIPBLAS_STATUS_SUCCESS;
     if (ok) {
-        hipblasLtMatmulHeuristicResult_t heur[1];
+        hipblasLtMatmulHeuristicResult_t heur[kCandidates];
         int n = 0;
-        ok = hipblasLtMatmulAlgoGetHeuristic(g->h, p.md, p.la, p.lb, p.lc, p.lc, pref, 1, heur, &n) ==
-                 HIPBLAS_STATUS_SUCCESS &&
-             n > 0 && heur[0].workspaceSize <= kWorkspace;
-        if (ok) p.algo = heur[0].algo;
+        ok = hipblasLtMatmulAlgoGetHeuristic(g->h, p.md, p.la, p.lb, p.lc, p.lc, pref, kCandidates, heur,
+                                             &n) == HIPBLAS_STATUS_SUCCESS;
+        for (int i = 0; ok && i < n; ++i)
+            if (heur[i].state == HIPBLAS_STATUS_SUCCESS && heur[i].workspaceSize <= kWorkspace)
+                p.cands.push_back(heur[i].algo);
+        ok = ok && !p.cands.empty();
+        if (ok) p.algo = p.cands[0];
     }
     if (pref) (void)hipblasLtMatmulPreferenceDestroy(pref);
     p.ok = ok;
@@ -111,8 +120,35 @@ bool libgemm_tn(LibGemm *g, bool bf16, const void *A, const void *B, float *C, i
     if (!p->ok) return false;
     if (!A) return true;                 // shape check only
     const float alpha = 1.0f, beta = 0.0f;
-    return hipblasLtMatmul(g->h, p->md, &alpha, A, p->la, B, p->lb, &beta, C, p->lc, C, p->lc, &p->algo,
-                           g->ws, g->wsz, s) == HIPBLAS_STATUS_SUCCESS;
+    auto run = [&](const hipblasLtMatmulAlgo_t &algo) {
+        return hipblasLtMatmul(g->h, p->md, &alpha, A, p->la, B, p->lb, &beta, C, p->lc, C, p->lc, &algo,
+                               g->ws, g->wsz, s) == HIPBLAS_STATUS_SUCCESS;
+    };
+    if (!p->tuned) {
+        p->tuned = true;
+        if (p->cands.size() > 1) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+                float best = -1.0f;
+                for (const auto &algo : p->cands) {
+                    float ms = 0.0f;
+                    if (!run(algo) || hipEventRecord(e0, s) != hipSuccess || !run(algo) || !run(algo) ||
+                        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        (void)hipGetLastError();
+                        continue;
+                    }
+                    if (best < 0.0f || ms < best) {
+                        best = ms;
+                        p->algo = algo;
+                    }
+                }
+            }
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    }
+    return run(p->algo);
 }
 
 }  // namespace ssmap
