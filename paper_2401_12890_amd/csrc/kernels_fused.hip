@@ -1159,21 +1159,24 @@ void append_tiles(const Grid &g, int job, int mode, FusedShape sh, std::vector<T
               tz = (int)((g.nz + sh.tz - 1) / sh.tz);
     // Bricks that run at the same time on one XCD can share their face halos
     // through its L2. The float32 16 x 8 x 4 brick (one workgroup per CU, 32 per
-    // XCD) lists its bricks in blocks of 4 x 8 x 1 (x fastest inside a block, the
-    // blocks in x, y, z order). At 128 x 128 x 64 (8 x 16 x 16 bricks) this measured
-    // 2.5 % faster than x-fastest rows, with 4 % fewer bytes read; blocks two bricks
-    // wide read less still but ran 8 % slower, and the 16 x 4 x 4 bricks measured
-    // 0.6-1 % slower with any blocking, so every other shape keeps the plain order.
+    // XCD) lists its bricks in blocks of 8 x 2 x 2 (x fastest inside a block, then
+    // y, then z; the blocks in x, y, z order). At 128 x 128 x 64 (8 x 16 x 16
+    // bricks) this measured about 1 % faster than blocks of 4 x 8 x 1 and 3.5 %
+    // faster than x-fastest rows; blocks two bricks wide (2 x 4 x 4, 2 x 2 x 8)
+    // read fewer bytes but ran 8 % slower. The 16 x 4 x 4 bricks ran 8-12 %
+    // slower with any blocking tried (2 x 8 x 4, 3 x 4 x 4, 6 x 4 x 2, ...), so
+    // every other shape keeps the plain order.
     const bool blocked = mode == MODE_FP32 && sh.ty == 8 && sh.tz == 4;
-    const int bx = blocked ? 4 : tx, by = blocked ? 8 : ty;
-    for (int k = 0; k < tz; ++k)
+    const int bx = blocked ? 8 : tx, by = blocked ? 2 : ty, bz = blocked ? 2 : 1;
+    for (int k0 = 0; k0 < tz; k0 += bz)
         for (int j0 = 0; j0 < ty; j0 += by)
             for (int i0 = 0; i0 < tx; i0 += bx)
-                for (int jy = j0; jy < std::min(j0 + by, ty); ++jy)
-                    for (int i = i0; i < std::min(i0 + bx, tx); ++i)
-                        if (!code || brick_has_inside(g, *code, (int64_t)i * TX, (int64_t)jy * sh.ty,
-                                                      (int64_t)k * sh.tz, TX, sh.ty, sh.tz))
-                            out.push_back(TileRef{job, i, jy, k});
+                for (int k = k0; k < std::min(k0 + bz, tz); ++k)
+                    for (int jy = j0; jy < std::min(j0 + by, ty); ++jy)
+                        for (int i = i0; i < std::min(i0 + bx, tx); ++i)
+                            if (!code || brick_has_inside(g, *code, (int64_t)i * TX, (int64_t)jy * sh.ty,
+                                                          (int64_t)k * sh.tz, TX, sh.ty, sh.tz))
+                                out.push_back(TileRef{job, i, jy, k});
 }
 
 bool launch_fused(const FusedLaunch &L, hipStream_t s) {
