@@ -79,19 +79,24 @@ typedef enum {
                                SSMAP_MONITOR_PRIMAL. AUTO takes it for grids of at
                                most 32 bricks and 2..32 chunks                    */
     SSMAP_KERNEL_GEMM = 3   /* any rank, float32 / bf16x3: the two contractions as
-                               MFMA-tiled GEMMs over all voxels (compute bound at
-                               high rank), the stencil / z-update and r-vector
-                               recursion as the GEMMs' epilogues; monitoring
-                               allowed, no SSMAP_KEEP_AUX or SSMAP_MONITOR_PRIMAL */
+                               GEMMs over all voxels (hipBLASLt, else MFMA-tiled
+                               GEMMs of this library; compute bound at high rank),
+                               the stencil / z-update and the r-vector recursion as
+                               elementwise passes; monitoring allowed, no
+                               SSMAP_KEEP_AUX, SSMAP_MONITOR_PRIMAL or
+                               SSMAP_WARM_START                                   */
 } ssmap_kernel;
 
 enum {
     SSMAP_KEEP_AUX = 1,     /* keep f^K and d^K of the solve for ssmap_get_aux    */
-    SSMAP_MONITOR_PRIMAL = 4 /* with check_every > 0: also the primal residual
+    SSMAP_MONITOR_PRIMAL = 4, /* with check_every > 0: also the primal residual
                                ||z^k - f^k|| at every check (and DFCS of f^k when a
                                reference is set); f^k needs d^{k-1}, so the two
                                iterations before each check are bracketed by two
                                extra passes each (fused and unfused kernels only) */
+    SSMAP_WARM_START = 8    /* start from the z^0 and d^0 set by ssmap_set_initial
+                               instead of z = d = 0 (Algorithm 2's initialisation);
+                               fused and unfused kernels only (AUTO picks them) */
 };
 
 /* LADMM parameters (Algorithm 2 inputs, Sec. III-E; selection rules, Sec. III-F). */
@@ -104,8 +109,8 @@ typedef struct {
     int check_every;        /* 0: no monitoring; k > 0: objective, residuals and DFCS
                                (float64 reductions) every k iterations and after the
                                last one, into the stats history                          */
-    int flags;              /* SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL (| SSMAP_AUTOTUNE for
-                               batches)                                                  */
+    int flags;              /* SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL | SSMAP_WARM_START
+                               (| SSMAP_AUTOTUNE for batches)                            */
     int kernel;             /* ssmap_kernel                                              */
     int reserved;
     double stop_tol;        /* 0: run all iters. > 0 (needs check_every > 0, no
@@ -221,6 +226,20 @@ ssmap_status ssmap_set_mask(ssmap_ctx *ctx, const uint8_t *mask);
  * copied to the device. Every monitored solve on ctx then reports DFCS of z^k
  * (and of f^k with SSMAP_MONITOR_PRIMAL). f_star = NULL removes it. */
 ssmap_status ssmap_set_reference(ssmap_ctx *ctx, const double *f_star);
+
+/* Initial iterate for solves with SSMAP_WARM_START (Algorithm 2 starts from
+ * z = d = 0; a warm start starts from a given z^0 and scaled dual d^0 instead,
+ * e.g. the z^K and d^K of an earlier solve on the same data, lambda, beta and
+ * rank (checkpoint and resume; d^K from ssmap_get_aux), or a minimiser z* with
+ * d* = K_r^T (m - K_r z*), which the iteration leaves in place). z0, d0: N*Q
+ * float64 voxel-major host buffers (as F_out), finite; either may be NULL for
+ * zeros; copied to the device (N*Q*8 bytes each). From them the solve forms its
+ * reduced state on the device in float64 (y^0 = V_r^T z^0, w^0 = a.h -
+ * b.(y^0 - V_r^T d^0 / beta), Eq. DictVecSVD) and rounds it to the state
+ * precision; outside a mask both are taken as 0. Both NULL removes the
+ * initial iterate. EINVAL: a warm-started solve with none set, or with the
+ * chunk-split or GEMM kernel, a batch, or the allocation-free entry point. */
+ssmap_status ssmap_set_initial(ssmap_ctx *ctx, const double *z0, const double *d0);
 
 /* Penalty selection heuristic (Sec. III-F): solve the centre patch of the
  * grid (3 voxels per axis longer than 1, fewer on shorter axes; the box

@@ -26,13 +26,14 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KERNELS = {"auto": 0, "unfused": 1, "fused": 2, "gemm": 3, "split": 4}
 SSMAP_KEEP_AUX = 1
 SSMAP_MONITOR_PRIMAL = 4
+SSMAP_WARM_START = 8
 MAX_HIST = 512
 
 EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_device_noalloc",
            "ssmap_get_aux",
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
            "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_set_reference",
-           "ssmap_tune_beta",
+           "ssmap_set_initial", "ssmap_tune_beta",
            "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
            "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
@@ -147,6 +148,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_set_mask.restype = ip
     lib.ssmap_set_reference.argtypes = [vp, dp]
     lib.ssmap_set_reference.restype = ip
+    lib.ssmap_set_initial.argtypes = [vp, dp, dp]
+    lib.ssmap_set_initial.restype = ip
     lib.ssmap_tune_beta.argtypes = [vp, dp, ctypes.c_double, ctypes.POINTER(Steps), ip, dp, ip,
                                     dp, dp]
     lib.ssmap_tune_beta.restype = ip
@@ -197,9 +200,9 @@ def _dptr(a: np.ndarray):
 
 
 def make_steps(beta, xi_p=0.0, rank=0, precision="fp64", check_every=0, keep_aux=False,
-               kernel="auto", autotune=False, stop_tol=0.0, primal=False) -> Steps:
+               kernel="auto", autotune=False, stop_tol=0.0, primal=False, warm=False) -> Steps:
     flags = (SSMAP_KEEP_AUX if keep_aux else 0) | (SSMAP_AUTOTUNE if autotune else 0) | \
-        (SSMAP_MONITOR_PRIMAL if primal else 0)
+        (SSMAP_MONITOR_PRIMAL if primal else 0) | (SSMAP_WARM_START if warm else 0)
     return Steps(beta=float(beta), xi_p=float(xi_p), rank=int(rank),
                  precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                  check_every=int(check_every), flags=flags,
@@ -304,6 +307,15 @@ def ssmap_set_reference(ctx: int, f_star) -> None:
     _check(ctx, load().ssmap_set_reference(ctx, _dptr(f)))
 
 
+def ssmap_set_initial(ctx: int, z0, d0) -> None:
+    """z0, d0: (N, Q) float64 initial iterate for warm starts (None: zeros);
+    both None removes it."""
+    zs = None if z0 is None else np.ascontiguousarray(z0, dtype=np.float64)
+    ds = None if d0 is None else np.ascontiguousarray(d0, dtype=np.float64)
+    _check(ctx, load().ssmap_set_initial(ctx, None if zs is None else _dptr(zs),
+                                         None if ds is None else _dptr(ds)))
+
+
 def ssmap_tune_beta(ctx: int, M: np.ndarray, lam: float, steps: Steps, iters: int, betas):
     """Returns (best beta, objectives per candidate)."""
     M = np.ascontiguousarray(M, dtype=np.float64)
@@ -368,6 +380,13 @@ class Mapper:
         if f_star is not None and np.shape(f_star) != (self.N, self.Q):
             raise ValueError("f_star must be (N, Q)")
         ssmap_set_reference(self.ctx, f_star)
+
+    def set_initial(self, z0=None, d0=None) -> None:
+        """Initial iterate (z^0, d^0) for solves with warm=True."""
+        for x in (z0, d0):
+            if x is not None and np.shape(x) != (self.N, self.Q):
+                raise ValueError("z0 and d0 must be (N, Q)")
+        ssmap_set_initial(self.ctx, z0, d0)
 
     def tune_beta(self, M, lam, iters, betas, **kw):
         """Patch heuristic for beta; returns (best beta, objectives)."""

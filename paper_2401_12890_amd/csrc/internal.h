@@ -119,6 +119,12 @@ bool launch_split(int mode, const SplitArgs &sa, FusedShape sh, const TileRef *t
 // f may alias dprev); post: t <- beta (t - z^{k+1}) = d^{k+1}.
 void launch_aux_pre(int mode, const IterArgs &a, void *t, void *f, const void *dprev,
                     hipStream_t s);
+// Warm start: z^0 (and d^0 into dc when given) from voxel-major float64 inputs
+// (NULL: zeros) into the chunked state, y^0 = V_r^T z^0 and w^0 = a.h - b.(y^0 -
+// V_r^T d^0 / beta) into a.y, a.w (ranks below r), after the projection set a.h;
+// V64: V_r in float64, Qp x RP.
+void launch_warm(int mode, const IterArgs &a, const double *z0, const double *d0, const double *V64,
+                 void *zc, void *dc, int Q, hipStream_t s);
 void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t count,
                      hipStream_t s);
 

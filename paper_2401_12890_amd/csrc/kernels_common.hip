@@ -638,6 +638,62 @@ k_reduce_partials(const double *__restrict__ partial, int nblocks, const double 
     }
 }
 
+// ------------------------------------------------------------- warm start
+// Algorithm 2 from a given z^0 and d^0 instead of zeros, in the reduced form:
+// y^0 = V_r^T z^0 and w^0 = a.h - b.(y^0 - V_r^T d^0 / beta) (the f-step of
+// Eq. DictVecSVD written for w, as the iteration carries it). One wave per voxel,
+// lanes over the nodes q (coalesced reads of the voxel-major inputs): z^0 (and
+// d^0 when dc is given, for the aux bracket) into the chunked state layout, the
+// two contractions with V_r in float64 for NR ranks from NR blockIdx.y on,
+// butterfly sums over the wave, then those rank rows below r of y and w (padded
+// ranks keep their initial values; outside a mask everything stays as
+// initialised, i.e. z = d = 0).
+template <typename T, int NR>
+__global__ void __launch_bounds__(256)
+k_warm(IterArgs a, const double *__restrict__ z0, const double *__restrict__ d0,
+       const double *__restrict__ V64, T *__restrict__ zc, T *__restrict__ dc, int Q) {
+    const int lane = threadIdx.x & 63;
+    const int64_t N = a.g.N;
+    const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one voxel per wave
+    if (n >= N) return;
+    if (a.code && (a.code[n] & 0x80u) == 0) return;
+    const int r0 = NR * (int)blockIdx.y;
+    double ya[NR], va[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) ya[i] = va[i] = 0.0;
+    for (int q = lane; q < Q; q += 64) {
+        const double zv = z0 ? z0[n * Q + q] : 0.0;
+        const double dv = d0 ? d0[n * Q + q] : 0.0;
+        if (blockIdx.y == 0) {
+            const size_t e = ((size_t)(q / QC) * N + n) * QC + q % QC;
+            zc[e] = (T)zv;
+            if (dc) dc[e] = (T)dv;
+        }
+        const double *Vq = V64 + (size_t)q * a.RP + r0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if (r0 + i < a.RP) {
+                ya[i] += Vq[i] * zv;
+                va[i] += Vq[i] * dv;
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        ya[i] = wave_sum(ya[i]);
+        va[i] = wave_sum(va[i]);
+    }
+    if (lane != 0) return;
+    T *y = (T *)a.y, *w = (T *)a.w;
+    const T *ah = (const T *)a.ah, *b = (const T *)a.bcoef;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if (r0 + i < a.r) {
+            const size_t o = (size_t)(r0 + i) * N + n;
+            y[o] = (T)ya[i];
+            w[o] = (T)((double)ah[o] - (double)b[r0 + i] * (ya[i] - va[i] / a.beta));
+        }
+}
+
 // ------------------------------------------------------------- output
 template <typename T, typename O>
 __global__ void __launch_bounds__(256)
@@ -736,6 +792,26 @@ void launch_aux_pre(int mode, const IterArgs &a, void *t, void *f, const void *d
     else
         hipLaunchKernelGGL(k_aux_pre<MODE_BF16X3>, grid, block, 0, s, a, (float *)t, (float *)f,
                            (const float *)dprev);
+}
+
+void launch_warm(int mode, const IterArgs &a, const double *z0, const double *d0, const double *V64,
+                 void *zc, void *dc, int Q, hipStream_t s) {
+    const dim3 grid(blocks_for(a.g.N, 4), a.RP <= 16 ? 1 : (a.RP + 31) / 32), block(256);
+    if (mode == MODE_FP64) {
+        if (a.RP <= 16)
+            hipLaunchKernelGGL((k_warm<double, 16>), grid, block, 0, s, a, z0, d0, V64, (double *)zc,
+                               (double *)dc, Q);
+        else
+            hipLaunchKernelGGL((k_warm<double, 32>), grid, block, 0, s, a, z0, d0, V64, (double *)zc,
+                               (double *)dc, Q);
+    } else {
+        if (a.RP <= 16)
+            hipLaunchKernelGGL((k_warm<float, 16>), grid, block, 0, s, a, z0, d0, V64, (float *)zc,
+                               (float *)dc, Q);
+        else
+            hipLaunchKernelGGL((k_warm<float, 32>), grid, block, 0, s, a, z0, d0, V64, (float *)zc,
+                               (float *)dc, Q);
+    }
 }
 
 void launch_aux_post(int mode, void *t, const void *znew, double beta, size_t count,

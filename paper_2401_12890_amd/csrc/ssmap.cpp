@@ -137,6 +137,8 @@ struct ssmap_ctx {
     } arena;
     void *scratch = nullptr;              // this device's scratch array (NULL: lookup failed)
     bool has_ref = false;                 // a reference map f* for DFCS is on the device ("fstar")
+    bool has_init = false;                // an initial iterate for warm starts is set
+    bool init_z = false, init_d = false;  // z^0 / d^0 given ("init_z", "init_d"), else zeros
     LibGemm *lg = nullptr;                // exact-rank path: the library products (hipBLASLt)
     bool lg_tried = false;
     hipError_t scratch_err = hipSuccess;
@@ -289,6 +291,8 @@ void validate_steps(ssmap_ctx *c, double lambda, const ssmap_steps *st, int iter
         fail(SSMAP_EINVAL, "stop_tol must be finite and >= 0");
     if (st->stop_tol > 0 && (st->check_every == 0 || (st->flags & SSMAP_KEEP_AUX)))
         fail(SSMAP_EINVAL, "stop_tol needs check_every > 0 and no SSMAP_KEEP_AUX");
+    if ((st->flags & SSMAP_WARM_START) && !c->has_init)
+        fail(SSMAP_EINVAL, "SSMAP_WARM_START without an initial iterate (ssmap_set_initial)");
 }
 
 // Bricks of a grid for a brick shape (without a mask).
@@ -316,9 +320,11 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_sp
     p.fused = st->kernel == SSMAP_KERNEL_FUSED || (st->kernel == SSMAP_KERNEL_AUTO && can_fuse);
     // GEMM path: float32 / bf16x3 without aux output or primal residual (f is never
     // formed there); AUTO takes it where no fused kernel exists
-    const bool gemm_ok = p.mode != MODE_FP64 && !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL));
+    const bool gemm_ok = p.mode != MODE_FP64 &&
+                         !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL | SSMAP_WARM_START));
     if (st->kernel == SSMAP_KERNEL_GEMM && !gemm_ok)
-        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without aux output or primal residual");
+        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without aux output, primal residual "
+                           "or warm start");
     p.gemm = st->kernel == SSMAP_KERNEL_GEMM || (st->kernel == SSMAP_KERNEL_AUTO && !can_fuse && gemm_ok);
     // Chunk split: float64 / float32 grids with few bricks and short spectra, where
     // one workgroup per brick would leave most CUs idle (no aux output or primal
@@ -326,10 +332,10 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_sp
     const int64_t esz = p.mode == MODE_FP64 ? 8 : 4;
     const bool split_ok = can_fuse && p.mode != MODE_BF16X3 && c->nchunk >= 2 &&
                           (int64_t)c->nchunk * p.RP * c->g.N * esz < ((int64_t)1 << 31) &&
-                          !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL));
+                          !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL | SSMAP_WARM_START));
     if (st->kernel == SSMAP_KERNEL_SPLIT && !split_ok)
         fail(SSMAP_EINVAL, "the split kernel runs float64 or float32 with at least two chunks, "
-                           "no aux output and no primal residual");
+                           "no aux output, no primal residual and no warm start");
     p.split = st->kernel == SSMAP_KERNEL_SPLIT ||
               (st->kernel == SSMAP_KERNEL_AUTO && allow_split && split_ok && c->nchunk <= kSplitMaxChunks &&
                brick_count(c->g, default_shape(p.mode, c->g)) <= kSplitMaxBricks);
@@ -350,6 +356,7 @@ struct Prepared {
     IterArgs a{};             // z / znew of iteration 0
     void *z[2] = {nullptr, nullptr};
     bool monitor = false, aux = false, primal = false;
+    bool warm = false;            // z^0, d^0 from ssmap_set_initial
     double *V64 = nullptr, *t = nullptr, *mperp2 = nullptr, *partial = nullptr, *stat = nullptr,
            *sig = nullptr;
     const double *fstar = nullptr;
@@ -403,6 +410,12 @@ void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
         launch_zero(P.sw[0], (size_t)pl.RP * N, (int)esz, s);
         launch_zero(P.sy[0], (size_t)pl.RP * N, (int)esz, s);
     }
+    if (P.warm) {            // z^0, y^0, w^0 (and d^0 for the aux bracket) from the initial iterate
+        const size_t nq = (size_t)N * c->Q * 8;
+        launch_warm(pl.mode, P.a, c->init_z ? (const double *)ensure(c, "init_z", nq) : nullptr,
+                    c->init_d ? (const double *)ensure(c, "init_d", nq) : nullptr, P.V64, P.z[0],
+                    (P.aux || P.primal) ? P.dbuf : nullptr, c->Q, s);
+    }
     HIPC(c, hipGetLastError());
 }
 
@@ -417,6 +430,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     P.stop_tol = st->stop_tol;
     P.aux = (st->flags & SSMAP_KEEP_AUX) != 0;
     P.primal = P.monitor && (st->flags & SSMAP_MONITOR_PRIMAL) != 0;
+    P.warm = (st->flags & SSMAP_WARM_START) != 0;
     if (P.pl.gemm) {
         P.dM = dM;
         P.iters = iters;
@@ -435,10 +449,10 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         {"z0", zbytes}, {"z1", zbytes}, {"w", rbytes}, {"y", rbytes}, {"ah", rbytes},
         {"V", (size_t)Qp * RP * esz}, {"b", (size_t)RP * esz}, {"Ur", (size_t)Pm * r * 8},
         {"sig", (size_t)RP * 8}, {"acoef", (size_t)RP * 8}, {"bad", 256}};
+    if (P.monitor || P.warm) need.push_back({"V64", (size_t)Qp * RP * 8});
     if (P.monitor) {
         need.push_back({"t", (size_t)r * N * 8});
         need.push_back({"mperp2", (size_t)N * 8});
-        need.push_back({"V64", (size_t)Qp * RP * 8});
         need.push_back({"partial", (size_t)kMonitorBlocks * ST_COUNT * 8});
         need.push_back({"stat", (size_t)ST_COUNT * 8});
     }
@@ -493,9 +507,11 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         Vop = ensure(c, "Vop", hc.Vop.size());
         HIPC(c, hipMemcpyAsync(Vop, hc.Vop.data(), hc.Vop.size(), hipMemcpyHostToDevice, s));
     }
-    if (P.monitor) {
+    if (P.monitor || P.warm) {
         P.V64 = (double *)ensure(c, "V64", (size_t)Qp * RP * 8);
         HIPC(c, hipMemcpyAsync(P.V64, hc.Vh.data(), hc.Vh.size() * 8, hipMemcpyHostToDevice, s));
+    }
+    if (P.monitor) {
         P.t = (double *)ensure(c, "t", (size_t)r * N * 8);
         P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
         P.partial = (double *)ensure(c, "partial", (size_t)kMonitorBlocks * ST_COUNT * 8);
@@ -910,14 +926,15 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
     }
     IterArgs a = args_for(P, k);
     // f and d around iteration k. The iteration never forms them; when f^{k+1}
-    // is wanted (it needs d^k, itself formed around iteration k - 1; d^0 = 0),
+    // is wanted (it needs d^k, itself formed around iteration k - 1; d^0 = 0, or
+    // the warm start's, which init_state left in dbuf),
     // iteration k is bracketed: t = z^k + V_r w^k and f^{k+1} = t - d^k / beta
     // (over d^k, in place) before it, d^{k+1} = beta (t - z^{k+1}) after it.
     // Afterwards dbuf holds d^{k+1} and tbuf f^{k+1}.
     const bool need_f = wants_f(P, k);
     const bool bracket = need_f || wants_f(P, k + 1);
     void *fbuf = need_f ? P.dbuf : nullptr;
-    const void *dprev = need_f && k > 0 ? P.dbuf : nullptr;
+    const void *dprev = need_f && (k > 0 || P.warm) ? P.dbuf : nullptr;   // d^0 = 0 unless warm
     if (bracket) {
         a.dprev = dprev;
         a.fout = fbuf;
@@ -1100,8 +1117,8 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
     for (int j = 0; j < nj; ++j) {
         if (!dM[j] || !dF[j]) fail(SSMAP_EINVAL, "NULL buffer for job " + std::to_string(j));
         validate_steps(b->jobs[j], lambda[j], &steps[j], iters);
-        if (steps[j].check_every != 0 || (steps[j].flags & SSMAP_KEEP_AUX))
-            fail(SSMAP_EINVAL, "batches take no monitoring and no SSMAP_KEEP_AUX");
+        if (steps[j].check_every != 0 || (steps[j].flags & (SSMAP_KEEP_AUX | SSMAP_WARM_START)))
+            fail(SSMAP_EINVAL, "batches take no monitoring, no SSMAP_KEEP_AUX and no warm start");
         tune |= (steps[j].flags & SSMAP_AUTOTUNE) != 0;
     }
     ssmap_batch_stats &S = b->stats;
@@ -1340,6 +1357,8 @@ ssmap_status ssmap_solve_device_noalloc(ssmap_ctx *ctx, const void *dM, double l
         validate_steps(ctx, lambda, steps, iters);
         if (steps->flags & SSMAP_KEEP_AUX)
             fail(SSMAP_EINVAL, "an allocation-free solve keeps no aux output (SSMAP_KEEP_AUX)");
+        if (steps->flags & SSMAP_WARM_START)
+            fail(SSMAP_EINVAL, "an allocation-free solve takes no warm start");
         if (steps->kernel == SSMAP_KERNEL_GEMM)
             fail(SSMAP_EINVAL, "an allocation-free solve runs the fused or unfused kernels");
         HIPC(ctx, hipSetDevice(ctx->device));
@@ -1450,6 +1469,28 @@ ssmap_status ssmap_set_reference(ssmap_ctx *ctx, const double *f_star) {
         void *d = ensure(ctx, "fstar", n * 8);
         HIPC(ctx, hipMemcpy(d, f_star, n * 8, hipMemcpyHostToDevice));
         ctx->has_ref = true;
+    });
+}
+
+ssmap_status ssmap_set_initial(ssmap_ctx *ctx, const double *z0, const double *d0) {
+    if (!ctx) return SSMAP_EINVAL;
+    return guarded(ctx, [&] {
+        HIPC(ctx, hipSetDevice(ctx->device));
+        ctx->has_init = false;
+        if (!z0 && !d0) {
+            ctx->init_z = ctx->init_d = false;
+            return;
+        }
+        const size_t n = (size_t)ctx->g.N * ctx->Q;
+        for (const double *p : {z0, d0})
+            if (p)
+                for (size_t i = 0; i < n; ++i)
+                    if (!std::isfinite(p[i])) fail(SSMAP_ENONFINITE, "z0 or d0 holds a NaN or Inf");
+        if (z0) HIPC(ctx, hipMemcpy(ensure(ctx, "init_z", n * 8), z0, n * 8, hipMemcpyHostToDevice));
+        if (d0) HIPC(ctx, hipMemcpy(ensure(ctx, "init_d", n * 8), d0, n * 8, hipMemcpyHostToDevice));
+        ctx->init_z = z0 != nullptr;
+        ctx->init_d = d0 != nullptr;
+        ctx->has_init = true;
     });
 }
 

@@ -168,6 +168,24 @@ def fista(K_r, m, grid, lam, iters=20000, tol=1e-14, D=None):
     return x, Jx
 
 
+def polish_active_set(K_r, m, z, grid, lam, thresh=1e-7):
+    """Exact minimiser on the support of an approximate one: with the free set
+    F = {z > thresh max z} and z = 0 elsewhere, solve the normal equations of the
+    nonnegative problem restricted to F, H_FF z_F = b_F, with the dense Hessian
+    H = I_N (x) K^T K + lambda D^T D (x) I_Q (explicit ordered-pair D, voxel-major
+    z) and b = vec(K^T m_n). Returns (z, complementarity residual of the result);
+    the support is right when the residual is at rounding level."""
+    N, Q = z.shape
+    D = explicit_D(grid)
+    H = np.kron(np.eye(N), K_r.T @ K_r) + lam * np.kron((D.T @ D).toarray(), np.eye(Q))
+    b = (m @ K_r).reshape(-1)
+    F = np.flatnonzero(z.reshape(-1) > thresh * z.max())
+    x = np.zeros(N * Q)
+    x[F] = np.linalg.solve(H[np.ix_(F, F)], b[F])
+    zp = x.reshape(N, Q)
+    return zp, kkt_residual(K_r, m, zp, grid, lam)[1]
+
+
 def kkt_residual(K_r, m, z, grid, lam):
     """Return (min z, max |min(z, grad)|-style complementarity, most negative
     gradient on the zero set) at z for the nonnegative problem."""
