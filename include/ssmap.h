@@ -313,10 +313,20 @@ typedef struct {
 ssmap_status ssmap_batch_create(int njobs, const double *const *K, const int *P, const int *Q,
                                 const int64_t *grids, ssmap_batch **out);
 
+/* Masked voxel set of job `job` (0 <= job < njobs), exactly as ssmap_set_mask
+ * for a single problem (Sec. II-C, maskless footnote): outside voxels stay 0,
+ * the regulariser runs over inside face pairs, the xi_p rule takes the masked
+ * graph's ||D^T D||, the job's bricks with no inside voxel leave the shared
+ * launches, and its rows of M outside are not read. mask = NULL restores the
+ * whole box. EINVAL for a job index out of range. */
+ssmap_status ssmap_batch_set_mask(ssmap_batch *b, int job, const uint8_t *mask);
+
 /* Solve every job for `iters` iterations on device buffers, ordered on
  * `hip_stream`. dM[j] / dF[j] as in ssmap_solve_device for job j; lambda and
  * steps are per job (njobs entries). steps[j].check_every must be 0 and
- * SSMAP_KEEP_AUX unset (use the single-problem entry points for those).
+ * SSMAP_KEEP_AUX and SSMAP_WARM_START unset (use the single-problem entry
+ * points for those). Each job's map equals, bit for bit, its single solve with
+ * SSMAP_KERNEL_FUSED (and its mask).
  * SSMAP_AUTOTUNE in any job's flags turns the shape search on; the shapes it
  * chooses are kept in `b` and used by its later solves of the same classes
  * (same precision, rank bucket and member jobs) until it is destroyed. */

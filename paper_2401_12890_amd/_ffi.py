@@ -34,7 +34,7 @@ EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_dev
            "ssmap_get_stats", "ssmap_get_singular_values", "ssmap_last_error",
            "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_set_reference",
            "ssmap_set_initial", "ssmap_tune_beta",
-           "ssmap_batch_create", "ssmap_batch_solve", "ssmap_batch_solve_device",
+           "ssmap_batch_create", "ssmap_batch_set_mask", "ssmap_batch_solve", "ssmap_batch_solve_device",
            "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
            "ssmap_server_pump", "ssmap_server_poll", "ssmap_server_drain",
@@ -160,6 +160,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(vp)]
     lib.ssmap_batch_create.restype = ip
+    lib.ssmap_batch_set_mask.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_uint8)]
+    lib.ssmap_batch_set_mask.restype = ip
     lib.ssmap_batch_solve.argtypes = [vp, pp, dp, ctypes.POINTER(Steps), ip, pp]
     lib.ssmap_batch_solve.restype = ip
     lib.ssmap_batch_solve_device.argtypes = [vp, pp, dp, ctypes.POINTER(Steps), ip, pp, vp]
@@ -435,6 +437,15 @@ def _bcheck(b, st):
         raise SsmapError(st, load().ssmap_batch_last_error(b).decode())
 
 
+def ssmap_batch_set_mask(b, job: int, mask) -> None:
+    """mask: N_job booleans, or None for the whole box."""
+    if mask is None:
+        _bcheck(b, load().ssmap_batch_set_mask(b, int(job), None))
+        return
+    mk = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+    _bcheck(b, load().ssmap_batch_set_mask(b, int(job), mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+
 def ssmap_batch_solve(b, Ms, lams, steps_list, iters, shapes):
     """Host solve; shapes[j] = (N_j, Q_j). Returns a list of (N_j, Q_j) maps."""
     Ms = [np.ascontiguousarray(M, dtype=np.float64) for M in Ms]
@@ -484,6 +495,11 @@ class BatchMapper:
         self.grids = [tuple(int(v) for v in g) for g in grids]
         self.N = [g[0] * g[1] * g[2] for g in self.grids]
         self.b = ssmap_batch_create(self.Ks, self.grids)
+
+    def set_mask(self, job, mask) -> None:
+        if mask is not None and np.size(mask) != self.N[job]:
+            raise ValueError("mask must have N_job entries")
+        ssmap_batch_set_mask(self.b, job, mask)
 
     def solve(self, Ms, lams, betas, iters, **kw):
         steps = [make_steps(bt, **kw) for bt in betas]

@@ -1649,6 +1649,15 @@ ssmap_status ssmap_batch_solve_device(ssmap_batch *b, const void *const *dM, con
     });
 }
 
+ssmap_status ssmap_batch_set_mask(ssmap_batch *b, int job, const uint8_t *mask) {
+    if (!b) return SSMAP_EINVAL;
+    return batch_guarded(b, [&] {
+        if (job < 0 || job >= (int)b->jobs.size()) fail(SSMAP_EINVAL, "job index out of range");
+        const ssmap_status st = ssmap_set_mask(b->jobs[job], mask);
+        if (st != SSMAP_OK) fail(st, "job " + std::to_string(job) + ": " + ssmap_last_error(b->jobs[job]));
+    });
+}
+
 ssmap_status ssmap_batch_solve(ssmap_batch *b, const double *const *M, const double *lambda,
                                const ssmap_steps *steps, int iters, double *const *F_out) {
     if (!b) return SSMAP_EINVAL;
@@ -1662,8 +1671,8 @@ ssmap_status ssmap_batch_solve(ssmap_batch *b, const double *const *M, const dou
             ssmap_ctx *c = b->jobs[j];
             if (!M[j] || !F_out[j]) fail(SSMAP_EINVAL, "NULL buffer for job " + std::to_string(j));
             const size_t nm = (size_t)c->g.N * c->P, nf = (size_t)c->g.N * c->Q;
-            for (size_t i = 0; i < nm; ++i)
-                if (!std::isfinite(M[j][i]))
+            for (size_t i = 0; i < nm; ++i)    // rows outside a job's mask are not read
+                if (!std::isfinite(M[j][i]) && (c->code.empty() || (c->code[i / c->P] & 0x80)))
                     fail(SSMAP_ENONFINITE, "job " + std::to_string(j) + ": M holds a NaN or Inf");
             const bool f64 = steps[j].precision == SSMAP_FP64;
             const size_t esz = f64 ? 8 : 4;
