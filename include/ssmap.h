@@ -68,8 +68,8 @@ typedef enum {
 typedef enum {
     SSMAP_KERNEL_AUTO = 0,  /* fused MFMA kernel when the rank allows (r <= 32), split
                                over chunks for small grids (see SPLIT); else the GEMM
-                               path for float32 / bf16x3 without aux output or
-                               primal residual; else unfused                      */
+                               path for float32 / bf16x3 without primal residual or
+                               warm start; else unfused                           */
     SSMAP_KERNEL_UNFUSED = 1,
     SSMAP_KERNEL_FUSED = 2,
     SSMAP_KERNEL_SPLIT = 4, /* small grids, float64 / float32, r <= 32: the fused step
@@ -82,9 +82,9 @@ typedef enum {
                                GEMMs over all voxels (hipBLASLt, else MFMA-tiled
                                GEMMs of this library; compute bound at high rank),
                                the stencil / z-update and the r-vector recursion as
-                               elementwise passes; monitoring allowed, no
-                               SSMAP_KEEP_AUX, SSMAP_MONITOR_PRIMAL or
-                               SSMAP_WARM_START                                   */
+                               elementwise passes; monitoring and SSMAP_KEEP_AUX
+                               allowed (aux output needs the hipBLASLt products),
+                               no SSMAP_MONITOR_PRIMAL or SSMAP_WARM_START         */
 } ssmap_kernel;
 
 enum {
@@ -206,7 +206,8 @@ ssmap_status ssmap_solve_device_noalloc(ssmap_ctx *ctx, const void *dM, double l
                                         const ssmap_steps *steps, int iters, void *dF,
                                         void *hip_stream);
 
-/* f^iters and d^iters of the last solve run with SSMAP_KEEP_AUX.
+/* f^iters and d^iters of the last solve run with SSMAP_KEEP_AUX (zeros after a
+ * solve of zero iterations).
  *   f_out, d_out : N*Q float64 voxel-major host buffers; either may be NULL. */
 ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out);
 

@@ -217,6 +217,11 @@ void launch_epi_z(const float *U, const float *z, float *zn, uint16_t *zs3, Grid
                   double lam2, double beta, const uint8_t *code, hipStream_t s);
 void launch_epi_w(const float *Y, int64_t N, int Rg, const float *ah, float *sv, float *w, uint16_t *ws3,
                   const float *bcoef, hipStream_t s);
+// f^{k+1} (into f, over dprev in place; f NULL: none) and d^{k+1} (into d) of the
+// library path's iteration k from z^k, its u^k and z^{k+1} (voxel-major, count
+// entries); dprev NULL: d^k = 0.
+void launch_gemm_aux(const float *z, const float *u, const float *zn, const float *dprev, float *f,
+                     float *d, size_t count, double beta, hipStream_t s);
 // Library product (hipBLASLt): C[n][m] = sum_k A[m][k] B[n][k] for m < M, n < N,
 // k < K; A M x K and B N x K row-major, bf16 or float32, C float32 (N x M).
 // false when the library offers no algorithm for the shape.

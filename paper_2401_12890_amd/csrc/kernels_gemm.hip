@@ -413,6 +413,21 @@ k_gemm_output(const float *__restrict__ z, TO *__restrict__ F, int64_t N, int Q,
 
 inline unsigned nblocks(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
 
+// f and d around iteration k of the library path (voxel-major rows of Qg, the
+// product's u^k = V_r w^k still in its buffer): t = z^k + u^k, f^{k+1} = t -
+// d^k / beta (written over d^k in place when f is given; d^0 = 0 when dprev is
+// NULL) and d^{k+1} = beta (t - z^{k+1}) (Algorithm 2's f- and d-steps in the
+// reduced form).
+__global__ void __launch_bounds__(256)
+k_gemm_aux(const float *z, const float *u, const float *zn, const float *dprev, float *f, float *d,
+           size_t count, float beta) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float t = z[i] + u[i];
+    if (f) f[i] = t - (dprev ? dprev[i] : 0.0f) / beta;
+    d[i] = beta * (t - zn[i]);
+}
+
 }  // namespace
 
 namespace {
@@ -465,6 +480,12 @@ void launch_epi_w(const float *Y, int64_t N, int Rg, const float *ah, float *sv,
                   const float *bcoef, hipStream_t s) {
     const EpiW e{ah, sv, w, ws3, bcoef, Rg, 3};
     hipLaunchKernelGGL(k_epi_w, dim3(nblocks(N * (Rg / 4), 256)), dim3(256), 0, s, e, Y, N);
+}
+
+void launch_gemm_aux(const float *z, const float *u, const float *zn, const float *dprev, float *f,
+                     float *d, size_t count, double beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_gemm_aux, dim3(nblocks((int64_t)count, 256)), dim3(256), 0, s, z, u, zn, dprev, f,
+                       d, count, (float)beta);
 }
 
 void launch_gemm_from_ranks(const float *src, int RP, float *dst, uint16_t *ds, int64_t N, int Rg,

@@ -120,6 +120,7 @@ struct ssmap_ctx {
     bool aux_valid = false;
     int aux_mode = 0;
     int aux_iters = 0;
+    int aux_ld = 0;                       // aux_f / aux_d: 0 chunked state; > 0 voxel-major float32 rows
     void *aux_f = nullptr, *aux_d = nullptr;
     // masked voxel set (empty code: the whole box)
     std::vector<uint8_t> code;
@@ -320,11 +321,9 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_sp
     p.fused = st->kernel == SSMAP_KERNEL_FUSED || (st->kernel == SSMAP_KERNEL_AUTO && can_fuse);
     // GEMM path: float32 / bf16x3 without aux output or primal residual (f is never
     // formed there); AUTO takes it where no fused kernel exists
-    const bool gemm_ok = p.mode != MODE_FP64 &&
-                         !(st->flags & (SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL | SSMAP_WARM_START));
+    const bool gemm_ok = p.mode != MODE_FP64 && !(st->flags & (SSMAP_MONITOR_PRIMAL | SSMAP_WARM_START));
     if (st->kernel == SSMAP_KERNEL_GEMM && !gemm_ok)
-        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without aux output, primal residual "
-                           "or warm start");
+        fail(SSMAP_EINVAL, "the GEMM path runs float32 or bf16x3 without primal residual or warm start");
     p.gemm = st->kernel == SSMAP_KERNEL_GEMM || (st->kernel == SSMAP_KERNEL_AUTO && !can_fuse && gemm_ok);
     // Chunk split: float64 / float32 grids with few bricks and short spectra, where
     // one workgroup per brick would leave most CUs idle (no aux output or primal
@@ -600,6 +599,10 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     P.glib = c->lg && libgemm_tn(c->lg, bf, nullptr, nullptr, nullptr, Qg, N, Ku, s) &&
              libgemm_tn(c->lg, bf, nullptr, nullptr, nullptr, Rg, N, Ky, s);
     P.nseg = P.glib ? 3 : 2;
+    // f and d need u^k, which only the library products leave in memory
+    if (P.aux && !P.glib)
+        fail(SSMAP_EINVAL, "aux output on the GEMM path needs the hipBLASLt products "
+                           "(none for this shape): use SSMAP_KERNEL_UNFUSED");
     std::vector<std::pair<std::string, size_t>> need = {
         {"gz0", zb}, {"gz1", zb}, {"gs", rb}, {"gah", rb}, {"gt0", tb}, {"gt1", tb},
         {"gb", (size_t)Rg * 4}, {"gAu", (size_t)Qg * Ku * esA}, {"gAy", (size_t)Rg * Ky * esA},
@@ -614,6 +617,10 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
         need.push_back({"gU", zb});
         need.push_back({"gY", rb});
     }
+    if (P.aux) {
+        need.push_back({"gaux0", zb});
+        need.push_back({"gaux1", zb});
+    }
     if (P.monitor) {
         need.push_back({"t", (size_t)r * N * 8});
         need.push_back({"mperp2", (size_t)N * 8});
@@ -623,6 +630,12 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
     }
     plan_check(c, need);
     for (int k = 0; k < 2; ++k) P.gz[k] = (float *)ensure(c, k ? "gz1" : "gz0", zb);
+    if (P.aux) {                  // f and d around the last two iterations (voxel-major)
+        P.dbuf = ensure(c, "gaux0", zb);
+        P.tbuf = ensure(c, "gaux1", zb);
+        launch_zero(P.dbuf, (size_t)N * Qg, 4, s);
+        launch_zero(P.tbuf, (size_t)N * Qg, 4, s);
+    }
     P.gs = (float *)ensure(c, "gs", rb);
     P.gah = (float *)ensure(c, "gah", rb);
     // rank-major projection temporaries: a.h (= w^0) and y^0
@@ -749,6 +762,8 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
 // One GEMM-path iteration k: u = V_r w^k with the z-update as its epilogue, then
 // y^{k+1} = V_r^T z^{k+1} with the r-vector recursion as its epilogue. Both
 // launches are bracketed by timing events (stats.gemm_ms).
+bool wants_f(const Prepared &P, int k);
+
 void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     const Plan &pl = P.pl;
     const bool bf = pl.mode == MODE_BF16X3;
@@ -766,6 +781,14 @@ void step_gemm(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
         if (!libgemm_tn(c->lg, bf, P.gAu, Bu, P.gU, Qg, N, Ku, s)) fail(SSMAP_EDEVICE, "hipBLASLt product failed");
         HIPC(c, hipEventRecord(ev[1], s));
         launch_epi_z(P.gU, z, zn, bf ? P.gzs : nullptr, c->g, Qg, pl.tau, 2.0 * pl.lam, pl.beta, mask_dev(c), s);
+        // f^{k+1} and d^{k+1} around the last two iterations (as the fused path's
+        // bracket; afterwards dbuf holds d^{k+1}, tbuf f^{k+1})
+        const bool need_f = wants_f(P, k);
+        if (need_f || wants_f(P, k + 1)) {
+            launch_gemm_aux(z, P.gU, zn, need_f && k > 0 ? (const float *)P.dbuf : nullptr,
+                            need_f ? (float *)P.dbuf : nullptr, (float *)P.tbuf, (size_t)N * Qg, pl.beta, s);
+            std::swap(P.dbuf, P.tbuf);
+        }
         HIPC(c, hipEventRecord(ev[2], s));
         if (!libgemm_tn(c->lg, bf, P.gAy, By, P.gY, Rg, N, Ky, s)) fail(SSMAP_EDEVICE, "hipBLASLt product failed");
         HIPC(c, hipEventRecord(ev[3], s));
@@ -800,6 +823,14 @@ void finish_gemm(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
     }
     S.gemm_ms = ms;
     S.gemm_library = P.glib ? 1 : 0;
+    if (P.aux) {
+        c->aux_valid = true;
+        c->aux_mode = MODE_FP32;
+        c->aux_iters = iters;
+        c->aux_f = P.tbuf;
+        c->aux_d = P.dbuf;
+        c->aux_ld = P.pl.Qg;
+    }
     const bool bf = P.pl.mode == MODE_BF16X3;
     S.gemm_flops = 2.0 * 2.0 * (double)P.pl.Qg * P.pl.Rg * (bf ? 3.0 : 1.0) * (double)c->g.N * iters;
 }
@@ -976,6 +1007,7 @@ void finish(ssmap_ctx *c, const Prepared &P, void *dF, hipStream_t s) {
         c->aux_iters = iters;
         c->aux_f = P.tbuf;
         c->aux_d = P.dbuf;
+        c->aux_ld = 0;
     }
 }
 
@@ -1575,7 +1607,10 @@ ssmap_status ssmap_get_aux(ssmap_ctx *ctx, double *f_out, double *d_out) {
                 std::memset(dst[k], 0, nf * 8);
                 continue;
             }
-            launch_output(ctx->aux_mode, src[k], tmp, ctx->Q, N, true, nullptr);
+            if (ctx->aux_ld > 0)       // GEMM path: voxel-major float32 rows of aux_ld
+                launch_gemm_output((const float *)src[k], tmp, true, N, ctx->Q, ctx->aux_ld, nullptr);
+            else
+                launch_output(ctx->aux_mode, src[k], tmp, ctx->Q, N, true, nullptr);
             HIPC(ctx, hipGetLastError());
             HIPC(ctx, hipMemcpy(dst[k], tmp, nf * 8, hipMemcpyDeviceToHost));
         }

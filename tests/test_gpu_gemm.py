@@ -70,6 +70,8 @@ def test_auto_takes_the_gemm_path_above_rank_32(torch_cuda):
         assert mp.stats()["kernel"] == 3
         mp.solve(p.m, p.lam, p.beta, 10, precision="fp32", rank=40, check_every=5, primal=True)
         assert mp.stats()["kernel"] == 1
+        mp.solve(p.m, p.lam, p.beta, 10, precision="fp32", rank=40, keep_aux=True)
+        assert mp.stats()["kernel"] == 3
         mp.solve(p.m, p.lam, p.beta, 10, precision="fp32")
         assert mp.stats()["kernel"] == 2
 
@@ -90,8 +92,30 @@ def test_gemm_path_with_a_mask(torch_cuda):
 def test_gemm_path_rejections(torch_cuda):
     p = synth.generate("c1", grid=(6, 5, 1))
     with _ffi.Mapper(p.K, p.grid) as mp:
-        for kw in (dict(precision="fp64"), dict(precision="fp32", check_every=5, primal=True),
-                   dict(precision="fp32", keep_aux=True)):
+        for kw in (dict(precision="fp64"), dict(precision="fp32", check_every=5, primal=True)):
             with pytest.raises(_ffi.SsmapError) as e:
                 mp.solve(p.m, p.lam, p.beta, 5, kernel="gemm", **kw)
             assert e.value.status == _ffi.SSMAP_EINVAL, kw
+
+
+AUX_CASES = [("c3", (10, 9, 4), -1, 20), ("c2", (13, 6, 1), 45, 25), ("c2", (9, 8, 3), 40, 1)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("recipe,grid,rank,iters", AUX_CASES)
+def test_gemm_path_aux_output(torch_cuda, recipe, grid, rank, iters, prec):
+    """f^K and d^K from the library path's bracket (Algorithm 2's f- and d-steps
+    from z^k, u^k = V_r w^k and z^{k+1}) against the oracle at ten times the
+    tolerance, d's denominator floored at beta ||z|| as elsewhere."""
+    p = synth.generate(recipe, grid=grid, iters=iters)
+    ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters, rank=rank)
+    with _ffi.Mapper(p.K, p.grid) as mp:
+        F = mp.solve(p.m, p.lam, p.beta, iters, precision=prec, rank=rank, kernel="gemm", keep_aux=True)
+        st = mp.stats()
+        f, d = mp.aux()
+    floor = p.beta * np.linalg.norm(ref["z"])
+    ef, ed = relerr(f, ref["f"]), np.linalg.norm(d - ref["d"]) / max(np.linalg.norm(ref["d"]), floor)
+    say(recipe, grid, "rank", ref["rank"], prec, "z", relerr(F, ref["z"]), "f", ef, "d", ed)
+    assert st["kernel"] == 3 and st["gemm_library"] == 1
+    assert relerr(F, ref["z"]) <= TOL[prec]
+    assert ef <= 10 * TOL[prec] and ed <= 10 * TOL[prec]
