@@ -324,10 +324,11 @@ ssmap_status ssmap_batch_set_mask(ssmap_batch *b, int job, const uint8_t *mask);
 
 /* Solve every job for `iters` iterations on device buffers, ordered on
  * `hip_stream`. dM[j] / dF[j] as in ssmap_solve_device for job j; lambda and
- * steps are per job (njobs entries). steps[j].check_every must be 0 and
- * SSMAP_KEEP_AUX and SSMAP_WARM_START unset (use the single-problem entry
- * points for those). Each job's map equals, bit for bit, its single solve with
- * SSMAP_KERNEL_FUSED (and its mask).
+ * steps are per job (njobs entries). steps[j].check_every may be set per job
+ * (its history then goes to ssmap_batch_get_job_stats); stop_tol must be 0 and
+ * SSMAP_KEEP_AUX, SSMAP_MONITOR_PRIMAL and SSMAP_WARM_START unset (use the
+ * single-problem entry points for those). Each job's map equals, bit for bit,
+ * its single solve with SSMAP_KERNEL_FUSED (and its mask).
  * SSMAP_AUTOTUNE in any job's flags turns the shape search on; the shapes it
  * chooses are kept in `b` and used by its later solves of the same classes
  * (same precision, rank bucket and member jobs) until it is destroyed. */
@@ -340,6 +341,12 @@ ssmap_status ssmap_batch_solve(ssmap_batch *b, const double *const *M, const dou
                                const ssmap_steps *steps, int iters, double *const *F_out);
 
 ssmap_status ssmap_batch_get_stats(const ssmap_batch *b, ssmap_batch_stats *out);
+
+/* Statistics of job `job` in the last batch solve, as ssmap_get_stats for a
+ * single problem: rank, xi_p, precision, and with check_every > 0 the job's
+ * monitoring history (objective, dual residual, ||z||, DFCS against a reference
+ * is not available in batches). EINVAL for a job index out of range. */
+ssmap_status ssmap_batch_get_job_stats(const ssmap_batch *b, int job, ssmap_stats *out);
 
 /* Message for the last failure on b (or of the last failed ssmap_batch_create when b is NULL). */
 const char *ssmap_batch_last_error(const ssmap_batch *b);

@@ -35,7 +35,8 @@ EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_dev
            "ssmap_destroy", "ssmap_version", "ssmap_set_mask", "ssmap_set_reference",
            "ssmap_set_initial", "ssmap_tune_beta",
            "ssmap_batch_create", "ssmap_batch_set_mask", "ssmap_batch_solve", "ssmap_batch_solve_device",
-           "ssmap_batch_get_stats", "ssmap_batch_last_error", "ssmap_batch_destroy",
+           "ssmap_batch_get_stats", "ssmap_batch_get_job_stats", "ssmap_batch_last_error",
+           "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
            "ssmap_server_pump", "ssmap_server_poll", "ssmap_server_drain",
            "ssmap_server_get_stats", "ssmap_server_last_error", "ssmap_server_destroy"]
@@ -168,6 +169,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_batch_solve_device.restype = ip
     lib.ssmap_batch_get_stats.argtypes = [vp, ctypes.POINTER(BatchStats)]
     lib.ssmap_batch_get_stats.restype = ip
+    lib.ssmap_batch_get_job_stats.argtypes = [vp, ip, ctypes.POINTER(Stats)]
+    lib.ssmap_batch_get_job_stats.restype = ip
     lib.ssmap_batch_last_error.argtypes = [vp]
     lib.ssmap_batch_last_error.restype = ctypes.c_char_p
     lib.ssmap_batch_destroy.argtypes = [vp]
@@ -263,6 +266,10 @@ def ssmap_get_aux(ctx: int, N: int, Q: int):
 def ssmap_get_stats(ctx: int) -> dict:
     s = Stats()
     _check(ctx, load().ssmap_get_stats(ctx, ctypes.byref(s)))
+    return _stats_dict(s)
+
+
+def _stats_dict(s: "Stats") -> dict:
     n = s.n_hist
     return dict(rank=s.rank, rank_padded=s.rank_padded, precision=s.precision, kernel=s.kernel,
                 iters=s.iters, xi_p=s.xi_p, tau=s.tau, dtd_norm=s.dtd_norm,
@@ -437,6 +444,12 @@ def _bcheck(b, st):
         raise SsmapError(st, load().ssmap_batch_last_error(b).decode())
 
 
+def ssmap_batch_get_job_stats(b, job: int) -> dict:
+    s = Stats()
+    _bcheck(b, load().ssmap_batch_get_job_stats(b, int(job), ctypes.byref(s)))
+    return _stats_dict(s)
+
+
 def ssmap_batch_set_mask(b, job: int, mask) -> None:
     """mask: N_job booleans, or None for the whole box."""
     if mask is None:
@@ -495,6 +508,9 @@ class BatchMapper:
         self.grids = [tuple(int(v) for v in g) for g in grids]
         self.N = [g[0] * g[1] * g[2] for g in self.grids]
         self.b = ssmap_batch_create(self.Ks, self.grids)
+
+    def job_stats(self, job) -> dict:
+        return ssmap_batch_get_job_stats(self.b, job)
 
     def set_mask(self, job, mask) -> None:
         if mask is not None and np.size(mask) != self.N[job]:

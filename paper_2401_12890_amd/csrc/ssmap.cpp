@@ -1079,6 +1079,11 @@ struct BatchClass {
     std::vector<int> jobs;
     FusedShape shape{16, 1};
     int ntiles = 0;
+    // monitored members: each member's bricks are one contiguous run of the brick
+    // table (tile_off, tile_cnt per member), so the monitored build's per-brick
+    // sums of (z^{k+1} - z^k)^2 in `mon` split by job
+    std::vector<int> tile_off, tile_cnt;
+    double *mon = nullptr;
 };
 
 }  // namespace
@@ -1103,19 +1108,26 @@ std::string g_batch_create_error;
 // u K-step bucket of the rank) and whether the grids are planar.
 int rank_bucket(int r) { return r <= 16 ? 0 : r <= 20 ? 1 : r <= 24 ? 2 : 3; }
 
-void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector<Prepared> &Ps,
+void upload_class(ssmap_batch *b, int ci, BatchClass &C, const std::vector<Prepared> &Ps,
                   FusedShape shape, FusedLaunch &L, hipStream_t s) {
     std::vector<IterArgs> args(2 * C.jobs.size());
     std::vector<TileRef> tiles;
+    C.tile_off.assign(C.jobs.size(), 0);
+    C.tile_cnt.assign(C.jobs.size(), 0);
+    bool monitored = false;
     for (size_t k = 0; k < C.jobs.size(); ++k) {
         const int j = C.jobs[k];
         args[2 * k] = args_for(Ps[j], 0);                    // even iterations
         args[2 * k + 1] = args_for(Ps[j], 1);                // odd iterations
+        C.tile_off[k] = (int)tiles.size();
         append_tiles(b->jobs[j]->g, (int)k, C.mode, shape, tiles,
                      b->jobs[j]->code.empty() ? nullptr : &b->jobs[j]->code);
+        C.tile_cnt[k] = (int)tiles.size() - C.tile_off[k];
+        monitored |= Ps[j].monitor;
     }
     ssmap_ctx *A = &b->arena;
     const std::string tag = std::to_string(ci);
+    C.mon = monitored ? (double *)ensure(A, "cls_mon" + tag, std::max<size_t>(1, tiles.size()) * 8) : nullptr;
     IterArgs *dj = (IterArgs *)ensure(A, "cls_jobs" + tag, args.size() * sizeof(IterArgs));
     TileRef *dt = (TileRef *)ensure(A, "cls_tiles" + tag, tiles.size() * sizeof(TileRef));
     HIPC(A, hipMemcpyAsync(dj, args.data(), args.size() * sizeof(IterArgs), hipMemcpyHostToDevice, s));
@@ -1134,9 +1146,11 @@ void upload_class(ssmap_batch *b, int ci, const BatchClass &C, const std::vector
 
 // One shared launch of iteration k (jobs[2j], jobs[2j+1]: job j's even and
 // odd descriptors; a brick names its job by index).
-void launch_class(ssmap_batch *b, const FusedLaunch &L, size_t njobs, int k, hipStream_t s) {
+void launch_class(ssmap_batch *b, const FusedLaunch &L, size_t njobs, int k, hipStream_t s,
+                  double *mon = nullptr) {
     FusedLaunch Lk = L;
     Lk.round = k;
+    Lk.mon = mon;
     if (!launch_fused(Lk, s)) fail(SSMAP_EINVAL, "no fused kernel for this brick shape");
     (void)b;
     (void)njobs;
@@ -1149,8 +1163,10 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
     for (int j = 0; j < nj; ++j) {
         if (!dM[j] || !dF[j]) fail(SSMAP_EINVAL, "NULL buffer for job " + std::to_string(j));
         validate_steps(b->jobs[j], lambda[j], &steps[j], iters);
-        if (steps[j].check_every != 0 || (steps[j].flags & (SSMAP_KEEP_AUX | SSMAP_WARM_START)))
-            fail(SSMAP_EINVAL, "batches take no monitoring, no SSMAP_KEEP_AUX and no warm start");
+        if (steps[j].stop_tol != 0 ||
+            (steps[j].flags & (SSMAP_KEEP_AUX | SSMAP_WARM_START | SSMAP_MONITOR_PRIMAL)))
+            fail(SSMAP_EINVAL, "batches take no stopping rule, primal residual, SSMAP_KEEP_AUX or "
+                               "warm start");
         tune |= (steps[j].flags & SSMAP_AUTOTUNE) != 0;
     }
     ssmap_batch_stats &S = b->stats;
@@ -1244,13 +1260,37 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
                                                                   t_tune).count();
     // single-job launch plans of the solo jobs (unfused, or beyond the class limit)
     std::vector<FusedLaunch> solo_L(solo.size());
-    for (size_t i = 0; i < solo.size(); ++i)
+    for (size_t i = 0; i < solo.size(); ++i) {
         if (Ps[solo[i]].pl.fused) solo_L[i] = single_launch(b->jobs[solo[i]], Ps[solo[i]], s);
+        Ps[solo[i]].ntiles = solo_L[i].ntiles;
+    }
+    // monitored jobs: the sums of each job after the iteration, into its own stats
+    auto monitor = [&](int j, int k) {
+        try {
+            (void)monitor_step(b->jobs[j], Ps[j], k, s);
+        } catch (const Fail &f) {
+            throw Fail{f.status, "job " + std::to_string(j) + ": " + f.msg};
+        }
+    };
     // ---- the shared iteration loop
     HIPC(&b->arena, hipEventRecord(b->ev[2], s));
     for (int k = 0; k < iters; ++k) {
-        for (size_t c = 0; c < classes.size(); ++c) launch_class(b, Ls[c], classes[c].jobs.size(), k, s);
+        for (size_t c = 0; c < classes.size(); ++c) {
+            bool any = false;
+            for (int j : classes[c].jobs) any |= checked_after(Ps[j], k);
+            launch_class(b, Ls[c], classes[c].jobs.size(), k, s, any ? classes[c].mon : nullptr);
+        }
         for (size_t i = 0; i < solo.size(); ++i) step_job(b->jobs[solo[i]], Ps[solo[i]], &solo_L[i], k, s);
+        for (size_t c = 0; c < classes.size(); ++c)
+            for (size_t m = 0; m < classes[c].jobs.size(); ++m) {
+                const int j = classes[c].jobs[m];
+                if (!checked_after(Ps[j], k)) continue;
+                Ps[j].monpart = classes[c].mon + classes[c].tile_off[m];
+                Ps[j].ntiles = classes[c].tile_cnt[m];
+                monitor(j, k);
+            }
+        for (int j : solo)
+            if (checked_after(Ps[j], k)) monitor(j, k);
     }
     HIPC(&b->arena, hipGetLastError());
     HIPC(&b->arena, hipEventRecord(b->ev[3], s));
@@ -1682,6 +1722,12 @@ ssmap_status ssmap_batch_solve_device(ssmap_batch *b, const void *const *dM, con
         HIPC(&b->arena, hipSetDevice(b->jobs[0]->device));
         batch_solve_impl(b, dM, lambda, steps, iters, dF, (hipStream_t)hip_stream);
     });
+}
+
+ssmap_status ssmap_batch_get_job_stats(const ssmap_batch *b, int job, ssmap_stats *out) {
+    if (!b || !out || job < 0 || job >= (int)b->jobs.size()) return SSMAP_EINVAL;
+    *out = b->jobs[job]->stats;
+    return SSMAP_OK;
 }
 
 ssmap_status ssmap_batch_set_mask(ssmap_batch *b, int job, const uint8_t *mask) {

@@ -126,9 +126,10 @@ def test_batch_errors(torch_cuda, slices):
         with pytest.raises(_ffi.SsmapError) as e:
             bm.solve(*args, keep_aux=True)
         assert e.value.status == _ffi.SSMAP_EINVAL
-        with pytest.raises(_ffi.SsmapError) as e:
-            bm.solve(*args, check_every=1)
-        assert e.value.status == _ffi.SSMAP_EINVAL
+        for kw in (dict(check_every=1, stop_tol=1e-3), dict(check_every=1, primal=True)):
+            with pytest.raises(_ffi.SsmapError) as e:
+                bm.solve(*args, **kw)
+            assert e.value.status == _ffi.SSMAP_EINVAL, kw
         bad = [p.m.copy() for p in jobs]
         bad[2][0, 0] = np.inf
         with pytest.raises(_ffi.SsmapError) as e:
@@ -182,3 +183,43 @@ def test_batch_with_masks_equals_masked_solo_and_oracle(torch_cuda, slices, prec
         assert err <= TOL[prec], (p.grid, err)
         if mk is not None:
             assert np.all(Fb[~mk] == 0.0)
+
+
+def test_batch_monitoring_per_job(torch_cuda, slices):
+    """check_every per job in a batch (ssmap_batch_get_job_stats): each monitored
+    job's history equals its single solve's (objective and ||z|| to 1e-12; the
+    dual residual to 1e-5, its per-brick float32 partial sums being grouped by
+    the class's brick shape) and the oracle's objective within 1e-4; a job at
+    the unapproximated rank runs outside the shared launches and is monitored
+    on its own path; a job with check_every = 0 has no history."""
+    iters = 20
+    jobs = slices[:4]
+    ranks = [-1, 0, 0, 0]            # job 0: P = 60, Q = 100, so r = 60, outside the fused classes
+    every = [5, 10, 0, 4]
+    steps = [_ffi.make_steps(p.beta, rank=r, precision="fp32", check_every=e)
+             for p, r, e in zip(jobs, ranks, every)]
+    with _ffi.BatchMapper([p.K for p in jobs], [p.grid for p in jobs]) as bm:
+        F = _ffi.ssmap_batch_solve(bm.b, [p.m for p in jobs], [p.lam for p in jobs], steps, iters,
+                                   [(p.N, p.Q) for p in jobs])
+        sts = [bm.job_stats(j) for j in range(len(jobs))]
+        with pytest.raises(_ffi.SsmapError):
+            bm.job_stats(len(jobs))
+    for p, r, e, st, Fb in zip(jobs, ranks, every, sts, F):
+        if e == 0:
+            assert st["hist_iter"] == []
+            continue
+        assert st["hist_iter"] == list(range(e, iters + 1, e))
+        kw = {} if r == -1 and min(p.P, p.Q) > 32 else {"kernel": "fused"}
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            Fs = mp.solve(p.m, p.lam, p.beta, iters, precision="fp32", rank=r, check_every=e, **kw)
+            one = mp.stats()
+        assert np.array_equal(Fb, Fs)
+        ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters, rank=r, track_every=e)
+        J = {k: v for (k, v, _) in ref["hist"]}
+        say("monitored job", p.grid, "rank", st["rank"], "kernel", st["kernel"], "J", st["hist_objective"][-1])
+        assert st["kernel"] == one["kernel"] and (r != -1 or st["kernel"] == 3)
+        for i, k in enumerate(st["hist_iter"]):
+            assert st["hist_objective"][i] == pytest.approx(one["hist_objective"][i], rel=1e-12)
+            assert st["hist_znorm"][i] == pytest.approx(one["hist_znorm"][i], rel=1e-12)
+            assert st["hist_dual"][i] == pytest.approx(one["hist_dual"][i], rel=1e-5)
+            assert st["hist_objective"][i] == pytest.approx(J[k], rel=1e-4)
