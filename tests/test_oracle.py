@@ -356,6 +356,64 @@ def test_fullsize_golden_values_come_from_the_oracle():
     assert [s["voxel"] for s in gold["samples"]] == [list(p) for p in mk.points(prob.grid)]
 
 
+def test_iters300_golden_files_are_consistent_with_their_script_and_rules():
+    """The stored 300-iteration oracle results (too long to recompute here) carry
+    the rank of the oracle's rule on the recipe's dictionary (it does not depend
+    on the grid), the xi_p rule's value on the full grid, the recipe's lambda and
+    beta and the script's sample voxels; their sums agree with each other and with
+    the sampled Q-vectors (a mix-up of stored arrays fails here)."""
+    import importlib.util
+    path = os.path.join(GOLDEN, "make_iters300_golden.py")
+    spec = importlib.util.spec_from_file_location("make_iters300_golden", path)
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    for case, cfg in mk.CASES.items():
+        g = np.load(os.path.join(GOLDEN, f"iters300_{case}.npz"))
+        grid = tuple(int(v) for v in g["grid"])
+        small = synth.generate(cfg["recipe"], grid=(4, 4, 2))
+        if cfg["grid"] is not None:
+            assert grid == tuple(cfg["grid"])
+        assert int(g["iters"]) == mk.ITERS
+        assert int(g["rank"]) == oracle.rank_rule(oracle.thin_svd(small.K)[1], 0)
+        assert float(g["xi_p"]) == oracle.xi_rule(small.lam, grid)
+        assert float(g["lam"]) == small.lam and float(g["beta"]) == small.beta
+        pts = mk.sample_voxels(grid, cfg["brick"])
+        nx, ny, _ = grid
+        assert np.array_equal(g["index"], [x + nx * (y + ny * z) for (x, y, z) in pts])
+        total = float(g["z_sum_q"].sum())
+        assert float(g["z_sum_n"].sum()) == pytest.approx(total, rel=1e-12)
+        assert float(np.sqrt((g["z_norm_q"] ** 2).sum())) == pytest.approx(float(g["norm_z"]), rel=1e-12)
+        np.testing.assert_allclose(g["z"].sum(axis=1), g["z_sum_q"][g["index"]], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(np.linalg.norm(g["z"], axis=1), g["z_norm_q"][g["index"]],
+                                   rtol=1e-12, atol=1e-15)
+
+
+def test_batch200_golden_values_come_from_the_oracle():
+    """The stored configured-batch values are the oracle's: recompute the smallest
+    stored slice (4,320 voxels, Q = 100) at the configured 200 iterations, and
+    check the other stored slices' sample indices and ranks against the generator
+    and the rank rule."""
+    import importlib.util
+    path = os.path.join(GOLDEN, "make_batch200_golden.py")
+    spec = importlib.util.spec_from_file_location("make_batch200_golden", path)
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    g = np.load(os.path.join(GOLDEN, "batch200_c4.npz"))
+    probs = synth.generate_batch()
+    chosen = mk.chosen_slices(probs)
+    assert [p.meta["slice"] for p in chosen] == [int(k) for k in g["slices"]]
+    for p in chosen:
+        k = p.meta["slice"]
+        assert np.array_equal(g[f"s{k}_index"], mk.sample_voxels(p.grid))
+        assert int(g[f"s{k}_rank"]) == oracle.rank_rule(oracle.thin_svd(p.K)[1], 0)
+    p = min(chosen, key=lambda p: p.N)
+    k = p.meta["slice"]
+    ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, int(g["iters"]))
+    np.testing.assert_allclose(ref["z"][g[f"s{k}_index"]], g[f"s{k}_z"], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(ref["z"].sum(axis=1), g[f"s{k}_z_sum_q"], rtol=1e-10, atol=1e-13)
+    assert float(np.linalg.norm(ref["z"])) == pytest.approx(float(g[f"s{k}_norm_z"]), rel=1e-12)
+
+
 def test_bench_uses_the_oracle_only_in_its_cpu_baseline():
     import ast
     src = open(os.path.join(os.path.dirname(GOLDEN), "..", "bench.py")).read()
