@@ -6,11 +6,12 @@
 // op(A) = A^T (A stored K x M) and op(B) = B (stored K x N). Each distinct shape
 // gets its matmul descriptor, layouts and up to kCandidates of the library's
 // heuristic algorithms once; the first product of a shape times each candidate
-// on the caller's stream (one warm-up and three timed runs) and keeps the
-// library's first choice unless another is more than 2 % faster (timings of
-// near-equal kernels are noisy), for the life of the context, so repeated
-// solves use one algorithm (one summation order). The workspace is allocated
-// once.
+// on the caller's stream in two rounds (one warm-up, then three timed runs per
+// round; a candidate's time is its better round, which takes out the first
+// runs' clock and cache effects and the order of the candidates) and keeps the
+// library's first choice unless another is more than 2 % faster, for the life
+// of the context, so repeated solves use one algorithm (one summation order).
+// The workspace is allocated once.
 #include "internal.h"
 
 #include <hip/hip_runtime_api.h>
@@ -131,23 +132,25 @@ bool libgemm_tn(LibGemm *g, bool bf16, const void *A, const void *B, float *C, i
         if (p->cands.size() > 1) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-                float first = -1.0f, best = -1.0f;
-                for (size_t i = 0; i < p->cands.size(); ++i) {
-                    const auto &algo = p->cands[i];
-                    float ms = 0.0f;
-                    if (!run(algo) || hipEventRecord(e0, s) != hipSuccess || !run(algo) || !run(algo) ||
-                        !run(algo) || hipEventRecord(e1, s) != hipSuccess ||
-                        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        (void)hipGetLastError();
-                        continue;
+                const size_t nc = p->cands.size();
+                std::vector<float> t(nc, -1.0f);
+                for (int round = 0; round < 2; ++round)
+                    for (size_t i = 0; i < nc; ++i) {
+                        const auto &algo = p->cands[i];
+                        float ms = 0.0f;
+                        if ((round == 0 && !run(algo)) || hipEventRecord(e0, s) != hipSuccess || !run(algo) ||
+                            !run(algo) || !run(algo) || hipEventRecord(e1, s) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                            (void)hipGetLastError();
+                            continue;
+                        }
+                        if (t[i] < 0.0f || ms < t[i]) t[i] = ms;
                     }
-                    if (i == 0) first = ms;
-                    if (best < 0.0f || ms < best) {
-                        best = ms;
-                        p->algo = algo;
-                    }
-                }
-                if (first > 0.0f && best > 0.98f * first) p->algo = p->cands[0];
+                size_t bi = 0;
+                for (size_t i = 1; i < nc; ++i)
+                    if (t[i] > 0.0f && (t[bi] < 0.0f || t[i] < t[bi])) bi = i;
+                p->algo = p->cands[(t[0] > 0.0f && t[bi] > 0.98f * t[0]) ? 0 : bi];
             }
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);
