@@ -9,14 +9,20 @@
 // on the caller's stream in two rounds (one warm-up, then three timed runs per
 // round; a candidate's time is its better round, which takes out the first
 // runs' clock and cache effects and the order of the candidates) and keeps the
-// library's first choice unless another is more than 2 % faster, for the life
-// of the context, so repeated solves use one algorithm (one summation order).
-// The workspace is allocated once.
+// library's first choice unless another is more than 2 % faster. The choice is
+// kept for the life of the process, per device and shape, and every later
+// context takes it without timing, so that all solves of a shape in a process
+// use one algorithm (one summation order) and give identical results, whichever
+// context runs them (a batch job and the same problem solved alone). The
+// workspace is allocated once per context.
 #include "internal.h"
 
 #include <hip/hip_runtime_api.h>
 #include <hipblaslt/hipblaslt.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 namespace ssmap {
@@ -43,6 +49,20 @@ namespace {
 
 constexpr size_t kWorkspace = (size_t)64 << 20;
 constexpr int kCandidates = 8;
+
+// The process's choices: (device, bf16, M, N, K) -> index into the heuristic's
+// candidate list (the same list for the same shape on the same device).
+using ChoiceKey = std::tuple<int, bool, int, int64_t, int>;
+std::mutex g_choice_mu;
+std::map<ChoiceKey, size_t> g_choice;
+
+bool chosen(const ChoiceKey &k, size_t &idx) {
+    std::lock_guard<std::mutex> lk(g_choice_mu);
+    auto it = g_choice.find(k);
+    if (it == g_choice.end()) return false;
+    idx = it->second;
+    return true;
+}
 
 LibGemm::Plan *plan_for(LibGemm *g, bool bf16, int M, int64_t N, int K) {
     for (auto &p : g->plans)
@@ -129,7 +149,13 @@ bool libgemm_tn(LibGemm *g, bool bf16, const void *A, const void *B, float *C, i
     };
     if (!p->tuned) {
         p->tuned = true;
-        if (p->cands.size() > 1) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const ChoiceKey key{dev, bf16, M, N, K};
+        size_t idx = 0;
+        if (chosen(key, idx) && idx < p->cands.size()) {
+            p->algo = p->cands[idx];
+        } else if (p->cands.size() > 1) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
                 const size_t nc = p->cands.size();
@@ -150,7 +176,10 @@ bool libgemm_tn(LibGemm *g, bool bf16, const void *A, const void *B, float *C, i
                 size_t bi = 0;
                 for (size_t i = 1; i < nc; ++i)
                     if (t[i] > 0.0f && (t[bi] < 0.0f || t[i] < t[bi])) bi = i;
-                p->algo = p->cands[(t[0] > 0.0f && t[bi] > 0.98f * t[0]) ? 0 : bi];
+                idx = (t[0] > 0.0f && t[bi] > 0.98f * t[0]) ? 0 : bi;
+                std::lock_guard<std::mutex> lk(g_choice_mu);
+                idx = g_choice.emplace(key, idx).first->second;   // a choice made meanwhile wins
+                p->algo = p->cands[idx < p->cands.size() ? idx : 0];
             }
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);
