@@ -49,6 +49,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def workload_label(name, default_prec, prec):
+    """The workload's description, naming the precision actually run."""
+    label = WORKLOADS[name]
+    return label if prec == default_prec else label.replace(default_prec, prec)
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -630,8 +636,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE_NAME[prec], "data": "synthetic (seeded generator, no dataset)",
-        "config": {"workload": WORKLOADS[args.workload] if args.grid is None else
-                   f"{args.workload} recipe on a {'x'.join(map(str, prob.grid))} grid",
+        "config": {"workload": workload_label(args.workload, prob.precision, prec) if args.grid is None
+                   else f"{args.workload} recipe on a {'x'.join(map(str, prob.grid))} grid",
                    "grid": list(prob.grid), "P": prob.P,
                    "Q": prob.Q, "rank": r, "iters": iters, "lambda": prob.lam,
                    "beta": prob.beta, "precision": prec, "kernel": kern_name},

@@ -145,7 +145,9 @@ struct MonArgs {
     const double *fstar;      // reference map for DFCS (N x Q float64, voxel-major), or NULL
     const double *V64;        // V_r in float64, (16 nchunk) x RP, zero padded
     const void *y;            // y = V_r^T z as the iteration left it (state type, RP x N
-                              // rank-major), or NULL: the monitor contracts V64 with z
+                              // rank-major, or voxel-major rows of yld), or NULL: the
+                              // monitor contracts V64 with z
+    int64_t yld;              // > 0: y voxel-major, element (r, n) at n yld + r
     const double *dzpart;     // per-brick sums of (z - zprev)^2 from the iteration, or NULL
     int ndz;
     const double *sig, *t, *mperp2;   // singular values (RP), U_r^T m (r x N), ||m_perp||^2 (N)

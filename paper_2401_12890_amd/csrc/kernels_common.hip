@@ -345,7 +345,8 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
         const bool contract = a.y == nullptr;
         if (!contract && valid)             // data term from the iteration's y
             for (int rr = i4; rr < a.r; rr += 4) {
-                const double yv = (double)((const T *)a.y)[(size_t)rr * N + n];
+                const double yv = (double)((const T *)a.y)[a.yld > 0 ? (size_t)n * a.yld + rr
+                                                                     : (size_t)rr * N + n];
                 const double e = a.t[(size_t)rr * N + n] - a.sig[rr] * yv;
                 acc[ST_DATA] += e * e;
             }
@@ -863,7 +864,7 @@ int monitor_blocks(int64_t N) {
 
 void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hipStream_t s) {
     const int64_t esz = mode == MODE_FP64 ? 8 : 4;
-    if (a.y && a.ld == 0 && a.nchunk > 0 && a.nchunk <= kMonitorBlocks &&
+    if (a.y && a.ld == 0 && a.yld == 0 && a.nchunk > 0 && a.nchunk <= kMonitorBlocks &&
         a.g.N * QC * esz + 64 < ((int64_t)1 << 31)) {
         // one pass along z: about as many blocks as the device runs at once (no tail)
         const bool extra = a.zprev || a.f || a.fstar;

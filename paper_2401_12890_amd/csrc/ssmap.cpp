@@ -870,6 +870,10 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
         m.zprev = P.gz[k & 1];
         m.ld = pl.Qg;
         m.nchunk = pl.Qg / QC;
+        if (P.glib) {                // the library product left y^{k+1} = V_r^T z^{k+1} (N x Rg)
+            m.y = P.gY;
+            m.yld = pl.Rg;
+        }
     } else {
         // the iteration left y^{k+1} = V_r^T z^{k+1} in its r-vector state; the fused
         // kernel also summed (z^{k+1} - z^k)^2 per brick
