@@ -108,7 +108,12 @@ typedef struct {
     int precision;          /* ssmap_precision                                           */
     int check_every;        /* 0: no monitoring; k > 0: objective, residuals and DFCS
                                (float64 reductions) every k iterations and after the
-                               last one, into the stats history                          */
+                               last one, into the stats history. Without stop_tol (and
+                               with at most SSMAP_MAX_HIST checks) the checks are read
+                               once, after the last iteration: a non-finite iterate
+                               then returns SSMAP_ENONFINITE after the run, naming the
+                               first check that saw it; with stop_tol each check is
+                               read when it is taken and ends the solve there        */
     int flags;              /* SSMAP_KEEP_AUX | SSMAP_MONITOR_PRIMAL | SSMAP_WARM_START
                                (| SSMAP_AUTOTUNE for batches)                            */
     int kernel;             /* ssmap_kernel                                              */

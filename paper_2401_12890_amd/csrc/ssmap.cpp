@@ -371,6 +371,11 @@ struct Prepared {
     int iters = 0;
     double stop_tol = 0.0;
     int check_every = 0;
+    // checks read after the run (no stopping rule): each check's sums go to their own
+    // slot of mhist (ST_COUNT doubles each); mchecks holds the iteration of each slot
+    bool defer = false;
+    double *mhist = nullptr;
+    mutable std::vector<int> mchecks;
     // GEMM path (voxel-major, padded): z ping-pong; s = y + w; w (float32 operand);
     // a.h; bf16 splits; constants
     float *gz[2] = {nullptr, nullptr}, *gs = nullptr, *gw = nullptr, *gah = nullptr, *gb = nullptr;
@@ -380,6 +385,12 @@ struct Prepared {
     float *gU = nullptr, *gY = nullptr;   // their results: u (N x Qg), y (N x Rg)
     int nseg = 2;                 // bf16 split segments per row (3 for the library products)
 };
+
+// Monitor checks of a solve: after every check_every-th iteration and the last.
+int monitor_checks(const Prepared &P) {
+    if (P.check_every <= 0 || P.iters <= 0) return 0;
+    return P.iters / P.check_every + (P.iters % P.check_every != 0);
+}
 
 IterArgs args_for(const Prepared &P, int k) {
     IterArgs a = P.a;
@@ -454,6 +465,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         need.push_back({"mperp2", (size_t)N * 8});
         need.push_back({"partial", (size_t)kMonitorBlocks * ST_COUNT * 8});
         need.push_back({"stat", (size_t)ST_COUNT * 8});
+        need.push_back({"mhist", (size_t)SSMAP_MAX_HIST * ST_COUNT * 8});
     }
     if (P.aux || P.primal) {
         need.push_back({"auxA", zbytes});
@@ -515,6 +527,8 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
         P.partial = (double *)ensure(c, "partial", (size_t)kMonitorBlocks * ST_COUNT * 8);
         P.stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
+        P.defer = P.stop_tol <= 0 && monitor_checks(P) <= SSMAP_MAX_HIST;
+        if (P.defer) P.mhist = (double *)ensure(c, "mhist", (size_t)SSMAP_MAX_HIST * ST_COUNT * 8);
         P.fstar = ref_dev(c);
         if (pl.fused) {
             const FusedShape sh = default_shape(pl.mode, c->g);
@@ -627,6 +641,7 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
         need.push_back({"V64", (size_t)Qg * RP * 8});
         need.push_back({"partial", (size_t)kMonitorBlocks * ST_COUNT * 8});
         need.push_back({"stat", (size_t)ST_COUNT * 8});
+        need.push_back({"mhist", (size_t)SSMAP_MAX_HIST * ST_COUNT * 8});
     }
     plan_check(c, need);
     for (int k = 0; k < 2; ++k) P.gz[k] = (float *)ensure(c, k ? "gz1" : "gz0", zb);
@@ -666,6 +681,8 @@ Prepared prepare_gemm(ssmap_ctx *c, Prepared P, hipStream_t s) {
         P.mperp2 = (double *)ensure(c, "mperp2", (size_t)N * 8);
         P.partial = (double *)ensure(c, "partial", (size_t)kMonitorBlocks * ST_COUNT * 8);
         P.stat = (double *)ensure(c, "stat", (size_t)ST_COUNT * 8);
+        P.defer = P.stop_tol <= 0 && monitor_checks(P) <= SSMAP_MAX_HIST;
+        if (P.defer) P.mhist = (double *)ensure(c, "mhist", (size_t)SSMAP_MAX_HIST * ST_COUNT * 8);
         P.fstar = ref_dev(c);
         HIPC(c, hipStreamSynchronize(s));      // v64 is a local
     }
@@ -859,10 +876,9 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
 }
 
 // Monitoring after iteration k (z^{k+1} against z^k; f^{k+1} when the primal
-// residual is asked for, left in tbuf by the bracket of iteration k). Returns
-// true when the residual stopping rule fires: k + 1 is a multiple of check_every
-// and ||z^{k+1} - z^k|| <= stop_tol ||z^{k+1}||.
-bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
+// residual is asked for, left in tbuf by the bracket of iteration k): the
+// reductions, in stream order, into `out` (ST_COUNT doubles on the device).
+void monitor_launch(ssmap_ctx *c, const Prepared &P, int k, double *out, hipStream_t s) {
     const Plan &pl = P.pl;
     MonArgs m{};
     if (pl.gemm) {
@@ -901,11 +917,15 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
     m.Q = c->Q;
     m.g = c->g;
     m.code = mask_dev(c);
-    launch_monitor(pl.mode, m, P.partial, P.stat, s);
+    launch_monitor(pl.mode, m, P.partial, out, s);
     HIPC(c, hipGetLastError());
-    HIPC(c, hipMemcpyAsync(c->host_stats, P.stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
-    HIPC(c, hipStreamSynchronize(s));
-    const double *h = c->host_stats;
+}
+
+// One check's sums `h` (host) after iteration k into the history; ENONFINITE for a
+// non-finite iterate. Returns true when the residual stopping rule fires: k + 1 is
+// a multiple of check_every and ||z^{k+1} - z^k|| <= stop_tol ||z^{k+1}||.
+bool monitor_record(ssmap_ctx *c, const Prepared &P, int k, const double *h) {
+    const Plan &pl = P.pl;
     ssmap_stats &S = c->stats;
     if (S.n_hist < SSMAP_MAX_HIST) {
         const int i = S.n_hist++;
@@ -922,6 +942,33 @@ bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
         fail(SSMAP_ENONFINITE, "non-finite iterate at iteration " + std::to_string(k + 1));
     return P.stop_tol > 0 && (k + 1) % P.check_every == 0 &&
            std::sqrt(h[ST_DZ]) <= P.stop_tol * std::sqrt(h[ST_ZNORM]);
+}
+
+// The check after iteration k. Without a stopping rule it is only enqueued (its
+// sums to the next slot of mhist, read by monitor_flush after the run); else the
+// host waits for it. Returns true when the stopping rule fires.
+bool monitor_step(ssmap_ctx *c, const Prepared &P, int k, hipStream_t s) {
+    if (P.defer && P.mchecks.size() < (size_t)SSMAP_MAX_HIST) {
+        monitor_launch(c, P, k, P.mhist + P.mchecks.size() * ST_COUNT, s);
+        P.mchecks.push_back(k);
+        return false;
+    }
+    monitor_launch(c, P, k, P.stat, s);
+    HIPC(c, hipMemcpyAsync(c->host_stats, P.stat, ST_COUNT * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    return monitor_record(c, P, k, c->host_stats);
+}
+
+// The deferred checks of a solve, in order, into the history (ENONFINITE names the
+// first check that saw a non-finite iterate).
+void monitor_flush(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
+    if (P.mchecks.empty()) return;
+    std::vector<double> h(P.mchecks.size() * ST_COUNT);
+    HIPC(c, hipMemcpyAsync(h.data(), P.mhist, h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    const std::vector<int> ks = std::move(P.mchecks);
+    P.mchecks.clear();
+    for (size_t i = 0; i < ks.size(); ++i) (void)monitor_record(c, P, ks[i], h.data() + i * ST_COUNT);
 }
 
 // One iteration of one job outside a shared launch (unfused kernels, or the
@@ -1032,6 +1079,7 @@ void solve_impl(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps *
     }
     HIPC(c, hipGetLastError());
     HIPC(c, hipEventRecord(c->ev[3], s));
+    monitor_flush(c, P, s);
     finish(c, P, dF, s);
     ssmap_stats &S = c->stats;
     S.project_ms = elapsed_ms(c->ev[0], c->ev[1]);
@@ -1298,6 +1346,13 @@ void batch_solve_impl(ssmap_batch *b, const void *const *dM, const double *lambd
     }
     HIPC(&b->arena, hipGetLastError());
     HIPC(&b->arena, hipEventRecord(b->ev[3], s));
+    for (int j = 0; j < (int)Ps.size(); ++j) {
+        try {
+            monitor_flush(b->jobs[j], Ps[j], s);
+        } catch (const Fail &f) {
+            throw Fail{f.status, "job " + std::to_string(j) + ": " + f.msg};
+        }
+    }
     for (int j = 0; j < nj; ++j) finish(b->jobs[j], Ps[j], dF[j], s);
     HIPC(&b->arena, hipEventRecord(b->ev[4], s));
     HIPC(&b->arena, hipStreamSynchronize(s));
