@@ -193,13 +193,17 @@ EDGES = [
     ("one iteration", dict(P=9, Q=17, grid=(6, 5, 2), iters=1)),
     ("two iterations", dict(P=9, Q=17, grid=(6, 5, 2), iters=2)),
     ("rank 33 of 40", dict(P=40, Q=48, grid=(5, 4, 2), iters=20, rank=33)),
+    ("P = 1", dict(P=1, Q=9, grid=(6, 4, 1), iters=25)),
+    ("rank 1", dict(P=8, Q=12, grid=(5, 4, 2), iters=25, rank=1)),
 ]
 
 
-@pytest.mark.parametrize("kernel", ["unfused", "fused"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kernel", ["unfused", "fused", "gemm"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("label,case", EDGES, ids=[e[0] for e in EDGES])
 def test_edge_cases(torch_cuda, kernel, prec, label, case):
+    if kernel == "gemm" and prec == "fp64":
+        pytest.skip("the GEMM path runs float32 and bf16x3")
     prob = synth.random_problem(case["P"], case["Q"], case["grid"], seed=zlib.crc32(label.encode()) % 1000,
                                 lam=0.3, beta=0.5, positive_K=True)
     rank = case.get("rank", -1)
@@ -208,7 +212,7 @@ def test_edge_cases(torch_cuda, kernel, prec, label, case):
     with _ffi.Mapper(prob.K, prob.grid) as mp:
         z = run(mp, prob, prec, kernel, case["iters"], ref, keep_aux=True)
         f, d = mp.aux()
-    tol = TOL[prec] if prec == "fp64" else 1e-5
+    tol = TOL[prec]
     if case["iters"] == 0:
         assert not z.any() and not f.any() and not d.any()
         return
