@@ -81,6 +81,7 @@ struct FusedLaunch {
 bool fused_supported(int mode, int RP, int64_t N);
 bool launch_fused(const FusedLaunch &L, hipStream_t s);   // false: no such shape
 FusedShape default_shape(int mode, const Grid &g);
+int device_cus();   // compute units of the current device (0 when unknown)
 std::vector<FusedShape> candidate_shapes(int mode, bool planar);
 // Bricks of a grid in launch order for precision `mode`; with `code` only bricks
 // holding an inside voxel.
@@ -148,6 +149,8 @@ struct MonArgs {
                               // rank-major, or voxel-major rows of yld), or NULL: the
                               // monitor contracts V64 with z
     int64_t yld;              // > 0: y voxel-major, element (r, n) at n yld + r
+    const void *ypart;        // or y as npart per-chunk partial products (state type, each
+    int npart;                // RP x N rank-major, RP N apart), summed in chunk order
     const double *dzpart;     // per-brick sums of (z - zprev)^2 from the iteration, or NULL
     int ndz;
     const double *sig, *t, *mperp2;   // singular values (RP), U_r^T m (r x N), ||m_perp||^2 (N)

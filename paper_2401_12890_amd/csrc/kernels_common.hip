@@ -342,11 +342,25 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
         const bool ex = ein && x + 1 < nx && in(n + 1);
         const bool ey = ein && yy + 1 < ny && in(n + nx);
         const bool ez = ein && zz + 1 < nz && in(n + nx * ny);
-        const bool contract = a.y == nullptr;
+        const bool contract = a.y == nullptr && a.ypart == nullptr;
         if (!contract && valid)             // data term from the iteration's y
             for (int rr = i4; rr < a.r; rr += 4) {
-                const double yv = (double)((const T *)a.y)[a.yld > 0 ? (size_t)n * a.yld + rr
-                                                                     : (size_t)rr * N + n];
+                double yv;
+                if (a.ypart) {              // the partials in chunk order, as the next iteration sums them
+                    T ys = (T)0;            // (bricks outside a mask are never written; z = y = 0 there)
+                    const T *yp = (const T *)a.ypart + (size_t)rr * N + n;
+                    for (int c0 = 0; ein && c0 < a.npart; c0 += 8) {
+                        T pv[8];            // eight loads in flight, then added in order
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            pv[u] = c0 + u < a.npart ? yp[(size_t)(c0 + u) * a.RP * N] : (T)0;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) ys += pv[u];
+                    }
+                    yv = (double)ys;
+                } else {
+                    yv = (double)((const T *)a.y)[a.yld > 0 ? (size_t)n * a.yld + rr : (size_t)rr * N + n];
+                }
                 const double e = a.t[(size_t)rr * N + n] - a.sig[rr] * yv;
                 acc[ST_DATA] += e * e;
             }

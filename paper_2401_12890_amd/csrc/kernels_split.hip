@@ -69,7 +69,6 @@ template <> struct ST<MODE_FP64> {
 };
 
 constexpr unsigned OOB = 0x80000000u;       // beyond every range: loads 0, stores dropped
-constexpr int NT = 512;                     // threads per workgroup (8 waves)
 constexpr int TX = 16;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, unsigned bytes) {
@@ -115,7 +114,9 @@ template <int TY, int TZ> struct Slots {
 // KSU: u K-steps (ceil(r / 4)); RB: 16-rank blocks of the padded rank; TAIL:
 // float32 ranks 17..20 with y of ranks 16..19 on the vector ALU (the operand
 // blocks then carry one 16-rank y block and a tail table, as for the fused kernel).
-template <int MODE, int RB, int KSU, int TY, int TZ>
+// NT: threads (64 per 16-voxel row of the brick at most; 512 for the taller
+// bricks, 256 and 128 for the 16 x 4 x 1 and 16 x 2 x 1 ones).
+template <int MODE, int RB, int KSU, int TY, int TZ, int NT>
 __global__ void __launch_bounds__(NT, 1)
 k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     using F = ST<MODE>;
@@ -132,9 +133,10 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     constexpr int VB = (MODE == MODE_FP64 ? 4096 : 2048) * RB;   // bytes of a chunk's V block
     constexpr int PG = 8;                // chunk partials loaded per group
     static_assert(NB % NW == 0, "brick rows must split over the waves");
-    static_assert(VB % 16 == 0 && VB / 16 <= NT, "V block must stage in one pass");
+    constexpr int VL = (VB / 16 + NT - 1) / NT;   // 16-byte pieces of the V block per thread
+    static_assert(VB % 16 == 0, "V block of whole 16-byte pieces");
     __shared__ V4 lds[4 * B::NSP + 1];
-    __shared__ uint4 ldsv[NT];
+    __shared__ uint4 ldsv[VB / 16];
 
     const IterArgs &a = sa.a;
     const int nch = a.nchunk;
@@ -179,12 +181,19 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
             R[l] = F::load(zr, off);
         }
         const __amdgpu_buffer_rsrc_t vr = rsrc(a.Vu, (unsigned)(nch * VB));
-        const uint4 Rv = __builtin_bit_cast(
-            uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                       vr, tid < VB / 16 ? (unsigned)(c * VB + 16 * tid) : OOB, 0, 0));
+        uint4 Rv[VL];
+#pragma unroll
+        for (int v = 0; v < VL; ++v) {
+            const int piece = tid + NT * v;
+            Rv[v] = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                           vr, piece < VB / 16 ? (unsigned)(c * VB + 16 * piece) : OOB, 0, 0));
+        }
 #pragma unroll
         for (int l = 0; l < NL; ++l) lds[loff[l]] = R[l];
-        ldsv[tid] = Rv;
+#pragma unroll
+        for (int v = 0; v < VL; ++v)
+            if (tid + NT * v < VB / 16) ldsv[tid + NT * v] = Rv[v];
     }
 
     // ---- per-row voxels and w^k of the u operand (lane: ranks 4 s + l/16, voxel j)
@@ -343,14 +352,16 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     }
 }
 
-template <int MODE, int RB, int KSU, int TY, int TZ>
+template <int MODE, int RB, int KSU, int TY, int TZ, int NT = 512>
 void launch_s(const SplitArgs &sa, const TileRef *tiles, int ntiles, hipStream_t s) {
-    hipLaunchKernelGGL((k_split<MODE, RB, KSU, TY, TZ>), dim3(ntiles * sa.a.nchunk), dim3(NT), 0, s,
+    hipLaunchKernelGGL((k_split<MODE, RB, KSU, TY, TZ, NT>), dim3(ntiles * sa.a.nchunk), dim3(NT), 0, s,
                        sa, tiles);
 }
 
 template <int MODE, int RB, int KSU>
 bool split_shape(const SplitArgs &sa, FusedShape sh, const TileRef *tiles, int ntiles, hipStream_t s) {
+    if (sh.ty == 2 && sh.tz == 1) return launch_s<MODE, RB, KSU, 2, 1, 128>(sa, tiles, ntiles, s), true;
+    if (sh.ty == 4 && sh.tz == 1) return launch_s<MODE, RB, KSU, 4, 1, 256>(sa, tiles, ntiles, s), true;
     if (sh.ty == 8 && sh.tz == 1) return launch_s<MODE, RB, KSU, 8, 1>(sa, tiles, ntiles, s), true;
     if (sh.ty == 16 && sh.tz == 1) return launch_s<MODE, RB, KSU, 16, 1>(sa, tiles, ntiles, s), true;
     if (sh.ty == 4 && sh.tz == 2) return launch_s<MODE, RB, KSU, 4, 2>(sa, tiles, ntiles, s), true;

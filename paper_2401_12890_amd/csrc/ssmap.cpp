@@ -344,6 +344,21 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_sp
     return p;
 }
 
+// The brick shape of a plan's launches: the default shape, except for the chunk
+// split on planar grids, which takes the thinnest of 16 x {2, 4, 8} bricks whose
+// (brick, chunk) workgroups (one per CU) still fit the device at once, so that an
+// iteration's loads are spread over more CUs (a 32 x 32 grid with 7 chunks: 224
+// workgroups of 16 x 2 voxels instead of 56 of 16 x 8).
+FusedShape plan_shape(const ssmap_ctx *c, const Plan &pl) {
+    const FusedShape def = default_shape(pl.mode, c->g);
+    if (!pl.split || c->g.nz != 1) return def;
+    const int dc = device_cus();
+    const int64_t cus = dc > 0 ? dc : 256;
+    for (int ty : {2, 4, 8})
+        if (brick_count(c->g, FusedShape{ty, 1}) * c->nchunk <= cus) return FusedShape{ty, 1};
+    return def;
+}
+
 // ---------------------------------------------------------------- solve phases
 // A solve is prepare (per-solve coefficients, operand images, projection a1,
 // state initialisation), the iteration loop (a2..a7) and finish (a8). The
@@ -474,7 +489,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     if (pl.fused) {
         need.push_back({"Vop", (size_t)c->nchunk * 8 * RP * 64 * 2});
         // launch plan: two descriptors and at most this many bricks
-        const FusedShape sh = default_shape(pl.mode, c->g);
+        const FusedShape sh = plan_shape(c, pl);
         const size_t nb = (size_t)((c->g.nx + 15) / 16) * ((c->g.ny + sh.ty - 1) / sh.ty) *
                           ((c->g.nz + sh.tz - 1) / sh.tz);
         need.push_back({"jobs", 2 * sizeof(IterArgs)});
@@ -531,7 +546,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
         if (P.defer) P.mhist = (double *)ensure(c, "mhist", (size_t)SSMAP_MAX_HIST * ST_COUNT * 8);
         P.fstar = ref_dev(c);
         if (pl.fused) {
-            const FusedShape sh = default_shape(pl.mode, c->g);
+            const FusedShape sh = plan_shape(c, pl);
             const size_t nb = (size_t)((c->g.nx + 15) / 16) * ((c->g.ny + sh.ty - 1) / sh.ty) *
                               ((c->g.nz + sh.tz - 1) / sh.tz);
             P.monpart = (double *)ensure(c, "monpart", nb * 8);
@@ -859,7 +874,7 @@ FusedLaunch single_launch(ssmap_ctx *c, const Prepared &P, hipStream_t s) {
     L.mode = P.pl.mode;
     L.r = P.pl.r;
     L.RP = P.pl.RP;
-    L.shape = default_shape(P.pl.mode, c->g);
+    L.shape = plan_shape(c, P.pl);
     std::vector<TileRef> tiles;
     append_tiles(c->g, 0, L.mode, L.shape, tiles, c->code.empty() ? nullptr : &c->code);
     IterArgs two[2] = {args_for(P, 0), args_for(P, 1)};
@@ -896,6 +911,8 @@ void monitor_launch(ssmap_ctx *c, const Prepared &P, int k, double *out, hipStre
         m.z = P.z[(k + 1) & 1];
         if (pl.split) {              // y^{k+1} exists only as per-chunk partials
             m.zprev = P.z[k & 1];
+            m.ypart = P.sp[(k + 1) & 1];
+            m.npart = c->nchunk;
         } else if (pl.fused) {
             m.y = P.a.y;
             m.dzpart = P.monpart;
