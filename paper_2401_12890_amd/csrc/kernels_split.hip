@@ -160,11 +160,23 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     const unsigned chunk_bytes = (unsigned)(chunk_elems * sizeof(T));
     const T tau = (T)a.tau, lam2 = (T)a.lam2, beta = (T)a.beta;
 
-    // ---- stage z^k of chunk c (brick and face halo) and the chunk's V operand block
+    // ---- stage z^k of chunk c (brick and face halo) and the chunk's V operand block.
+    // Thin bricks (at most 256 threads, registers to spare) keep the staged values in
+    // registers until the row loads below have been issued too, so that both go out
+    // in one memory round trip, and write them to LDS before the barrier.
+    constexpr bool HOLD = NT <= 256;
+    V4 R[NL];
+    int loff[NL];
+    uint4 Rv[VL];
+    auto stage_to_lds = [&]() {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) lds[loff[l]] = R[l];
+#pragma unroll
+        for (int v = 0; v < VL; ++v)
+            if (tid + NT * v < VB / 16) ldsv[tid + NT * v] = Rv[v];
+    };
     {
         const __amdgpu_buffer_rsrc_t zr = rsrc((const T *)a.z + (size_t)c * chunk_elems, chunk_bytes);
-        V4 R[NL];
-        int loff[NL];
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             const int f = tid + NT * l;
@@ -181,7 +193,6 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
             R[l] = F::load(zr, off);
         }
         const __amdgpu_buffer_rsrc_t vr = rsrc(a.Vu, (unsigned)(nch * VB));
-        uint4 Rv[VL];
 #pragma unroll
         for (int v = 0; v < VL; ++v) {
             const int piece = tid + NT * v;
@@ -189,11 +200,7 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
                 uint4, __builtin_amdgcn_raw_buffer_load_b128(
                            vr, piece < VB / 16 ? (unsigned)(c * VB + 16 * piece) : OOB, 0, 0));
         }
-#pragma unroll
-        for (int l = 0; l < NL; ++l) lds[loff[l]] = R[l];
-#pragma unroll
-        for (int v = 0; v < VL; ++v)
-            if (tid + NT * v < VB / 16) ldsv[tid + NT * v] = Rv[v];
+        if constexpr (!HOLD) stage_to_lds();
     }
 
     // ---- per-row voxels and w^k of the u operand (lane: ranks 4 s + l/16, voxel j)
@@ -276,6 +283,7 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
             }
         }
     }
+    if constexpr (HOLD) stage_to_lds();
     __syncthreads();
 
     // ---- V operands of the chunk, the update of its 16 nodes, partial y^{k+1}
