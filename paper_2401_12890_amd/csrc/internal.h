@@ -81,7 +81,6 @@ struct FusedLaunch {
 bool fused_supported(int mode, int RP, int64_t N);
 bool launch_fused(const FusedLaunch &L, hipStream_t s);   // false: no such shape
 FusedShape default_shape(int mode, const Grid &g);
-int device_cus();   // compute units of the current device (0 when unknown)
 std::vector<FusedShape> candidate_shapes(int mode, bool planar);
 // Bricks of a grid in launch order for precision `mode`; with `code` only bricks
 // holding an inside voxel.

@@ -1017,8 +1017,6 @@ k_fused_dma(const IterArgs *__restrict__ jobs, const TileRef *__restrict__ tiles
 // Longest brick (in 16-node chunks) that the double-buffered shapes run persistent.
 constexpr int kPersistChunks = 32;
 
-}  // namespace
-
 // Compute units of the current device (the persistent grid's width), read once per device.
 int device_cus() {
     static std::atomic<int> cus[64];
@@ -1031,8 +1029,6 @@ int device_cus() {
     }
     return n;
 }
-
-namespace {
 
 template <int MODE, int RB, int KSU, int TY, int TZ, bool MON>
 void launch_t(const FusedLaunch &L, hipStream_t s) {

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -349,10 +350,22 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_sp
 // (brick, chunk) workgroups (one per CU) still fit the device at once, so that an
 // iteration's loads are spread over more CUs (a 32 x 32 grid with 7 chunks: 224
 // workgroups of 16 x 2 voxels instead of 56 of 16 x 8).
+int current_device_cus() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 FusedShape plan_shape(const ssmap_ctx *c, const Plan &pl) {
     const FusedShape def = default_shape(pl.mode, c->g);
     if (!pl.split || c->g.nz != 1) return def;
-    const int dc = device_cus();
+    const int dc = current_device_cus();
     const int64_t cus = dc > 0 ? dc : 256;
     for (int ty : {2, 4, 8})
         if (brick_count(c->g, FusedShape{ty, 1}) * c->nchunk <= cus) return FusedShape{ty, 1};
