@@ -345,11 +345,7 @@ Plan make_plan(ssmap_ctx *c, double lambda, const ssmap_steps *st, bool allow_sp
     return p;
 }
 
-// The brick shape of a plan's launches: the default shape, except for the chunk
-// split on planar grids, which takes the thinnest of 16 x {2, 4, 8} bricks whose
-// (brick, chunk) workgroups (one per CU) still fit the device at once, so that an
-// iteration's loads are spread over more CUs (a 32 x 32 grid with 7 chunks: 224
-// workgroups of 16 x 2 voxels instead of 56 of 16 x 8).
+// Compute units of the current device (0 when unknown), read once per device.
 int current_device_cus() {
     static std::atomic<int> cus[64];
     int dev = 0;
@@ -362,6 +358,11 @@ int current_device_cus() {
     return n;
 }
 
+// The brick shape of a plan's launches: the default shape, except for the chunk
+// split on planar grids, which takes the thinnest of 16 x {2, 4, 8} bricks whose
+// (brick, chunk) workgroups (one per CU) still fit the device at once, so that an
+// iteration's loads are spread over more CUs (a 32 x 32 grid with 7 chunks: 224
+// workgroups of 16 x 2 voxels instead of 56 of 16 x 8).
 FusedShape plan_shape(const ssmap_ctx *c, const Plan &pl) {
     const FusedShape def = default_shape(pl.mode, c->g);
     if (!pl.split || c->g.nz != 1) return def;
