@@ -80,6 +80,8 @@ __device__ __forceinline__ void split2x4(const v4f &v, uint16_t *dst, int k, int
 
 // Epilogue of u = V_r w: z^{k+1} = max(0, z - tau (2 lambda (deg z - sum of
 // neighbours) - beta u)) for the voxel's 4 nodes q..q+3; outside a mask z stays 0.
+constexpr int EPI_RUN = 4;   // voxels along x per k_epi_z block
+
 struct EpiZ {
     const float *z;
     float *zn;
@@ -130,6 +132,25 @@ __device__ __forceinline__ ColZ column(const EpiZ &e, int64_t n) {
     return c;
 }
 
+// The projected z-update of one voxel's nodes q .. q + 3 from z there, its six
+// face-neighbour rows (weighted as the column says) and u; stores z^{k+1} and
+// its bf16 split.
+__device__ __forceinline__ void zupdate(const EpiZ &e, const ColZ &c, int q, const v4f &zc, const v4f (&nb)[6],
+                                        const v4f &u) {
+    v4f nsum = v4f{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nsum += c.wt[k] * nb[k];
+    v4f r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float lap = c.deg * zc[i] - nsum[i];
+        const float v = zc[i] - e.tau * (e.lam2 * lap - e.beta * u[i]);
+        r[i] = (v > 0.0f && c.inside) ? v : 0.0f;
+    }
+    *(v4f *)(e.zn + c.n * (int64_t)e.Qg + q) = r;
+    if (e.zs) split2x4(r, e.zs + c.n * e.nseg * (int64_t)e.Qg, q, e.Qg, e.nseg);
+}
+
 // G steps of one voxel (nodes q[g] .. q[g] + 3): every load is issued before any
 // result is computed, so a lane has 7 G loads in flight instead of 7 (the
 // epilogue is bound by their latency).
@@ -144,20 +165,7 @@ __device__ __forceinline__ void epilogue_batch(const EpiZ &e, const ColZ &c, con
         for (int k = 0; k < 6; ++k) nb[g][k] = *(const v4f *)(c.nb[k] + q[g]);
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        v4f nsum = v4f{0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < 6; ++k) nsum += c.wt[k] * nb[g][k];
-        v4f r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float lap = c.deg * zc[g][i] - nsum[i];
-            const float v = zc[g][i] - e.tau * (e.lam2 * lap - e.beta * u[g][i]);
-            r[i] = (v > 0.0f && c.inside) ? v : 0.0f;
-        }
-        *(v4f *)(e.zn + c.n * (int64_t)e.Qg + q[g]) = r;
-        if (e.zs) split2x4(r, e.zs + c.n * e.nseg * (int64_t)e.Qg, q[g], e.Qg, e.nseg);
-    }
+    for (int g = 0; g < G; ++g) zupdate(e, c, q[g], zc[g], nb[g], u[g]);
 }
 
 // Epilogue of y = V_r^T z: w^{k+1} = a.h - b.(2 y^{k+1} - s^k), s^{k+1} =
@@ -380,13 +388,42 @@ k_gemm_from_ranks(const float *__restrict__ src, int RP, float *__restrict__ dst
 // P[n][m], m over M = Qg or Rg): one lane per voxel and 4 consecutive rows m.
 __global__ void __launch_bounds__(256)
 k_epi_z(EpiZ e, const float *__restrict__ U) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // a block: one tile of 256 node quads for EPI_RUN consecutive voxels n0 ..
+    // (the x-neighbours of voxel n are the rows of n - 1 and n + 1, so the run
+    // reads EPI_RUN + 2 rows along x instead of 3 EPI_RUN; the y and z
+    // neighbours and u per voxel). Every load is issued before any result.
     const int per = e.Qg / 4;
-    if (idx >= e.g.N * per) return;
-    const int64_t n = idx / per;
-    const int q[1] = {4 * (int)(idx % per)};
-    const v4f u[1] = {*(const v4f *)(U + n * (int64_t)e.Qg + q[0])};
-    epilogue_batch<1>(e, column(e, n), q, u);
+    const int64_t qt = (per + 255) / 256;
+    const int64_t n0 = (int64_t)(blockIdx.x / qt) * EPI_RUN;
+    const int qi = (int)(blockIdx.x % qt) * 256 + (int)threadIdx.x;
+    const int64_t N = e.g.N;
+    if (qi >= per || n0 >= N) return;
+    const int q = 4 * qi;
+    const int64_t Q = e.Qg;
+    v4f xr[EPI_RUN + 2];                 // rows n0 - 1 .. n0 + EPI_RUN (clamped to the grid)
+#pragma unroll
+    for (int j = 0; j < EPI_RUN + 2; ++j) {
+        const int64_t n = n0 - 1 + j;
+        xr[j] = *(const v4f *)(e.z + (n < 0 ? 0 : n >= N ? N - 1 : n) * Q + q);
+    }
+    ColZ col[EPI_RUN];
+    v4f yz[EPI_RUN][4], u[EPI_RUN];
+#pragma unroll
+    for (int j = 0; j < EPI_RUN; ++j) {
+        const int64_t n = n0 + j < N ? n0 + j : N - 1;
+        col[j] = column(e, n);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) yz[j][k] = *(const v4f *)(col[j].nb[2 + k] + q);
+        u[j] = *(const v4f *)(U + n * Q + q);
+    }
+#pragma unroll
+    for (int j = 0; j < EPI_RUN; ++j) {
+        if (n0 + j >= N) break;
+        // a missing x-neighbour is the voxel's own row at weight 0, as in column()
+        const v4f nb[6] = {col[j].wt[0] != 0.0f ? xr[j] : xr[j + 1], col[j].wt[1] != 0.0f ? xr[j + 2] : xr[j + 1],
+                           yz[j][0], yz[j][1], yz[j][2], yz[j][3]};
+        zupdate(e, col[j], q, xr[j + 1], nb, u[j]);
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -473,7 +510,8 @@ bool launch_gemm_y(bool bf16, const void *A, const void *B, int K, int64_t N, in
 void launch_epi_z(const float *U, const float *z, float *zn, uint16_t *zs3, Grid g, int Qg, double tau,
                   double lam2, double beta, const uint8_t *code, hipStream_t s) {
     const EpiZ e{z, zn, zs3, g, Qg, (float)tau, (float)lam2, (float)beta, code, 3};
-    hipLaunchKernelGGL(k_epi_z, dim3(nblocks(g.N * (Qg / 4), 256)), dim3(256), 0, s, e, U);
+    const int64_t qt = (Qg / 4 + 255) / 256;
+    hipLaunchKernelGGL(k_epi_z, dim3((unsigned)(nblocks(g.N, EPI_RUN) * qt)), dim3(256), 0, s, e, U);
 }
 
 void launch_epi_w(const float *Y, int64_t N, int Rg, const float *ah, float *sv, float *w, uint16_t *ws3,
