@@ -229,6 +229,37 @@ def cpu_baseline_batch(sub):
                       f"iterations after one"}
 
 
+def batch200_parity(Fs, probs, prec):
+    """The timed batch's own maps of the stored slices (tests/golden/batch200_c4.npz,
+    written by tests/golden/make_batch200_golden.py from the generator and the
+    oracle only: per Q the smallest and the largest slice at the configured 200
+    iterations) against the stored FP64 values: the full Q-vectors at the sampled
+    voxels and every voxel's spectral sum; the worst slice is reported."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "batch200_c4.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    if int(g["iters"]) != probs[0].iters or int(g["nslices"]) != len(probs):
+        return None
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    import torch
+    e_s, e_sum = 0.0, 0.0
+    for k in (int(v) for v in g["slices"]):
+        F = Fs[k]
+        idx = torch.as_tensor(g[f"s{k}_index"], device=F.device)
+        e_s = max(e_s, rel(F[idx].double().cpu().numpy(), g[f"s{k}_z"]))
+        e_sum = max(e_sum, rel(F.double().sum(dim=1).cpu().numpy(), g[f"s{k}_z_sum_q"]))
+    return {"kind": "the timed batch's maps of stored slices vs stored FP64 oracle values (z^200 at "
+                    "sampled voxels, every voxel's spectral sum; worst slice)",
+            "slices": [int(v) for v in g["slices"]], "iters": int(g["iters"]),
+            "rel_err_sampled": e_s, "rel_err_spectral_sums": e_sum,
+            "tol": {"fp32": 1e-5, "bf16x3": 1e-3}[prec]}
+
+
 def bench_batch(args):
     """Batched uneven slices: one batch solve (all slices, shared launches,
     autotuned bricks) per step, in bf16x3 and in float32, against the same
@@ -258,8 +289,10 @@ def bench_batch(args):
             lat.append((time.perf_counter() - ts) * 1e3)
             loop.append(bm.stats()["iterate_ms"])
             log(f"{prec} batch step {k}: {lat[-1]:.1f} ms (loop {loop[-1]:.1f} ms)")
+        torch.cuda.synchronize()
+        par = None if args.no_parity else batch200_parity(Fs, probs, prec)
         out[prec] = dict(ms=sum(lat) / len(lat), loop_ms=sum(loop) / len(loop), lat=lat,
-                         classes=tuned, ranks=None)
+                         classes=tuned, ranks=None, parity=par)
     # the same slices one after another (float32, default bricks)
     seq_ms = 0.0
     ranks = []
@@ -296,7 +329,8 @@ def bench_batch(args):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "shared fused launches (bf16x3)", "avg_launch_ms": per_launch_ms,
                      "alg_bytes_per_launch": alg},
-        "cpu_baseline": cpu, "parity": None,
+        "cpu_baseline": cpu,
+        "parity": None if args.no_parity else {"bf16x3": out["bf16x3"]["parity"], "fp32": out["fp32"]["parity"]},
     }
     print(json.dumps(line), flush=True)
 
