@@ -1,5 +1,6 @@
 """Write tests/golden/fullsize_<workload>.json: oracle values at sampled voxels
-of the full-size workloads after 4 iterations.
+of the full-size workloads after 4 iterations (c2 and c3 at the rank of the
+rank rule, c3x: the c3 recipe at the unapproximated rank min(P, Q) = 1000).
 
 Calls only the seeded generator (inputs) and oracle/ (values). For each
 sampled voxel the FP64 oracle is run on a crop of half-width 5 around it
@@ -8,7 +9,7 @@ full-grid value there). Stored per voxel: its coordinates, ||z^4|| and the
 projection <z^4, g> on a fixed seeded Gaussian vector g (PCG64 seed 2401),
 which lets the benchmark check its own full-size output without the oracle.
 
-    python tests/golden/make_fullsize_golden.py
+    python tests/golden/make_fullsize_golden.py [workload ...]
 """
 import json
 import os
@@ -25,6 +26,8 @@ from paper_2401_12890_amd import synth  # noqa: E402
 
 ITERS = 4
 PROJ_SEED = 2401
+# workload -> (recipe, rank parameter of the rank rule: 0 the 0.005 % rule, -1 min(P, Q))
+WORKLOADS = {"c2": ("c2", 0), "c3": ("c3", 0), "c3x": ("c3", -1)}
 
 
 def points(grid, n=12, seed=7):
@@ -36,11 +39,12 @@ def points(grid, n=12, seed=7):
     return pts
 
 
-def main():
-    for name in ("c2", "c3"):
-        prob = synth.generate(name)
+def main(argv):
+    for name in (argv or list(WORKLOADS)):
+        recipe, rank_param = WORKLOADS[name]
+        prob = synth.generate(recipe)
         U, s, V = oracle.thin_svd(prob.K)
-        rank = oracle.rank_rule(s, 0)
+        rank = oracle.rank_rule(s, rank_param)
         xi = oracle.xi_rule(prob.lam, prob.grid)
         g = np.random.Generator(np.random.PCG64(PROJ_SEED)).standard_normal(prob.Q)
         nx, ny, nz = prob.grid
@@ -66,4 +70,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

@@ -327,21 +327,27 @@ def test_dfcs_history_monotone_objective():
     assert len(out["hist"]) == 7
 
 
-def test_fullsize_golden_values_come_from_the_oracle():
+@pytest.mark.parametrize("workload,nsamples", [("c2", 2), ("c3x", 1)])
+def test_fullsize_golden_values_come_from_the_oracle(workload, nsamples):
     """The stored full-size sample values (used by the benchmark) are what the
-    oracle gives on crops: recompute two of them."""
+    oracle gives on crops: recompute some of them (c3x: the c3 recipe at the
+    unapproximated rank min(P, Q))."""
     import importlib.util
     path = os.path.join(GOLDEN, "make_fullsize_golden.py")
     spec = importlib.util.spec_from_file_location("make_fullsize_golden", path)
     mk = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mk)
-    with open(os.path.join(GOLDEN, "fullsize_c2.json")) as fh:
+    with open(os.path.join(GOLDEN, f"fullsize_{workload}.json")) as fh:
         gold = json.load(fh)
-    prob = synth.generate("c2")
+    recipe, rank_param = mk.WORKLOADS[workload]
+    prob = synth.generate(recipe)
+    assert gold["rank"] == oracle.rank_rule(oracle.thin_svd(prob.K)[1], rank_param)
+    if rank_param == -1:
+        assert gold["rank"] == min(prob.P, prob.Q)
     g = np.random.Generator(np.random.PCG64(gold["projection_seed"])).standard_normal(prob.Q)
     nx, ny, nz = prob.grid
     h = gold["iters"] + 1
-    for smp in gold["samples"][:2]:
+    for smp in gold["samples"][:nsamples]:
         x, y, z = smp["voxel"]
         x0, x1 = max(0, x - h), min(nx, x + h + 1)
         y0, y1 = max(0, y - h), min(ny, y + h + 1)
