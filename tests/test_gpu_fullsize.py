@@ -1,7 +1,8 @@
 """Full-size checks in the launch configuration the benchmark times.
 
-* Sampled parity: the full 128x128x64 (and 96x96x32) problem is solved on the
-  GPU for k iterations; z^k at a voxel depends only on data within k - 1
+* Sampled parity: the full 128x128x64 (and 96x96x32, also at the
+  unapproximated rank 1000 on the GEMM path) problem is solved on the GPU for k
+  iterations; z^k at a voxel depends only on data within k - 1
   voxels of it (each iteration widens the stencil's reach by one), so the
   FP64 oracle run on a crop of half-width k + 1 around a sampled voxel gives
   the same value there. Corners, faces and random interior voxels are
@@ -58,23 +59,27 @@ def crop_ref(prob, pt, k, rank, xi):
     return sub["z"][c]
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-def test_full_size_sampled_parity(torch_cuda, name):
+# (workload, recipe, rank parameter of the rank rule, kernel the benchmark times)
+FULL = [("c2", "c2", 0, 2), ("c3", "c3", 0, 2), ("c3x", "c3", -1, 3)]
+
+
+@pytest.mark.parametrize("name,recipe,rank_param,kernel", FULL, ids=[f[0] for f in FULL])
+def test_full_size_sampled_parity(torch_cuda, name, recipe, rank_param, kernel):
     torch = torch_cuda
-    prob = synth.generate(name)
+    prob = synth.generate(recipe)
     prec = prob.precision
     k = 4
     # the oracle's own rules on the full grid (not the library's values)
     U, s, V = oracle.thin_svd(prob.K)
-    rank = oracle.rank_rule(s, 0)
+    rank = oracle.rank_rule(s, rank_param)
     xi = oracle.xi_rule(prob.lam, prob.grid)
     say("full size", name, prob.grid, prec, "rank", rank, "xi", xi)
     with _ffi.Mapper(prob.K, prob.grid) as mp:
         M = torch.tensor(prob.m, dtype=torch.float32, device="cuda")
-        F = mp.solve_torch(M, prob.lam, prob.beta, k, precision=prec)
+        F = mp.solve_torch(M, prob.lam, prob.beta, k, precision=prec, rank=rank_param)
         torch.cuda.synchronize()
         st = mp.stats()
-        assert st["kernel"] == 2                       # the fused kernel the benchmark times
+        assert st["kernel"] == kernel                  # the kernel the benchmark times
         assert st["rank"] == rank
         assert st["xi_p"] == pytest.approx(xi, rel=1e-13)
         for pt in sample_points(prob.grid, 12, seed=5):
