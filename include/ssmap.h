@@ -418,9 +418,11 @@ ssmap_status ssmap_server_add_dictionary(ssmap_server *sv, const double *K, int 
  * voxel-major) and dF (N*Q, voxel-major; receives z^iters) are device buffers
  * in the precision's I/O type (float64 for SSMAP_FP64, else float32), borrowed
  * until the job is done. lambda, steps and iters as in ssmap_solve, with
- * steps->check_every = 0, steps->flags = 0 and kernel AUTO or FUSED; EINVAL
- * when no fused kernel covers the precision, rank and size; ENOMEM when the
- * job alone needs more than the budget. Returns the job id. */
+ * steps->flags = 0, no stop_tol and kernel AUTO or FUSED; steps->check_every
+ * > 0 monitors the job (at most 32 checks, iters / check_every rounded up;
+ * read with ssmap_server_get_job_stats; the job holds r N + N doubles more);
+ * EINVAL when no fused kernel covers the precision, rank and size; ENOMEM
+ * when the job alone needs more than the budget. Returns the job id. */
 ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t grid[3],
                                  const void *dM, double lambda, const ssmap_steps *steps,
                                  int iters, void *dF, int64_t *job_id);
@@ -432,6 +434,15 @@ ssmap_status ssmap_server_pump(ssmap_server *sv, double horizon_ms, int *n_pendi
 
 /* State, status and timings of one job. */
 ssmap_status ssmap_server_poll(ssmap_server *sv, int64_t job_id, ssmap_job_info *out);
+
+/* Monitoring record of a finished job submitted with steps->check_every > 0
+ * (objective of Eq. spat, dual residual and ||z|| after every check_every-th
+ * iteration and the last, float64 reductions, as ssmap_get_stats gives for a
+ * single solve; hist_primal and the DFCS entries are -1). rank, xi_p, tau and
+ * iters describe the job; n_hist is 0 for an unmonitored job. EINVAL while the
+ * job is not done. A check that saw a non-finite iterate makes the job's status
+ * SSMAP_ENONFINITE. */
+ssmap_status ssmap_server_get_job_stats(ssmap_server *sv, int64_t job_id, ssmap_stats *out);
 
 /* Pump until every submitted job is done and the device work has finished. */
 ssmap_status ssmap_server_drain(ssmap_server *sv);

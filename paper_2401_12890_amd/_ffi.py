@@ -38,7 +38,7 @@ EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_dev
            "ssmap_batch_get_stats", "ssmap_batch_get_job_stats", "ssmap_batch_last_error",
            "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
-           "ssmap_server_pump", "ssmap_server_poll", "ssmap_server_drain",
+           "ssmap_server_pump", "ssmap_server_poll", "ssmap_server_get_job_stats", "ssmap_server_drain",
            "ssmap_server_get_stats", "ssmap_server_last_error", "ssmap_server_destroy"]
 SSMAP_AUTOTUNE = 2
 MAX_CLASSES = 16
@@ -187,6 +187,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_server_pump.restype = ip
     lib.ssmap_server_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(JobInfo)]
     lib.ssmap_server_poll.restype = ip
+    lib.ssmap_server_get_job_stats.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Stats)]
+    lib.ssmap_server_get_job_stats.restype = ip
     lib.ssmap_server_drain.argtypes = [vp]
     lib.ssmap_server_drain.restype = ip
     lib.ssmap_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -607,6 +609,13 @@ def ssmap_server_poll(sv, job_id) -> dict:
                 done_ms=i.done_ms)
 
 
+def ssmap_server_get_job_stats(sv, job_id) -> dict:
+    """Monitoring record of a finished served job (history empty when unmonitored)."""
+    s = Stats()
+    _scheck(sv, load().ssmap_server_get_job_stats(sv, int(job_id), ctypes.byref(s)))
+    return _stats_dict(s)
+
+
 def ssmap_server_drain(sv) -> None:
     _scheck(sv, load().ssmap_server_drain(sv))
 
@@ -667,6 +676,9 @@ class Server:
     def poll(self, job_id) -> dict:
         info = ssmap_server_poll(self.sv, job_id)
         return info
+
+    def job_stats(self, job_id) -> dict:
+        return ssmap_server_get_job_stats(self.sv, job_id)
 
     def result(self, job_id):
         """F of a finished job (None while it runs); releases the job's tensors."""

@@ -44,6 +44,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kStagingBytes = (size_t)64 << 20;
 constexpr int kFlagSlots = 4096;
+constexpr int kServedChecks = 32;       // monitor checks a served job may ask for
 constexpr double kBytesPerMs = 4.0e9;     // round-time model: ~4 TB/s sustained
 constexpr double kLaunchMs = 0.006;
 
@@ -100,6 +101,15 @@ struct Job {
     hipEvent_t done_ev = nullptr;
     int state = QUEUED, status = SSMAP_OK;
     double submit_ms = 0, admit_ms = 0, done_ms = 0;
+    // monitoring (check_every > 0): U_r^T m, ||m_perp||^2 and the sums of each check
+    // (ST_COUNT doubles) in the job's memory; the singular values; the job's bricks
+    // in its class's brick table; the checks taken (iterations) and, once done, their sums
+    int check_every = 0, nchecks = 0;
+    double *t = nullptr, *mperp2 = nullptr, *hist = nullptr;
+    const double *sig = nullptr;
+    int tile_off = 0, tile_cnt = 0;
+    std::vector<int> hist_iter;
+    std::vector<double> hist_sums;
 };
 
 struct Class {
@@ -112,7 +122,8 @@ struct Class {
     bool dirty = false;
     IterArgs *djobs = nullptr;
     TileRef *dtiles = nullptr;
-    size_t cap_jobs = 0, cap_tiles = 0;
+    double *dmon = nullptr;                // per-brick (z^{k+1} - z^k)^2 of a monitored round
+    size_t cap_jobs = 0, cap_tiles = 0, cap_mon = 0;
     int ntiles = 0;
     int maxchunk = 0;                // largest chunk count among the members
     double model_ms = 0;                  // modelled duration of one round (alone on the GPU)
@@ -147,6 +158,10 @@ struct ssmap_server {
     std::deque<Region> stage_live;
     // pinned non-finite flags, one slot per unfinished job
     int *flags = nullptr;
+    // monitored jobs: pinned check sums per slot (kServedChecks x ST_COUNT doubles each)
+    // and a partial-sum buffer per lane, both allocated at the first monitored job
+    double *hist_pinned = nullptr;
+    double *lane_partial[kMaxLanes] = {};
     std::vector<int> free_slots;
     std::vector<hipEvent_t> fence_pool, timing_pool;
     std::vector<void *> dev_allocs;       // consts and tables (freed at destroy)
@@ -281,6 +296,12 @@ size_t job_bytes(int mode, int Qp, int RP, int64_t N) {
     return kAlign + 2 * align_up((size_t)Qp * N * esz) + 3 * align_up((size_t)RP * N * esz);
 }
 
+// Monitoring's share of a job's memory: U_r^T m (r x N), ||m_perp||^2 (N), the checks' sums.
+size_t monitor_bytes(int r, int64_t N, int nchecks) {
+    if (nchecks == 0) return 0;
+    return align_up((size_t)r * N * 8) + align_up((size_t)N * 8) + align_up((size_t)nchecks * ST_COUNT * 8);
+}
+
 Consts &get_consts(ssmap_server *sv, Dict &d, const Job &j, int li) {
     uint64_t bb;
     std::memcpy(&bb, &j.st.beta, 8);
@@ -366,7 +387,9 @@ void upload_tables(ssmap_server *sv, Class &C) {
         args[2 * k] = args_at(j, 0);
         args[2 * k + 1] = args_at(j, 1);
         args[2 * k].phase = args[2 * k + 1].phase = (int)(j.r0 & 1);
+        j.tile_off = (int)tiles.size();
         append_tiles(j.g, (int)k, C.mode, C.shape, tiles);
+        j.tile_cnt = (int)tiles.size() - j.tile_off;
         const size_t esz = j.mode == MODE_FP64 ? 8 : 4;
         bytes += (double)j.g.N * (2.0 * j.a.nchunk * QC + 5.0 * j.RP) * esz;
     }
@@ -377,6 +400,12 @@ void upload_tables(ssmap_server *sv, Class &C) {
     if (tiles.size() > C.cap_tiles) {
         C.cap_tiles = std::max<size_t>(2 * tiles.size(), 1024);
         C.dtiles = (TileRef *)dev_alloc(sv, C.cap_tiles * sizeof(TileRef));
+    }
+    bool monitored = false;
+    for (int64_t id : C.members) monitored |= sv->jobs[id].check_every > 0;
+    if (monitored && tiles.size() > C.cap_mon) {
+        C.cap_mon = std::max<size_t>(2 * tiles.size(), 1024);
+        C.dmon = (double *)dev_alloc(sv, C.cap_mon * sizeof(double));
     }
     upload(sv, C.lane, C.djobs, args.data(), args.size() * sizeof(IterArgs));
     upload(sv, C.lane, C.dtiles, tiles.data(), tiles.size() * sizeof(TileRef));
@@ -410,6 +439,9 @@ void retire(ssmap_server *sv, Job &j, int li) {
     launch_output(j.mode, j.z[j.iters & 1], j.dF, sv->dicts[j.dict].Q, j.g.N, false, s);
     HIPS(sv, hipGetLastError());
     HIPS(sv, hipMemcpyAsync(&sv->flags[j.slot], j.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (!j.hist_iter.empty())
+        HIPS(sv, hipMemcpyAsync(sv->hist_pinned + (size_t)j.slot * kServedChecks * ST_COUNT, j.hist,
+                                j.hist_iter.size() * ST_COUNT * 8, hipMemcpyDeviceToHost, s));
     j.done_ev = get_event(sv, true);
     HIPS(sv, hipEventRecord(j.done_ev, s));
     Fence f;
@@ -447,6 +479,18 @@ bool admit_one(ssmap_server *sv) {
     j.z[0] = p;
     j.z[1] = p + zb;
     void *w = p + 2 * zb, *y = p + 2 * zb + rb, *ah = p + 2 * zb + 2 * rb;
+    if (j.check_every > 0) {
+        uint8_t *mp = p + 2 * zb + 3 * rb;
+        j.t = (double *)mp;
+        j.mperp2 = (double *)(mp + align_up((size_t)j.r * N * 8));
+        j.hist = (double *)(mp + align_up((size_t)j.r * N * 8) + align_up((size_t)N * 8));
+        j.sig = cs.sig;
+        if (!sv->hist_pinned)
+            HIPS(sv, hipHostMalloc((void **)&sv->hist_pinned,
+                                   (size_t)kFlagSlots * kServedChecks * ST_COUNT * sizeof(double)));
+        if (!sv->lane_partial[li])
+            sv->lane_partial[li] = (double *)dev_alloc(sv, (size_t)kMonitorBlocks * ST_COUNT * 8);
+    }
 
     IterArgs &a = j.a;
     a = IterArgs{};
@@ -466,7 +510,7 @@ bool admit_one(ssmap_server *sv) {
 
     // a1: projection and z^0 = 0, w^0 = a.h, y^0 = 0
     launch_zero(j.bad, 1, 4, s);
-    launch_project(j.mode, j.dM, d.P, cs.Ur, cs.sig, cs.acoef, j.r, j.RP, N, nullptr, nullptr, ah,
+    launch_project(j.mode, j.dM, d.P, cs.Ur, cs.sig, cs.acoef, j.r, j.RP, N, j.t, j.mperp2, ah,
                    w, y, j.bad, nullptr, s);
     launch_zero(j.z[0], (size_t)d.Qp * N, (int)esz, s);
     launch_zero(j.z[1], (size_t)d.Qp * N, (int)esz, s);
@@ -495,6 +539,13 @@ void reap(ssmap_server *sv, Job &j) {
     put_event(sv, j.done_ev, true);
     j.done_ev = nullptr;
     j.status = sv->flags[j.slot] ? SSMAP_ENONFINITE : SSMAP_OK;
+    if (!j.hist_iter.empty()) {
+        const double *h = sv->hist_pinned + (size_t)j.slot * kServedChecks * ST_COUNT;
+        j.hist_sums.assign(h, h + j.hist_iter.size() * ST_COUNT);
+        for (size_t i = 0; i < j.hist_iter.size(); ++i)
+            if (h[i * ST_COUNT + ST_NONFINITE] != 0.0 || !std::isfinite(h[i * ST_COUNT + ST_DATA]))
+                j.status = SSMAP_ENONFINITE;
+    }
     sv->free_slots.push_back(j.slot);
     j.slot = -1;
     j.state = DONE;
@@ -527,6 +578,39 @@ void close_chunk(ssmap_server *sv, Class &C) {
     put_event(sv, ch.end, true);
 }
 
+// Whether a monitored job takes a check once its class has run `round` rounds
+// (every check_every-th iteration of the job and its last).
+bool checked_after_round(const Job &j, int64_t round) {
+    if (j.check_every <= 0) return false;
+    const int64_t done = round - j.r0;
+    return done > 0 && done <= j.iters && (done % j.check_every == 0 || done == j.iters);
+}
+
+// The reductions of a job's check after its iteration `done` (z^done against
+// z^{done-1}, y^done from the job's r-vector state, the per-brick sums of the
+// class's monitored launch), in stream order, into the job's next check slot.
+void monitor_job(ssmap_server *sv, const Class &C, Job &j, hipStream_t s) {
+    const Dict &d = sv->dicts[j.dict];
+    const int done = (int)(C.round - j.r0);
+    if ((int)j.hist_iter.size() >= j.nchecks) sfail(SSMAP_EINVAL, "more monitor checks than planned");
+    MonArgs m{};
+    m.z = j.z[done & 1];
+    m.y = j.a.y;
+    m.dzpart = C.dmon + j.tile_off;
+    m.ndz = j.tile_cnt;
+    m.sig = j.sig;
+    m.t = j.t;
+    m.mperp2 = j.mperp2;
+    m.r = j.r;
+    m.RP = j.RP;
+    m.Q = d.Q;
+    m.g = j.g;
+    m.nchunk = d.nchunk;
+    launch_monitor(j.mode, m, sv->lane_partial[C.lane], j.hist + j.hist_iter.size() * ST_COUNT, s);
+    HIPS(sv, hipGetLastError());
+    j.hist_iter.push_back(done);
+}
+
 // Enqueue about horizon_ms of rounds for class C (at most two chunks per
 // class in flight: the host waits for the older one first).
 void run_class(ssmap_server *sv, Class &C, double horizon_ms) {
@@ -551,10 +635,18 @@ void run_class(ssmap_server *sv, Class &C, double horizon_ms) {
         L.ntiles = C.ntiles;
         L.maxchunk = C.maxchunk;
         L.round = (int)(C.round & 0x3fffffff);   // only the parity matters
+        // member jobs whose check falls after this round: the monitored build sums
+        // (z^{k+1} - z^k)^2 per brick, then each such job's reductions follow
+        bool any_check = false;
+        for (int64_t id : C.members) any_check |= checked_after_round(sv->jobs[id], C.round + 1);
+        L.mon = any_check ? C.dmon : nullptr;
         if (!launch_fused(L, s)) sfail(SSMAP_EINVAL, "no fused kernel for this class");
         sv->stats.launches++;
         ch.rounds++;
         C.round++;
+        if (any_check)
+            for (int64_t id : C.members)
+                if (checked_after_round(sv->jobs[id], C.round)) monitor_job(sv, C, sv->jobs[id], s);
         for (size_t k = 0; k < C.members.size();) {
             Job &j = sv->jobs[C.members[k]];
             if (C.round - j.r0 == j.iters) {
@@ -641,6 +733,7 @@ void free_server(ssmap_server *sv) {
     if (sv->slab_base) (void)hipFree(sv->slab_base);
     if (sv->stage) (void)hipHostFree(sv->stage);
     if (sv->flags) (void)hipHostFree(sv->flags);
+    if (sv->hist_pinned) (void)hipHostFree(sv->hist_pinned);
     delete sv;
 }
 
@@ -743,8 +836,13 @@ ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t gr
         if (st.rank < -1 || st.rank > d.kmin) sfail(SSMAP_EINVAL, "rank must be in [-1, min(P,Q)]");
         if (st.precision < SSMAP_FP64 || st.precision > SSMAP_BF16X3)
             sfail(SSMAP_EINVAL, "unknown precision");
-        if (st.check_every != 0 || st.flags != 0 || st.stop_tol != 0)
-            sfail(SSMAP_EINVAL, "served jobs take no monitoring, no flags and no stopping rule");
+        if (st.check_every < 0 || st.flags != 0 || st.stop_tol != 0)
+            sfail(SSMAP_EINVAL, "served jobs take no flags and no stopping rule; check_every >= 0");
+        const int nchecks = st.check_every > 0 && iters > 0
+                                ? iters / st.check_every + (iters % st.check_every != 0) : 0;
+        if (nchecks > kServedChecks)
+            sfail(SSMAP_EINVAL, "a served job takes at most " + std::to_string(kServedChecks) +
+                                    " monitor checks (iters / check_every)");
         if (st.kernel != SSMAP_KERNEL_AUTO && st.kernel != SSMAP_KERNEL_FUSED)
             sfail(SSMAP_EINVAL, "served jobs run the fused kernel");
         Job j;
@@ -762,7 +860,9 @@ ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t gr
             sfail(SSMAP_EINVAL, "no fused kernel for this precision, rank and size");
         j.xi = st.xi_p > 0 ? st.xi_p : kXiFactor * lambda * dtd_norm_closed(j.g) + kEpsXi;
         j.tau = 1.0 / (j.xi + st.beta);
-        j.bytes = job_bytes(j.mode, d.Qp, j.RP, j.g.N);
+        j.check_every = nchecks > 0 ? st.check_every : 0;
+        j.nchecks = nchecks;
+        j.bytes = job_bytes(j.mode, d.Qp, j.RP, j.g.N) + monitor_bytes(j.r, j.g.N, nchecks);
         if ((double)j.bytes > sv->budget)
             sfail(SSMAP_ENOMEM, "job needs " + std::to_string(j.bytes) +
                                     " device bytes, above the server budget");
@@ -802,6 +902,41 @@ ssmap_status ssmap_server_poll(ssmap_server *sv, int64_t job_id, ssmap_job_info 
         out->submit_ms = j.submit_ms;
         out->admit_ms = j.admit_ms;
         out->done_ms = j.done_ms;
+    });
+}
+
+ssmap_status ssmap_server_get_job_stats(ssmap_server *sv, int64_t job_id, ssmap_stats *out) {
+    if (!sv) return SSMAP_EINVAL;
+    return sv_guarded(sv, [&] {
+        if (!out) sfail(SSMAP_EINVAL, "NULL argument");
+        if (job_id < 0 || job_id >= (int64_t)sv->jobs.size()) sfail(SSMAP_EINVAL, "unknown job");
+        Job &j = sv->jobs[job_id];
+        reap(sv, j);
+        if (j.state != DONE) sfail(SSMAP_EINVAL, "job " + std::to_string(job_id) + " is not done");
+        std::memset(out, 0, sizeof(*out));
+        out->rank = j.r;
+        out->rank_padded = j.RP;
+        out->precision = j.mode;
+        out->kernel = SSMAP_KERNEL_FUSED;
+        out->iters = j.iters;
+        out->xi_p = j.xi;
+        out->tau = j.tau;
+        out->dtd_norm = dtd_norm_closed(j.g);
+        out->sigma_max = sv->dicts[j.dict].s.empty() ? 0.0 : sv->dicts[j.dict].s[0];
+        out->device_bytes = (double)j.bytes;
+        // the checks' sums as the single solve records them (Eq. spat, the dual residual, ||z||)
+        const int n = (int)std::min<size_t>(j.hist_iter.size(), SSMAP_MAX_HIST);
+        for (int i = 0; i < n; ++i) {
+            const double *h = j.hist_sums.data() + (size_t)i * ST_COUNT;
+            out->hist_iter[i] = j.hist_iter[i];
+            out->hist_objective[i] = 0.5 * h[ST_DATA] + j.lambda * h[ST_REG];
+            out->hist_dual[i] = j.st.beta * std::sqrt(h[ST_DZ]);
+            out->hist_znorm[i] = std::sqrt(h[ST_ZNORM]);
+            out->hist_primal[i] = -1.0;
+            out->hist_dfcs[i] = -1.0;
+            out->hist_dfcs_f[i] = -1.0;
+        }
+        out->n_hist = n;
     });
 }
 

@@ -151,13 +151,16 @@ def test_zero_iterations_nonfinite_and_rejections(torch_cuda, jobs):
         j0 = sv.submit(d, p.grid, M, p.lam, p.beta, 0, F=F0, ready=True, precision="fp32")
         jb = sv.submit(d, p.grid, Mbad, p.lam, p.beta, 5, ready=True, precision="fp32")
         jg = sv.submit(d, p.grid, M, p.lam, p.beta, 5, ready=True, precision="fp32")
-        bad = [dict(check_every=1), dict(keep_aux=True), dict(autotune=True),
+        bad = [dict(check_every=1, stop_tol=1e-3), dict(keep_aux=True), dict(autotune=True),
                dict(kernel="unfused"), dict(rank=p.K.shape[0] + 1)]
         for kw in bad:
             with pytest.raises(_ffi.SsmapError) as e:
                 sv.submit(d, p.grid, M, p.lam, p.beta, 5, ready=True,
                           **dict(dict(precision="fp32"), **kw))
             assert e.value.status == _ffi.SSMAP_EINVAL, kw
+        with pytest.raises(_ffi.SsmapError) as e:        # 33 monitor checks
+            sv.submit(d, p.grid, M, p.lam, p.beta, 33, ready=True, precision="fp32", check_every=1)
+        assert e.value.status == _ffi.SSMAP_EINVAL
         p2 = jobs[7][0]                                  # P = 60: rank 60 has no fused kernel
         d2 = sv.add_dictionary(p2.K)
         M2 = torch.tensor(p2.m, dtype=torch.float32, device="cuda")
@@ -183,3 +186,47 @@ def test_zero_iterations_nonfinite_and_rejections(torch_cuda, jobs):
         assert torch.isfinite(sv.result(jg)).all()
         with pytest.raises(_ffi.SsmapError):
             sv.poll(12345)
+
+
+def test_served_jobs_monitored(torch_cuda, jobs):
+    """check_every on served jobs (ssmap_server_get_job_stats): each monitored
+    job's history equals the same job solved alone with the fused kernel and
+    monitored alike (the same kernels, bricks and reductions over the same
+    iterates), and its objective the oracle's; an unmonitored job in the same
+    server has no history."""
+    torch = torch_cuda
+    sel = [jobs[0], jobs[1], jobs[6], jobs[8], jobs[9]]
+    every = [5, 0, 7, 4, 3]
+    Ms = device_inputs(torch, sel)
+    with _ffi.Server(4e9, 4) as sv:
+        ids = []
+        for (p, prec, iters), M, e in zip(sel, Ms, every):
+            d = sv.add_dictionary(p.K)
+            ids.append(sv.submit(d, p.grid, M, p.lam, p.beta, iters, ready=True, precision=prec,
+                                 check_every=e))
+        sv.drain()
+        sts = [sv.job_stats(i) for i in ids]
+        Fs = [sv.result(i) for i in ids]
+        with pytest.raises(_ffi.SsmapError):
+            sv.job_stats(12345)
+    J_TOL = {"fp64": 1e-9, "fp32": 1e-4, "bf16x3": 1e-3}
+    for (p, prec, iters), e, st, F in zip(sel, every, sts, Fs):
+        assert st["iters"] == iters and st["kernel"] == 2
+        if e == 0:
+            assert st["hist_iter"] == []
+            continue
+        expect = list(range(e, iters + 1, e)) + ([iters] if iters % e else [])
+        assert st["hist_iter"] == expect
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            zs = mp.solve(p.m, p.lam, p.beta, iters, precision=prec, kernel="fused", check_every=e)
+            one = mp.stats()
+        assert np.array_equal(F.double().cpu().numpy(), zs)
+        assert one["hist_iter"] == st["hist_iter"]
+        for a, b in (("hist_objective", 1e-12), ("hist_znorm", 1e-12), ("hist_dual", 1e-9)):
+            for x, y in zip(st[a], one[a]):
+                assert x == pytest.approx(y, rel=b), (p.grid, prec, a)
+        ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters, track_every=e)
+        J = {k: v for (k, v, _) in ref["hist"]}
+        say("served monitored", p.grid, prec, iters, e, st["hist_objective"][-1], J[iters])
+        for k, v in zip(st["hist_iter"], st["hist_objective"]):
+            assert v == pytest.approx(J[k], rel=J_TOL[prec]), (p.grid, prec, k)
