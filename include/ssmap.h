@@ -427,6 +427,18 @@ ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t gr
                                  const void *dM, double lambda, const ssmap_steps *steps,
                                  int iters, void *dF, int64_t *job_id);
 
+/* ssmap_server_submit for a job on a masked voxel set (the maskless footnote of
+ * Sec. II-C, as ssmap_set_mask for a single solve): mask holds N bytes (host,
+ * copied; nonzero = inside). Outside voxels are not unknowns (their rows of dM
+ * are not read, their z is 0), the regulariser runs over the graph the mask
+ * induces, and xi_p <= 0 takes ||D^T D|| of that graph (computed at submit,
+ * Lanczos on the host). The job holds N bytes more; bricks without an inside
+ * voxel are left out of the shared launches. NULL mask: ssmap_server_submit. */
+ssmap_status ssmap_server_submit_masked(ssmap_server *sv, int dict_id, const int64_t grid[3],
+                                        const uint8_t *mask, const void *dM, double lambda,
+                                        const ssmap_steps *steps, int iters, void *dF,
+                                        int64_t *job_id);
+
 /* Admit the queued jobs that fit, then enqueue about horizon_ms of iterations
  * for every class. Asynchronous: the host blocks only to keep at most two such
  * chunks per class in flight. *n_pending (may be NULL) = jobs not yet done. */

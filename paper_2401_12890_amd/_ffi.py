@@ -38,7 +38,8 @@ EXPORTS = ["ssmap_create", "ssmap_solve", "ssmap_solve_device", "ssmap_solve_dev
            "ssmap_batch_get_stats", "ssmap_batch_get_job_stats", "ssmap_batch_last_error",
            "ssmap_batch_destroy",
            "ssmap_server_create", "ssmap_server_add_dictionary", "ssmap_server_submit",
-           "ssmap_server_pump", "ssmap_server_poll", "ssmap_server_get_job_stats", "ssmap_server_drain",
+           "ssmap_server_submit_masked", "ssmap_server_pump", "ssmap_server_poll",
+           "ssmap_server_get_job_stats", "ssmap_server_drain",
            "ssmap_server_get_stats", "ssmap_server_last_error", "ssmap_server_destroy"]
 SSMAP_AUTOTUNE = 2
 MAX_CLASSES = 16
@@ -183,6 +184,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.ssmap_server_submit.argtypes = [vp, ip, i64p, vp, ctypes.c_double, ctypes.POINTER(Steps),
                                         ip, vp, i64p]
     lib.ssmap_server_submit.restype = ip
+    lib.ssmap_server_submit_masked.argtypes = [vp, ip, i64p, ctypes.POINTER(ctypes.c_uint8), vp,
+                                               ctypes.c_double, ctypes.POINTER(Steps), ip, vp, i64p]
+    lib.ssmap_server_submit_masked.restype = ip
     lib.ssmap_server_pump.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
     lib.ssmap_server_pump.restype = ip
     lib.ssmap_server_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(JobInfo)]
@@ -585,12 +589,23 @@ def ssmap_server_add_dictionary(sv, K: np.ndarray) -> int:
     return d.value
 
 
-def ssmap_server_submit(sv, dict_id, grid, dM, lam, steps, iters, dF) -> int:
+def ssmap_server_submit(sv, dict_id, grid, dM, lam, steps, iters, dF, mask=None) -> int:
+    """Queue a job; `mask` (N values, nonzero = inside, copied) makes it a masked job."""
     g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
     jid = ctypes.c_int64()
-    _scheck(sv, load().ssmap_server_submit(sv, int(dict_id), g, ctypes.c_void_p(dM), float(lam),
-                                           ctypes.byref(steps), int(iters), ctypes.c_void_p(dF),
-                                           ctypes.byref(jid)))
+    if mask is None:
+        st = load().ssmap_server_submit(sv, int(dict_id), g, ctypes.c_void_p(dM), float(lam),
+                                        ctypes.byref(steps), int(iters), ctypes.c_void_p(dF),
+                                        ctypes.byref(jid))
+    else:
+        mk = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+        if mk.size != int(grid[0]) * int(grid[1]) * int(grid[2]):
+            raise ValueError("mask must hold one value per voxel")
+        st = load().ssmap_server_submit_masked(sv, int(dict_id), g,
+                                               mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                               ctypes.c_void_p(dM), float(lam), ctypes.byref(steps),
+                                               int(iters), ctypes.c_void_p(dF), ctypes.byref(jid))
+    _scheck(sv, st)
     return jid.value
 
 
@@ -648,10 +663,11 @@ class Server:
         self.dicts[d] = np.asarray(K).shape
         return d
 
-    def submit(self, dict_id, grid, M, lam, beta, iters, F=None, ready=False, **kw) -> int:
+    def submit(self, dict_id, grid, M, lam, beta, iters, F=None, ready=False, mask=None, **kw) -> int:
         """Queue a job on device tensor M (N, P), float64 for fp64 and float32
         otherwise; returns its id. Unless `ready`, the current torch stream is
-        synchronized first so that M is complete when the server reads it."""
+        synchronized first so that M is complete when the server reads it.
+        `mask` (N values, nonzero = inside) makes it a masked job."""
         import torch
         P, Q = self.dicts[dict_id]
         N = int(grid[0]) * int(grid[1]) * int(grid[2])
@@ -666,7 +682,7 @@ class Server:
         if not ready:
             torch.cuda.current_stream(M.device).synchronize()
         jid = ssmap_server_submit(self.sv, dict_id, grid, M.data_ptr(), lam, steps, iters,
-                                  F.data_ptr())
+                                  F.data_ptr(), mask=mask)
         self.live[jid] = (M, F)
         return jid
 

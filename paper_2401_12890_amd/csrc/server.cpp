@@ -110,6 +110,11 @@ struct Job {
     int tile_off = 0, tile_cnt = 0;
     std::vector<int> hist_iter;
     std::vector<double> hist_sums;
+    // masked job: the code byte of every voxel (bit 7 inside, bits 0..2 inside face
+    // neighbours), on the host and in the job's memory
+    std::vector<uint8_t> code;
+    uint8_t *dcode = nullptr;
+    double dtd = 0;                       // ||D^T D|| of the job's grid (or of its mask's graph)
 };
 
 struct Class {
@@ -388,7 +393,7 @@ void upload_tables(ssmap_server *sv, Class &C) {
         args[2 * k + 1] = args_at(j, 1);
         args[2 * k].phase = args[2 * k + 1].phase = (int)(j.r0 & 1);
         j.tile_off = (int)tiles.size();
-        append_tiles(j.g, (int)k, C.mode, C.shape, tiles);
+        append_tiles(j.g, (int)k, C.mode, C.shape, tiles, j.code.empty() ? nullptr : &j.code);
         j.tile_cnt = (int)tiles.size() - j.tile_off;
         const size_t esz = j.mode == MODE_FP64 ? 8 : 4;
         bytes += (double)j.g.N * (2.0 * j.a.nchunk * QC + 5.0 * j.RP) * esz;
@@ -479,6 +484,10 @@ bool admit_one(ssmap_server *sv) {
     j.z[0] = p;
     j.z[1] = p + zb;
     void *w = p + 2 * zb, *y = p + 2 * zb + rb, *ah = p + 2 * zb + 2 * rb;
+    if (!j.code.empty()) {
+        j.dcode = p + 2 * zb + 3 * rb + monitor_bytes(j.r, N, j.nchecks);
+        upload(sv, li, j.dcode, j.code.data(), j.code.size());
+    }
     if (j.check_every > 0) {
         uint8_t *mp = p + 2 * zb + 3 * rb;
         j.t = (double *)mp;
@@ -507,11 +516,12 @@ bool admit_one(ssmap_server *sv) {
     a.tau = j.tau;
     a.lam2 = 2.0 * j.lambda;
     a.beta = j.st.beta;
+    a.code = j.dcode;
 
     // a1: projection and z^0 = 0, w^0 = a.h, y^0 = 0
     launch_zero(j.bad, 1, 4, s);
     launch_project(j.mode, j.dM, d.P, cs.Ur, cs.sig, cs.acoef, j.r, j.RP, N, j.t, j.mperp2, ah,
-                   w, y, j.bad, nullptr, s);
+                   w, y, j.bad, j.dcode, s);
     launch_zero(j.z[0], (size_t)d.Qp * N, (int)esz, s);
     launch_zero(j.z[1], (size_t)d.Qp * N, (int)esz, s);
     HIPS(sv, hipGetLastError());
@@ -606,6 +616,7 @@ void monitor_job(ssmap_server *sv, const Class &C, Job &j, hipStream_t s) {
     m.Q = d.Q;
     m.g = j.g;
     m.nchunk = d.nchunk;
+    m.code = j.dcode;
     launch_monitor(j.mode, m, sv->lane_partial[C.lane], j.hist + j.hist_iter.size() * ST_COUNT, s);
     HIPS(sv, hipGetLastError());
     j.hist_iter.push_back(done);
@@ -816,9 +827,9 @@ ssmap_status ssmap_server_add_dictionary(ssmap_server *sv, const double *K, int 
     });
 }
 
-ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t grid[3],
-                                 const void *dM, double lambda, const ssmap_steps *steps,
-                                 int iters, void *dF, int64_t *job_id) {
+ssmap_status ssmap_server_submit_masked(ssmap_server *sv, int dict_id, const int64_t grid[3],
+                                        const uint8_t *mask, const void *dM, double lambda,
+                                        const ssmap_steps *steps, int iters, void *dF, int64_t *job_id) {
     if (!sv) return SSMAP_EINVAL;
     return sv_guarded(sv, [&] {
         if (!grid || !dM || !dF || !steps || !job_id) sfail(SSMAP_EINVAL, "NULL argument");
@@ -858,11 +869,21 @@ ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t gr
         j.RP = (j.r + 15) / 16 * 16;
         if (!fused_supported(j.mode, j.RP, j.g.N))
             sfail(SSMAP_EINVAL, "no fused kernel for this precision, rank and size");
-        j.xi = st.xi_p > 0 ? st.xi_p : kXiFactor * lambda * dtd_norm_closed(j.g) + kEpsXi;
+        double dtd = 0.0;
+        if (mask) {                      // the graph the mask induces (as ssmap_set_mask)
+            int64_t inside = 0;
+            mask_codes(j.g, mask, j.code, inside);
+            dtd = masked_dtd_norm(j.g, j.code);
+        } else {
+            dtd = dtd_norm_closed(j.g);
+        }
+        j.dtd = dtd;
+        j.xi = st.xi_p > 0 ? st.xi_p : kXiFactor * lambda * dtd + kEpsXi;
         j.tau = 1.0 / (j.xi + st.beta);
         j.check_every = nchecks > 0 ? st.check_every : 0;
         j.nchecks = nchecks;
-        j.bytes = job_bytes(j.mode, d.Qp, j.RP, j.g.N) + monitor_bytes(j.r, j.g.N, nchecks);
+        j.bytes = job_bytes(j.mode, d.Qp, j.RP, j.g.N) + monitor_bytes(j.r, j.g.N, nchecks) +
+                  (mask ? align_up((size_t)j.g.N) : 0);
         if ((double)j.bytes > sv->budget)
             sfail(SSMAP_ENOMEM, "job needs " + std::to_string(j.bytes) +
                                     " device bytes, above the server budget");
@@ -872,6 +893,12 @@ ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t gr
         sv->queue.push_back(*job_id);
         sv->stats.submitted++;
     });
+}
+
+ssmap_status ssmap_server_submit(ssmap_server *sv, int dict_id, const int64_t grid[3],
+                                 const void *dM, double lambda, const ssmap_steps *steps,
+                                 int iters, void *dF, int64_t *job_id) {
+    return ssmap_server_submit_masked(sv, dict_id, grid, nullptr, dM, lambda, steps, iters, dF, job_id);
 }
 
 ssmap_status ssmap_server_pump(ssmap_server *sv, double horizon_ms, int *n_pending) {
@@ -921,7 +948,7 @@ ssmap_status ssmap_server_get_job_stats(ssmap_server *sv, int64_t job_id, ssmap_
         out->iters = j.iters;
         out->xi_p = j.xi;
         out->tau = j.tau;
-        out->dtd_norm = dtd_norm_closed(j.g);
+        out->dtd_norm = j.dtd;
         out->sigma_max = sv->dicts[j.dict].s.empty() ? 0.0 : sv->dicts[j.dict].s[0];
         out->device_bytes = (double)j.bytes;
         // the checks' sums as the single solve records them (Eq. spat, the dual residual, ||z||)

@@ -230,3 +230,56 @@ def test_served_jobs_monitored(torch_cuda, jobs):
         say("served monitored", p.grid, prec, iters, e, st["hist_objective"][-1], J[iters])
         for k, v in zip(st["hist_iter"], st["hist_objective"]):
             assert v == pytest.approx(J[k], rel=J_TOL[prec]), (p.grid, prec, k)
+
+
+def test_served_masked_jobs(torch_cuda, jobs):
+    """Masked served jobs (ssmap_server_submit_masked; the maskless footnote of
+    Sec. II-C): bitwise the single solve with the same mask (ssmap_set_mask,
+    fused kernel), zero outside, within tolerance of the oracle's masked solve,
+    and NaN data outside the mask never read; a masked job shares the server
+    with an unmasked one and takes monitoring."""
+    torch = torch_cuda
+    p2 = synth.generate("c1", grid=(29, 23, 1), iters=30)
+    yy, xx = np.mgrid[0:23, 0:29]
+    m2 = (((xx - 14) ** 2 + (yy - 11) ** 2 < 100) & ~((xx - 16) ** 2 + (yy - 12) ** 2 < 6)).reshape(-1)
+    p3 = synth.generate("c2", grid=(19, 11, 5), iters=17)
+    zz, yy, xx = np.mgrid[0:5, 0:11, 0:19]
+    m3 = ((((xx - 9) / 8.0) ** 2 + ((yy - 5) / 4.5) ** 2 + ((zz - 2) / 2.2) ** 2) < 1.0).reshape(-1)
+    cases = [(p2, "fp64", 30, m2, 6), (p3, "fp32", 17, m3, 0), (jobs[0][0], "fp32", 20, None, 0)]
+    Ms = []
+    for p, prec, _, mask, _ in cases:
+        m = p.m.copy()
+        if mask is not None:
+            m[~mask] = np.nan                          # outside rows are never read
+        Ms.append(torch.tensor(m, dtype=getattr(torch, TORCH_T[prec]), device="cuda"))
+    torch.cuda.synchronize()
+    with _ffi.Server(4e9, 4) as sv:
+        ids = []
+        for (p, prec, iters, mask, every), M in zip(cases, Ms):
+            d = sv.add_dictionary(p.K)
+            ids.append(sv.submit(d, p.grid, M, p.lam, p.beta, iters, ready=True, precision=prec,
+                                 mask=mask, check_every=every))
+        sv.drain()
+        infos = [sv.poll(i) for i in ids]
+        sts = [sv.job_stats(i) for i in ids]
+        Fs = [sv.result(i) for i in ids]
+    for (p, prec, iters, mask, every), F, info, st in zip(cases, Fs, infos, sts):
+        assert info["status"] == _ffi.SSMAP_OK
+        z = F.double().cpu().numpy()
+        with _ffi.Mapper(p.K, p.grid) as mp:
+            if mask is not None:
+                mp.set_mask(mask)
+            zs = mp.solve(p.m, p.lam, p.beta, iters, precision=prec, kernel="fused", check_every=every)
+            one = mp.stats()
+        assert np.array_equal(z, zs), (p.grid, prec)
+        assert info["xi_p"] == pytest.approx(one["xi_p"], rel=1e-13)
+        ref = oracle.ladmm(p.K, p.m, p.grid, p.lam, p.beta, iters, mask=mask)
+        err = np.linalg.norm(z - ref["z"]) / np.linalg.norm(ref["z"])
+        say("served masked", p.grid, prec, "inside", None if mask is None else int(mask.sum()), err)
+        assert err <= TOL[prec]
+        if mask is not None:
+            assert np.all(z[~mask] == 0.0)
+        if every:
+            assert st["hist_iter"] == one["hist_iter"] and len(st["hist_iter"]) > 0
+            for x, y in zip(st["hist_objective"], one["hist_objective"]):
+                assert x == pytest.approx(y, rel=1e-12)
