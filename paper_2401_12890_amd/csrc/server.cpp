@@ -386,17 +386,32 @@ IterArgs args_at(const Job &j, int parity) {
 void upload_tables(ssmap_server *sv, Class &C) {
     std::vector<IterArgs> args(2 * C.members.size());
     std::vector<TileRef> tiles;
+    std::vector<std::vector<TileRef>> per(C.members.size());
+    size_t ntiles = 0;
     double bytes = 0;
     for (size_t k = 0; k < C.members.size(); ++k) {
         Job &j = sv->jobs[C.members[k]];
         args[2 * k] = args_at(j, 0);
         args[2 * k + 1] = args_at(j, 1);
         args[2 * k].phase = args[2 * k + 1].phase = (int)(j.r0 & 1);
-        j.tile_off = (int)tiles.size();
-        append_tiles(j.g, (int)k, C.mode, C.shape, tiles, j.code.empty() ? nullptr : &j.code);
-        j.tile_cnt = (int)tiles.size() - j.tile_off;
+        append_tiles(j.g, (int)k, C.mode, C.shape, per[k], j.code.empty() ? nullptr : &j.code);
+        ntiles += per[k].size();
         const size_t esz = j.mode == MODE_FP64 ? 8 : 4;
         bytes += (double)j.g.N * (2.0 * j.a.nchunk * QC + 5.0 * j.RP) * esz;
+    }
+    // jobs with the most chunks first when workgroup b takes brick b (the brick
+    // count not a multiple of 8), as for batches; a job's bricks stay contiguous
+    std::vector<size_t> order(C.members.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    if (ntiles % 8 != 0)
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            return args[2 * x].nchunk > args[2 * y].nchunk;
+        });
+    for (size_t k : order) {
+        Job &j = sv->jobs[C.members[k]];
+        j.tile_off = (int)tiles.size();
+        tiles.insert(tiles.end(), per[k].begin(), per[k].end());
+        j.tile_cnt = (int)per[k].size();
     }
     if (args.size() > C.cap_jobs) {
         C.cap_jobs = std::max<size_t>(2 * args.size(), 16);

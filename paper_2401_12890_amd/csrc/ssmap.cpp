@@ -1198,15 +1198,32 @@ void upload_class(ssmap_batch *b, int ci, BatchClass &C, const std::vector<Prepa
     C.tile_off.assign(C.jobs.size(), 0);
     C.tile_cnt.assign(C.jobs.size(), 0);
     bool monitored = false;
+    std::vector<std::vector<TileRef>> per(C.jobs.size());
+    size_t ntiles = 0;
     for (size_t k = 0; k < C.jobs.size(); ++k) {
         const int j = C.jobs[k];
         args[2 * k] = args_for(Ps[j], 0);                    // even iterations
         args[2 * k + 1] = args_for(Ps[j], 1);                // odd iterations
-        C.tile_off[k] = (int)tiles.size();
-        append_tiles(b->jobs[j]->g, (int)k, C.mode, shape, tiles,
+        append_tiles(b->jobs[j]->g, (int)k, C.mode, shape, per[k],
                      b->jobs[j]->code.empty() ? nullptr : &b->jobs[j]->code);
-        C.tile_cnt[k] = (int)tiles.size() - C.tile_off[k];
+        ntiles += per[k].size();
         monitored |= Ps[j].monitor;
+    }
+    // A brick walks all of its job's chunks, so bricks of long spectra take longest.
+    // Workgroup b takes brick b when the brick count is not a multiple of 8 (else
+    // each XCD takes a contiguous eighth of the table): then the jobs with the most
+    // chunks go first, so that the short bricks fill in behind the long ones
+    // instead of the long ones running last. A job's bricks stay contiguous.
+    std::vector<size_t> order(C.jobs.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    if (ntiles % 8 != 0)
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            return args[2 * x].nchunk > args[2 * y].nchunk;
+        });
+    for (size_t k : order) {
+        C.tile_off[k] = (int)tiles.size();
+        tiles.insert(tiles.end(), per[k].begin(), per[k].end());
+        C.tile_cnt[k] = (int)per[k].size();
     }
     ssmap_ctx *A = &b->arena;
     const std::string tag = std::to_string(ci);
