@@ -140,7 +140,13 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
 
     const IterArgs &a = sa.a;
     const int nch = a.nchunk;
-    const int item = blockIdx.x;
+    // Workgroup b runs on XCD b % 8. Each XCD takes one contiguous eighth of the
+    // brick-major (brick, chunk) list, so the chunk workgroups of a brick, which all
+    // read the brick's y partials and r-vectors, share one L2 and its write-backs.
+    const int item = [] {
+        const int total = (int)gridDim.x, b = (int)blockIdx.x, x = b & 7;
+        return x * (total >> 3) + min(x, total & 7) + (b >> 3);
+    }();
     // the brick: from the table for a masked grid (only bricks with an inside
     // voxel), else straight from the index (x-fastest order, as the table lists it)
     TileRef tr;
