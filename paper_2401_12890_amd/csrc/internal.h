@@ -159,6 +159,7 @@ struct MonArgs {
     const uint8_t *code;      // mask codes or NULL
 };
 constexpr int kMonitorBlocks = 4096;  // partial sums: kMonitorBlocks x ST_COUNT doubles
+constexpr int kMonitorSpreadTiles = 1024;  // grids of at most this many 16-voxel tiles: a block per tile
 void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hipStream_t s);
 int monitor_blocks(int64_t N);
 

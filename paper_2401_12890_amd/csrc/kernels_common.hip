@@ -293,6 +293,10 @@ k_aux_post(T *__restrict__ t, const T *__restrict__ znew, T beta, size_t count) 
 // takes every forward face edge once (both ends inside a mask). Sums are
 // reduced across the wave by shuffles, across the four waves through LDS,
 // then in a fixed order over the blocks, so every result is bitwise repeatable.
+// SP (small grids with y given): a block takes one 16-voxel tile and its four
+// waves split the chunks (c = wave mod 4) and the ranks (r = lane / 16 + 4 wave
+// mod 16), a quarter of the serial loads per wave where the few tiles would
+// leave most CUs idle.
 typedef double v4d_m __attribute__((ext_vector_type(4)));
 
 template <typename T, bool VM>
@@ -315,7 +319,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int MON_RG = 4;                // 16-rank blocks per pass over z
 
-template <typename T, bool VM>
+template <typename T, bool VM, bool SP>
 __global__ void __launch_bounds__(256)
 k_monitor(MonArgs a, double *__restrict__ partial) {
     const T *z = (const T *)a.z;
@@ -334,7 +338,11 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
 #pragma unroll
     for (int k = 0; k < ST_COUNT; ++k) acc[k] = 0.0;
     const int64_t ntile = (N + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    const int64_t t0 = SP ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+    const int64_t tstep = SP ? (int64_t)gridDim.x : (int64_t)gridDim.x * 4;
+    const int c0 = SP ? wave : 0, cstep = SP ? 4 : 1;             // chunks of this wave
+    const int r0 = SP ? i4 + 4 * wave : i4, rstep = SP ? 16 : 4;  // ranks of this wave
+    for (int64_t tile = t0; tile < ntile; tile += tstep) {
         const int64_t n = tile * 16 + j;
         const bool valid = n < N;
         const int64_t x = n % nx, yy = (n / nx) % ny, zz = n / (nx * ny);
@@ -344,7 +352,7 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
         const bool ez = ein && zz + 1 < nz && in(n + nx * ny);
         const bool contract = a.y == nullptr && a.ypart == nullptr;
         if (!contract && valid)             // data term from the iteration's y
-            for (int rr = i4; rr < a.r; rr += 4) {
+            for (int rr = r0; rr < a.r; rr += rstep) {
                 double yv;
                 if (a.ypart) {              // the partials in chunk order, as the next iteration sums them
                     T ys = (T)0;            // (bricks outside a mask are never written; z = y = 0 there)
@@ -369,7 +377,7 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
             v4d_m yacc[MON_RG];
 #pragma unroll
             for (int g = 0; g < MON_RG; ++g) yacc[g] = v4d_m{0.0, 0.0, 0.0, 0.0};
-            for (int c = 0; c < a.nchunk; ++c) {
+            for (int c = c0; c < a.nchunk; c += cstep) {
                 T zv[4];
                 load4<T, VM>(z, at(c, n), valid, zv);
                 if (rg == 0) {
@@ -436,7 +444,7 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
                     }
                 }
         }
-        if (valid && i4 == 0) acc[ST_DATA] += a.mperp2[n];
+        if (valid && i4 == 0 && (!SP || wave == 0)) acc[ST_DATA] += a.mperp2[n];
     }
     __shared__ double red[4][ST_COUNT];
 #pragma unroll
@@ -890,14 +898,18 @@ void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hi
                            out);
         return;
     }
-    const int nb = monitor_blocks(a.g.N);
+    // small grids with y given: one tile per block, the waves splitting chunks and ranks
+    const int64_t ntile = (a.g.N + 15) / 16;
+    const bool sp = (a.y || a.ypart) && ntile <= kMonitorSpreadTiles;
+    const int nb = sp ? (int)(ntile > 0 ? ntile : 1) : monitor_blocks(a.g.N);
     const bool vm = a.ld > 0;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, a, partial); };
     if (mode == MODE_FP64) {
-        if (vm) hipLaunchKernelGGL((k_monitor<double, true>), dim3(nb), dim3(256), 0, s, a, partial);
-        else hipLaunchKernelGGL((k_monitor<double, false>), dim3(nb), dim3(256), 0, s, a, partial);
+        if (vm) sp ? go(k_monitor<double, true, true>) : go(k_monitor<double, true, false>);
+        else sp ? go(k_monitor<double, false, true>) : go(k_monitor<double, false, false>);
     } else {
-        if (vm) hipLaunchKernelGGL((k_monitor<float, true>), dim3(nb), dim3(256), 0, s, a, partial);
-        else hipLaunchKernelGGL((k_monitor<float, false>), dim3(nb), dim3(256), 0, s, a, partial);
+        if (vm) sp ? go(k_monitor<float, true, true>) : go(k_monitor<float, true, false>);
+        else sp ? go(k_monitor<float, false, true>) : go(k_monitor<float, false, false>);
     }
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, a.dzpart, a.ndz, out);
 }
