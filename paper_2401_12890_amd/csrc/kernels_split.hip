@@ -139,6 +139,12 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     __shared__ uint4 ldsv[VB / 16];
 
     const IterArgs &a = sa.a;
+    // One argument from each 64-byte line of the argument block, needed together:
+    // all four lines arrive in one scalar round trip, and the argument loads the
+    // compiler places later (after the brick lookup) hit the scalar cache instead
+    // of waiting out a miss just before the first vector load. (An empty asm
+    // statement: it only asks for the values in scalar registers at this point.)
+    asm volatile("" ::"s"(a.z), "s"(a.nchunk), "s"(a.code), "s"(sa.yout));
     const int nch = a.nchunk;
     // Workgroup b runs on XCD b % 8. Each XCD takes one contiguous eighth of the
     // brick-major (brick, chunk) list, so the chunk workgroups of a brick, which all
