@@ -133,10 +133,16 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     constexpr int VB = (MODE == MODE_FP64 ? 4096 : 2048) * RB;   // bytes of a chunk's V block
     constexpr int PG = 8;                // chunk partials loaded per group
     static_assert(NB % NW == 0, "brick rows must split over the waves");
-    constexpr int VL = (VB / 16 + NT - 1) / NT;   // 16-byte pieces of the V block per thread
+    // Thin bricks (at most 256 threads, registers to spare) keep the staged values in
+    // registers until the row loads below have been issued too, so that both go out
+    // in one memory round trip, and load their V operands straight into registers
+    // (each lane's values are coalesced in the chunk's block); the 512-thread bricks
+    // stage the block through LDS, which spares the registers.
+    constexpr bool HOLD = NT <= 256;
+    constexpr int VL = HOLD ? 1 : (VB / 16 + NT - 1) / NT;   // 16-byte pieces of the V block per thread
     static_assert(VB % 16 == 0, "V block of whole 16-byte pieces");
     __shared__ V4 lds[4 * B::NSP + 1];
-    __shared__ uint4 ldsv[VB / 16];
+    __shared__ uint4 ldsv[HOLD ? 1 : VB / 16];
 
     const IterArgs &a = sa.a;
     // One argument from each 64-byte line of the argument block, needed together:
@@ -172,20 +178,18 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     const unsigned chunk_bytes = (unsigned)(chunk_elems * sizeof(T));
     const T tau = (T)a.tau, lam2 = (T)a.lam2, beta = (T)a.beta;
 
-    // ---- stage z^k of chunk c (brick and face halo) and the chunk's V operand block.
-    // Thin bricks (at most 256 threads, registers to spare) keep the staged values in
-    // registers until the row loads below have been issued too, so that both go out
-    // in one memory round trip, and write them to LDS before the barrier.
-    constexpr bool HOLD = NT <= 256;
+    // ---- stage z^k of chunk c (brick and face halo) and, for the 512-thread bricks,
+    // the chunk's V operand block
     V4 R[NL];
     int loff[NL];
     uint4 Rv[VL];
     auto stage_to_lds = [&]() {
 #pragma unroll
         for (int l = 0; l < NL; ++l) lds[loff[l]] = R[l];
+        if constexpr (!HOLD)
 #pragma unroll
-        for (int v = 0; v < VL; ++v)
-            if (tid + NT * v < VB / 16) ldsv[tid + NT * v] = Rv[v];
+            for (int v = 0; v < VL; ++v)
+                if (tid + NT * v < VB / 16) ldsv[tid + NT * v] = Rv[v];
     };
     {
         const __amdgpu_buffer_rsrc_t zr = rsrc((const T *)a.z + (size_t)c * chunk_elems, chunk_bytes);
@@ -204,15 +208,45 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
             }
             R[l] = F::load(zr, off);
         }
-        const __amdgpu_buffer_rsrc_t vr = rsrc(a.Vu, (unsigned)(nch * VB));
+        if constexpr (!HOLD) {
+            const __amdgpu_buffer_rsrc_t vr = rsrc(a.Vu, (unsigned)(nch * VB));
 #pragma unroll
-        for (int v = 0; v < VL; ++v) {
-            const int piece = tid + NT * v;
-            Rv[v] = __builtin_bit_cast(
-                uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                           vr, piece < VB / 16 ? (unsigned)(c * VB + 16 * piece) : OOB, 0, 0));
+            for (int v = 0; v < VL; ++v) {
+                const int piece = tid + NT * v;
+                Rv[v] = __builtin_bit_cast(
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                               vr, piece < VB / 16 ? (unsigned)(c * VB + 16 * piece) : OOB, 0, 0));
+            }
+            stage_to_lds();
         }
-        if constexpr (!HOLD) stage_to_lds();
+    }
+
+    // ---- V operands of the chunk: lane l takes element e * 64 + l of the block for
+    // the u steps and the y blocks, and the tail table of its quad (float32 ranks 17..20)
+    T vu[KSU], vy[RBM][4], vt[TAIL ? 4 : 1][4];
+    auto v_operands = [&](auto &&elem) {
+#pragma unroll
+        for (int s = 0; s < KSU; ++s) vu[s] = elem(s * 64 + lane);
+#pragma unroll
+        for (int rb = 0; rb < RBM; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) vy[rb][i] = elem((KS + rb * 4 + i) * 64 + lane);
+        if constexpr (TAIL) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) vt[i][t] = elem((KS + 4) * 64 + i4 * 16 + i * 4 + t);
+        }
+    };
+    if constexpr (HOLD) {                // issued with the row loads below
+        const __amdgpu_buffer_rsrc_t vr = rsrc(a.Vu, (unsigned)(nch * VB));
+        v_operands([&](int e) -> T {
+            const unsigned off = (unsigned)(c * VB) + (unsigned)(e * sizeof(T));
+            if constexpr (sizeof(T) == 8)
+                return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(vr, off, 0, 0));
+            else
+                return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(vr, off, 0, 0));
+        });
     }
 
     // ---- per-row voxels and w^k of the u operand (lane: ranks 4 s + l/16, voxel j)
@@ -298,24 +332,8 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     if constexpr (HOLD) stage_to_lds();
     __syncthreads();
 
-    // ---- V operands of the chunk, the update of its 16 nodes, partial y^{k+1}
-    T vu[KSU], vy[RBM][4], vt[TAIL ? 4 : 1][4];
-    {
-        const T *VT = (const T *)ldsv;
-#pragma unroll
-        for (int s = 0; s < KSU; ++s) vu[s] = VT[s * 64 + lane];
-#pragma unroll
-        for (int rb = 0; rb < RBM; ++rb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) vy[rb][i] = VT[(KS + rb * 4 + i) * 64 + lane];
-        if constexpr (TAIL) {
-            const T *VTt = VT + (KS + 4) * 64 + i4 * 16;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) vt[i][t] = VTt[i * 4 + t];
-        }
-    }
+    // ---- the update of the chunk's 16 nodes, partial y^{k+1}
+    if constexpr (!HOLD) v_operands([&](int e) -> T { return ((const T *)ldsv)[e]; });
     const __amdgpu_buffer_rsrc_t zo = rsrc((T *)a.znew + (size_t)c * chunk_elems, chunk_bytes);
     const unsigned pbytes = (unsigned)(pstride * sizeof(T));
     const __amdgpu_buffer_rsrc_t po = rsrc((T *)sa.pout + (size_t)c * pstride, pbytes);
