@@ -142,25 +142,29 @@ def iters300_parity(name, prec, kernel, F=None):
             "tol": {"fp32": 1e-5, "bf16x3": 1e-3, "fp64": 1e-10}[prec]}
 
 
-def kernel_source_digest():
-    """sha256 of the fused-kernel source: counter-derived traffic is only
-    reported while it matches the source the counters were taken on."""
+def kernel_source_digest(source="kernels_fused.hip"):
+    """sha256 of a kernel source file: counter-derived traffic is only reported
+    while it matches the source the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2401_12890_amd", "csrc", "kernels_fused.hip")
+    path = os.path.join(ROOT, "paper_2401_12890_amd", "csrc", source)
     with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+def measured_traffic(workload, kernel_id, precision):
+    """HBM bytes per launch of the loop's kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, KiB per dispatch, scaled by the
-    calibration factor measured on a copy kernel of known size), or None."""
+    calibration factor measured on a copy kernel of known size), or None when
+    there is none for this workload, kernel family (2 fused, 4 chunk split) and
+    precision, or its kernel source has changed since."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_sha256") != kernel_source_digest():
+    if rec.get("kernel_id", 2) != kernel_id or rec.get("precision") != precision:
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_digest(rec.get("kernel_source_file", "kernels_fused.hip")):
         return None
     kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + \
         rec["write_kib_per_dispatch"] * rec["write_scale"]
@@ -632,7 +636,7 @@ def main():
                     "issued_flops_per_launch": sum(x[1] for x in gemm) / len(gemm) / n_launch,
                     "gemm_share_of_loop": round(g_ms / (sum(loop_ms) / len(loop_ms)), 4)}
     else:
-        traffic = measured_traffic(args.workload) if args.kernel in ("auto", "fused") else None
+        traffic = measured_traffic(args.workload, st["kernel"], prec)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": kern_name, "avg_launch_ms": round(per_launch_ms, 5),
