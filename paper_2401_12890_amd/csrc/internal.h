@@ -99,17 +99,15 @@ void fused_operands_bf16(const std::vector<double> &Vh, int Qp, int RP, std::vec
 
 // Small problems split over spectral chunks (kernels_split.hip): one workgroup
 // per (brick, chunk). The r-vectors travel as partial products: pin holds the
-// per-chunk partials of y^k ([chunk][rank][voxel], RP x N per chunk), win/yin
-// w^{k-1} and y^{k-1}; the launch writes its chunks' partials of y^{k+1} to
-// pout and, from the chunk-0 workgroups, w^k and y^k to wout/yout.
+// per-chunk partials of y^k ([chunk][rank][voxel], RP x N per chunk), sin
+// s^k = y^{k-1} + w^{k-1} (RP x N); the launch writes its chunks' partials of
+// y^{k+1} to pout and, from the chunk-0 workgroups, s^{k+1} = y^k + w^k to sout.
 struct SplitArgs {
     IterArgs a;
     const void *pin;
     void *pout;
-    const void *win;
-    void *wout;
-    const void *yin;
-    void *yout;
+    const void *sin;
+    void *sout;
 };
 bool launch_split(int mode, const SplitArgs &sa, FusedShape sh, const TileRef *tiles, int ntiles,
                   hipStream_t s);   // false: no such mode or shape

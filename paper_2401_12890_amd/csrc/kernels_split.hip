@@ -7,13 +7,15 @@
 //   1. forms w^k for its brick's voxels from the r-vectors, with
 //      y^k = sum over chunks of the partial products V_c^T z^k_c that the
 //      previous launch left (added in chunk order, so results are repeatable):
-//      w^k = a.h - b.(2 y^k - y^{k-1} - w^{k-1})  (w^0 = a.h);
+//      w^k = a.h - b.(2 y^k - s^k), s^k = y^{k-1} + w^{k-1}  (s^0 = 0, w^0 = a.h),
+//      the recursion w^k = a.h - b.(2 y^k - y^{k-1} - w^{k-1}) with one state
+//      array instead of two;
 //   2. stages z^k of its chunk (brick and one-voxel face halo) in LDS and
 //      forms u = V_r w^k on the matrix cores (the f-step contraction of
 //      Eq. DictVecSVD), the D^T D stencil of Eq. (l2) and the projected
 //      z-update of Eq. (z2), and writes its chunk of z^{k+1};
 //   3. writes its chunk's partial y^{k+1}_c = V_c^T z^{k+1}_c.
-// The workgroup of chunk 0 also keeps w^k and y^k for the next launch. The
+// The workgroup of chunk 0 also keeps s^{k+1} = y^k + w^k for the next launch. The
 // r-vectors are double buffered by iteration parity, so no workgroup reads
 // what another writes in the same launch. The lane mapping and the V operand
 // blocks are those of the fused kernel (lane l: voxel l % 16 of a 16-voxel
@@ -150,7 +152,7 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     // compiler places later (after the brick lookup) hit the scalar cache instead
     // of waiting out a miss just before the first vector load. (An empty asm
     // statement: it only asks for the values in scalar registers at this point.)
-    asm volatile("" ::"s"(a.z), "s"(a.nchunk), "s"(a.code), "s"(sa.yout));
+    asm volatile("" ::"s"(a.z), "s"(a.nchunk), "s"(a.code), "s"(sa.sout));
     const int nch = a.nchunk;
     // Workgroup b runs on XCD b % 8. Each XCD takes one contiguous eighth of the
     // brick-major (brick, chunk) list, so the chunk workgroups of a brick, which all
@@ -258,8 +260,7 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
     const size_t pstride = (size_t)a.RP * N;
     const unsigned pbytes1 = (unsigned)(pstride * sizeof(T));      // one chunk's partials
     const __amdgpu_buffer_rsrc_t prs = rsrc(sa.pin, (unsigned)(nch * (size_t)pbytes1)),
-                                 wir = rsrc(sa.win, pbytes1), yir = rsrc(sa.yin, pbytes1),
-                                 wor = rsrc(sa.wout, pbytes1), yor = rsrc(sa.yout, pbytes1),
+                                 sir = rsrc(sa.sin, pbytes1), sor = rsrc(sa.sout, pbytes1),
                                  ahr = rsrc(a.ah, pbytes1),
                                  bcr = rsrc(a.bcoef, (unsigned)(a.RP * sizeof(T)));
     auto ld1 = [](const __amdgpu_buffer_rsrc_t &r, unsigned off) -> T {
@@ -293,7 +294,7 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
         // loads of a group of PG chunks issue before any addition (out-of-range
         // chunks and ranks read 0, which leaves the sums unchanged).
         unsigned orr[KSU];
-        T yk[KSU], ahv[KSU], bcv[KSU], yiv[KSU], wiv[KSU];
+        T yk[KSU], ahv[KSU], bcv[KSU], siv[KSU];
 #pragma unroll
         for (int s = 0; s < KSU; ++s) {
             const int rr = 4 * s + i4;
@@ -301,8 +302,7 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
             yk[s] = (T)0;
             ahv[s] = ld1(ahr, orr[s]);   // issued with the partials below
             bcv[s] = ld1(bcr, rr < a.r ? (unsigned)(rr * sizeof(T)) : OOB);
-            yiv[s] = ld1(yir, orr[s]);
-            wiv[s] = ld1(wir, orr[s]);
+            siv[s] = ld1(sir, orr[s]);
         }
         for (int c0 = 0; c0 < nch; c0 += PG) {
             T pv[PG][KSU];
@@ -319,13 +319,10 @@ k_split(SplitArgs sa, const TileRef *__restrict__ tiles) {
         }
 #pragma unroll
         for (int s = 0; s < KSU; ++s) {
-            const int rr = 4 * s + i4;
-            (void)rr;
-            const T wk = ahv[s] - bcv[s] * ((T)2 * yk[s] - yiv[s] - wiv[s]);
+            const T wk = ahv[s] - bcv[s] * ((T)2 * yk[s] - siv[s]);
             wop[b][s] = wk;
             if (c == 0) {                // kept for the next launch
-                st1(wk, wor, orr[s]);
-                st1(yk[s], yor, orr[s]);
+                st1(yk[s] + wk, sor, orr[s]);
             }
         }
     }

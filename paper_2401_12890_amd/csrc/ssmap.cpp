@@ -394,8 +394,8 @@ struct Prepared {
     mutable void *dbuf = nullptr, *tbuf = nullptr;
     double *monpart = nullptr;    // fused path: per-brick (z^{k+1} - z^k)^2 of a monitored iteration
     int ntiles = 0;
-    // chunk split: partials of y (two iterations), w^{k-1} and y^{k-1} (two each)
-    void *sp[2] = {nullptr, nullptr}, *sw[2] = {nullptr, nullptr}, *sy[2] = {nullptr, nullptr};
+    // chunk split: partials of y (two iterations), s^k = y^{k-1} + w^{k-1} (two)
+    void *sp[2] = {nullptr, nullptr}, *ss[2] = {nullptr, nullptr};
     const void *dM = nullptr;
     int iters = 0;
     double stop_tol = 0.0;
@@ -444,10 +444,9 @@ void init_state(ssmap_ctx *c, Prepared &P, hipStream_t s) {
         launch_zero(P.auxA, (size_t)c->Qp * N, (int)esz, s);
         launch_zero(P.auxB, (size_t)c->Qp * N, (int)esz, s);
     }
-    if (pl.split) {          // y^0 = 0 (its partials), w^{-1} = y^{-1} = 0: then w^0 = a.h
+    if (pl.split) {          // y^0 = 0 (its partials), s^0 = y^{-1} + w^{-1} = 0: then w^0 = a.h
         launch_zero(P.sp[0], (size_t)c->nchunk * pl.RP * N, (int)esz, s);
-        launch_zero(P.sw[0], (size_t)pl.RP * N, (int)esz, s);
-        launch_zero(P.sy[0], (size_t)pl.RP * N, (int)esz, s);
+        launch_zero(P.ss[0], (size_t)pl.RP * N, (int)esz, s);
     }
     if (P.warm) {            // z^0, y^0, w^0 (and d^0 for the aux bracket) from the initial iterate
         const size_t nq = (size_t)N * c->Q * 8;
@@ -513,7 +512,7 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     if (pl.split)
         for (const char *nm : {"sp0", "sp1"}) need.push_back({nm, (size_t)c->nchunk * rbytes});
     if (pl.split)
-        for (const char *nm : {"sw0", "sw1", "sy0", "sy1"}) need.push_back({nm, rbytes});
+        for (const char *nm : {"ss0", "ss1"}) need.push_back({nm, rbytes});
     if (pl.mode == MODE_BF16X3) {
         need.push_back({"Vhi", (size_t)Qp * RP * 2});
         need.push_back({"Vlo", (size_t)Qp * RP * 2});
@@ -573,9 +572,9 @@ Prepared prepare(ssmap_ctx *c, const void *dM, double lambda, const ssmap_steps 
     P.dbuf = P.auxA;
     P.tbuf = P.auxB;
     if (pl.split) {
-        const char *names[3][2] = {{"sp0", "sp1"}, {"sw0", "sw1"}, {"sy0", "sy1"}};
-        void **dst[3] = {P.sp, P.sw, P.sy};
-        for (int b = 0; b < 3; ++b)
+        const char *names[2][2] = {{"sp0", "sp1"}, {"ss0", "ss1"}};
+        void **dst[2] = {P.sp, P.ss};
+        for (int b = 0; b < 2; ++b)
             for (int k = 0; k < 2; ++k)
                 dst[b][k] = ensure(c, names[b][k], b == 0 ? (size_t)c->nchunk * rbytes : rbytes);
     }
@@ -1029,10 +1028,8 @@ void step_job(ssmap_ctx *c, const Prepared &P, const FusedLaunch *L, int k, hipS
         sa.a = args_for(P, k);
         sa.pin = P.sp[k & 1];
         sa.pout = P.sp[(k + 1) & 1];
-        sa.win = P.sw[k & 1];
-        sa.wout = P.sw[(k + 1) & 1];
-        sa.yin = P.sy[k & 1];
-        sa.yout = P.sy[(k + 1) & 1];
+        sa.sin = P.ss[k & 1];
+        sa.sout = P.ss[(k + 1) & 1];
         if (!launch_split(pl.mode, sa, L->shape, L->tiles, L->ntiles, s))
             fail(SSMAP_EINVAL, "no split kernel for this precision and brick shape");
         return;
