@@ -319,6 +319,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int MON_RG = 4;                // 16-rank blocks per pass over z
 
+// 16 bytes (four float or two double values) through a raw buffer resource;
+// offsets are 32-bit within one chunk of the state
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mon_rsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, unsigned off, T out[4]) {
+    typedef unsigned v4u_m __attribute__((ext_vector_type(4)));
+    const v4u_m a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = __uint_as_float(a[i]);
+    } else {
+        const v4u_m b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+        out[0] = __hiloint2double(a[1], a[0]);
+        out[1] = __hiloint2double(a[3], a[2]);
+        out[2] = __hiloint2double(b[1], b[0]);
+        out[3] = __hiloint2double(b[3], b[2]);
+    }
+}
+constexpr unsigned MON_OOB = 0x80000000u;   // beyond every range: loads return 0
+
 template <typename T, bool VM, bool SP>
 __global__ void __launch_bounds__(256)
 k_monitor(MonArgs a, double *__restrict__ partial) {
@@ -353,8 +375,28 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
         const bool contract = a.y == nullptr && a.ypart == nullptr;
         if (!contract && valid)             // data term from the iteration's y
             for (int rr = r0; rr < a.r; rr += rstep) {
+                const double tv = a.t[(size_t)rr * N + n], sg = a.sig[rr];   // with the y loads
                 double yv;
-                if (a.ypart) {              // the partials in chunk order, as the next iteration sums them
+                if (SP && a.ypart) {        // the same sums, every load unconditional (out of range: 0)
+                    T ys = (T)0;
+                    const __amdgpu_buffer_rsrc_t pr =
+                        mon_rsrc(a.ypart, (unsigned)((size_t)a.npart * a.RP * N * sizeof(T)));
+                    for (int c0 = 0; c0 < a.npart; c0 += 8) {
+                        T pv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const unsigned off = ein && c0 + u < a.npart
+                                ? (unsigned)((((size_t)(c0 + u) * a.RP + rr) * N + n) * sizeof(T)) : MON_OOB;
+                            if constexpr (sizeof(T) == 8)
+                                pv[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(pr, off, 0, 0));
+                            else
+                                pv[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(pr, off, 0, 0));
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) ys += pv[u];
+                    }
+                    yv = (double)ys;
+                } else if (a.ypart) {       // the partials in chunk order, as the next iteration sums them
                     T ys = (T)0;            // (bricks outside a mask are never written; z = y = 0 there)
                     const T *yp = (const T *)a.ypart + (size_t)rr * N + n;
                     for (int c0 = 0; ein && c0 < a.npart; c0 += 8) {
@@ -369,9 +411,46 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
                 } else {
                     yv = (double)((const T *)a.y)[a.yld > 0 ? (size_t)n * a.yld + rr : (size_t)rr * N + n];
                 }
-                const double e = a.t[(size_t)rr * N + n] - a.sig[rr] * yv;
+                const double e = tv - sg * yv;
                 acc[ST_DATA] += e * e;
             }
+        // this lane's sums over its four nodes of chunk c: z norm, non-finite count,
+        // regulariser, dual, primal and DFCS terms
+        auto mon_stats = [&](int c, const T (&zv)[4], const T (&nb)[3][4], const T (&pv)[4],
+                             const T (&fv)[4]) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double v = (double)zv[s];
+                if (!__builtin_isfinite(v)) acc[ST_NONFINITE] += 1.0;
+                acc[ST_ZNORM] += v * v;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const double dd = v - (double)nb[e][s];
+                    acc[ST_REG] += (e == 0 ? ex : e == 1 ? ey : ez) ? dd * dd : 0.0;
+                }
+                if (zp) {
+                    const double dd = v - (double)pv[s];
+                    acc[ST_DZ] += dd * dd;
+                }
+                const int q = 16 * c + 4 * i4 + s;
+                const bool has_ref = a.fstar && valid && q < a.Q;
+                const double fs = has_ref ? a.fstar[n * a.Q + q] : 0.0;
+                if (a.fstar) {
+                    const double dd = has_ref ? v - fs : 0.0;
+                    acc[ST_DFCS] += dd * dd;
+                    acc[ST_FSTAR] += fs * fs;
+                }
+                if (fz) {
+                    const double f = (double)fv[s];
+                    const double dd = v - f;
+                    acc[ST_PRIMAL] += dd * dd;
+                    if (a.fstar) {
+                        const double df = has_ref ? f - fs : 0.0;
+                        acc[ST_DFCS_F] += df * df;
+                    }
+                }
+            }
+        };
         for (int rg = 0; rg < RB || rg == 0; rg += MON_RG) {
             if (!contract && rg > 0) break;
             v4d_m yacc[MON_RG];
@@ -379,6 +458,23 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
             for (int g = 0; g < MON_RG; ++g) yacc[g] = v4d_m{0.0, 0.0, 0.0, 0.0};
             for (int c = c0; c < a.nchunk; c += cstep) {
                 T zv[4];
+                if constexpr (SP) {
+                    // every load of the step issues before any is used (out of range: 0);
+                    // the host keeps these arrays below 2^31 bytes
+                    const unsigned zb = (unsigned)((VM ? N * a.ld : (int64_t)a.nchunk * N * QC) * sizeof(T));
+                    const __amdgpu_buffer_rsrc_t zr = mon_rsrc(z, zb), pr = mon_rsrc(zp ? zp : z, zb),
+                                                 fr = mon_rsrc(fz ? fz : z, zb);
+                    auto bo = [&](int64_t e, bool ok) { return ok ? (unsigned)(e * sizeof(T)) : MON_OOB; };
+                    T nb[3][4], pv[4], fv[4];
+                    bload4<T>(zr, bo(at(c, n), valid), zv);
+                    bload4<T>(zr, bo(at(c, n + 1), ex), nb[0]);
+                    bload4<T>(zr, bo(at(c, n + nx), ey), nb[1]);
+                    bload4<T>(zr, bo(at(c, n + nx * ny), ez), nb[2]);
+                    bload4<T>(pr, bo(at(c, n), valid && zp), pv);
+                    bload4<T>(fr, bo(at(c, n), valid && fz), fv);
+                    mon_stats(c, zv, nb, pv, fv);
+                    continue;                   // no contraction here: y is given
+                }
                 load4<T, VM>(z, at(c, n), valid, zv);
                 if (rg == 0) {
                     T nb[3][4], pv[4], fv[4];
@@ -387,38 +483,7 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
                     load4<T, VM>(z, at(c, n + nx * ny), ez, nb[2]);
                     if (zp) load4<T, VM>(zp, at(c, n), valid, pv);
                     if (fz) load4<T, VM>(fz, at(c, n), valid, fv);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const double v = (double)zv[s];
-                        if (!__builtin_isfinite(v)) acc[ST_NONFINITE] += 1.0;
-                        acc[ST_ZNORM] += v * v;
-#pragma unroll
-                        for (int e = 0; e < 3; ++e) {
-                            const double dd = v - (double)nb[e][s];
-                            acc[ST_REG] += (e == 0 ? ex : e == 1 ? ey : ez) ? dd * dd : 0.0;
-                        }
-                        if (zp) {
-                            const double dd = v - (double)pv[s];
-                            acc[ST_DZ] += dd * dd;
-                        }
-                        const int q = 16 * c + 4 * i4 + s;
-                        const bool has_ref = a.fstar && valid && q < a.Q;
-                        const double fs = has_ref ? a.fstar[n * a.Q + q] : 0.0;
-                        if (a.fstar) {
-                            const double dd = has_ref ? v - fs : 0.0;
-                            acc[ST_DFCS] += dd * dd;
-                            acc[ST_FSTAR] += fs * fs;
-                        }
-                        if (fz) {
-                            const double f = (double)fv[s];
-                            const double dd = v - f;
-                            acc[ST_PRIMAL] += dd * dd;
-                            if (a.fstar) {
-                                const double df = has_ref ? f - fs : 0.0;
-                                acc[ST_DFCS_F] += df * df;
-                            }
-                        }
-                    }
+                    mon_stats(c, zv, nb, pv, fv);
                 }
                 // y of ranks 16 (rg + g) .. + 15 over this chunk's 16 nodes
 #pragma unroll
@@ -456,27 +521,6 @@ k_monitor(MonArgs a, double *__restrict__ partial) {
     if (threadIdx.x < ST_COUNT) {
         const int k = threadIdx.x;
         partial[(size_t)blockIdx.x * ST_COUNT + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-    }
-}
-
-// 16 bytes (four float or two double values) through a raw buffer resource;
-// offsets are 32-bit within one chunk of the state
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t mon_rsrc(const void *p, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, unsigned off, T out[4]) {
-    typedef unsigned v4u_m __attribute__((ext_vector_type(4)));
-    const v4u_m a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-    if constexpr (sizeof(T) == 4) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[i] = __uint_as_float(a[i]);
-    } else {
-        const v4u_m b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
-        out[0] = __hiloint2double(a[1], a[0]);
-        out[1] = __hiloint2double(a[3], a[2]);
-        out[2] = __hiloint2double(b[1], b[0]);
-        out[3] = __hiloint2double(b[3], b[2]);
     }
 }
 
@@ -899,8 +943,12 @@ void launch_monitor(int mode, const MonArgs &a, double *partial, double *out, hi
         return;
     }
     // small grids with y given: one tile per block, the waves splitting chunks and ranks
+    // (its loads go through 32-bit buffer offsets: the arrays must stay below 2^31 bytes)
     const int64_t ntile = (a.g.N + 15) / 16;
-    const bool sp = (a.y || a.ypart) && ntile <= kMonitorSpreadTiles;
+    const int64_t zbytes = (a.ld > 0 ? a.g.N * a.ld : (int64_t)a.nchunk * a.g.N * QC) * esz;
+    const int64_t pbytes = a.ypart ? (int64_t)a.npart * a.RP * a.g.N * esz : 0;
+    const bool sp = (a.y || a.ypart) && ntile <= kMonitorSpreadTiles && zbytes + 64 < ((int64_t)1 << 31) &&
+                    pbytes + 64 < ((int64_t)1 << 31);
     const int nb = sp ? (int)(ntile > 0 ? ntile : 1) : monitor_blocks(a.g.N);
     const bool vm = a.ld > 0;
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, a, partial); };
